@@ -1,0 +1,201 @@
+/*
+ * sph.h -- C-ABI of libsphjet, the MI355X (gfx950) particle update of a 2-D
+ * weakly-compressible SPH solver with surface tension, after Pourabdian, Omidvar
+ * & Morad, "Numerical simulation of liquid jet breakup using smoothed particle
+ * hydrodynamics (SPH)".
+ *
+ * One call of sph_step advances every particle system of a context by one
+ * predictor-corrector step (Section 2-8) made of:
+ *   - a cell-linked-list neighbour search (Section 2-7): particles are binned in
+ *     square cells and counting-sorted by cell, so every neighbourhood is a few
+ *     contiguous ranges of the particle arrays;
+ *   - three neighbour sweeps per evaluation: colour function (eq. 14);
+ *     continuity (eq. 7), Tait pressure (eq. 26), momentum with artificial
+ *     viscosity (eq. 9-10) and interface normal (eq. 18); normal filter,
+ *     curvature and surface-tension acceleration (eq. 20-25);
+ *   - the time-step limit of eq. 30-32, reduced on the device, and the
+ *     predictor and corrector updates.
+ *
+ * Conventions
+ *   - Every function returns an sph_status (0 = success, < 0 = error); no C++
+ *     exception crosses this boundary. On error, sph_last_error(ctx) holds a
+ *     message (for a NULL or not-yet-created context, sph_last_error(NULL)
+ *     returns the thread's last message).
+ *   - Host arrays passed in are read during the call and never retained; the
+ *     caller keeps ownership. Device memory is never allocated by the library:
+ *     the caller supplies one device workspace of sph_workspace_bytes() bytes
+ *     and keeps it alive, unmoved, until sph_free().
+ *   - Particle arrays are FP64 on the host, in the caller's order; that order
+ *     defines the particle id (0 .. n-1). 2-vectors are interleaved (x0, y0,
+ *     x1, y1, ...). Systems are contiguous id ranges given by offsets[n_sys+1].
+ *     Particles of different systems never interact.
+ *   - On the device positions are kept in FP64; velocities, densities and all
+ *     derived quantities in the context's dtype (32 or 64 bits). Density is
+ *     stored as rho - rho0, so a 32-bit context rounds each input once to
+ *     float: vel -> float, mass -> float, (rho - rho0) -> float.
+ *   - Work is enqueued on the HIP stream given to sph_init; sph_step returns
+ *     without waiting. sph_read, sph_neighbors and sph_sync wait for the stream.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_EINVAL = -1,     /* bad argument: NULL pointer, size, parameter out of range */
+    SPH_ENOMEM = -2,     /* workspace smaller than sph_workspace_bytes() */
+    SPH_EDEVICE = -3,    /* a HIP runtime call failed (message in sph_last_error) */
+    SPH_EUNSTABLE = -4,  /* the device flagged a non-finite value, a density outside
+                            [rho0/2, 2 rho0], or a particle that moved farther than the
+                            cell skin within half a step; data was still copied out */
+    SPH_ECAPACITY = -5,  /* output buffer too small (sph_neighbors) */
+    SPH_ESTATE = -6      /* call not valid in the context's current state */
+} sph_status;
+
+/* Smoothing kernels, both with support 2h (Section 2-5). */
+enum { SPH_WENDLAND = 0,   /* eq. 28, normalised: 7/(4 pi h^2) (1 - q/2)^4 (1 + 2q) */
+       SPH_CUBIC = 1 };    /* eq. 27, 10/(7 pi h^2) times the cubic B-spline */
+
+/* Particle types. Walls and the piston are dynamic boundary particles: they
+ * enter every neighbour sum and their density obeys eq. 7 and eq. 26; walls do
+ * not move, the piston follows its prescribed motion. A fluid particle that
+ * leaves its system's box at the end of a step becomes INACTIVE for good and is
+ * excluded from every sum. */
+enum { SPH_FLUID = 0, SPH_WALL = 1, SPH_PISTON = 2, SPH_INACTIVE = 3 };
+
+/* Per-system physical parameters (SI or nondimensional, caller's choice). */
+typedef struct sph_params {
+    int32_t kernel;        /* SPH_WENDLAND or SPH_CUBIC */
+    int32_t closure;       /* 0: curvature from eq. 23; 1: learned closure (sph_set_closure) */
+    double h;              /* smoothing length (the paper uses 1.3 dx) */
+    double rho0;           /* reference density (eq. 26) */
+    double c0;             /* numerical sound speed, B = rho0 c0^2 / gamma (eq. 26) */
+    double gamma;          /* Tait exponent, 7 for a liquid (eq. 26) */
+    double alpha;          /* artificial-viscosity coefficient alpha_vis (eq. 10) */
+    double eta2_h2;        /* eta^2 / h^2, 0.01 in eq. 10 */
+    double sigma;          /* surface-tension coefficient (eq. 12, 24) */
+    double eps_h;          /* eps * h for the normal filter, 0.01 in eq. 20 */
+    double gravity[2];     /* g (eq. 25) */
+    double courant;        /* Cr in eq. 32 (0.2 in the paper), 0 < Cr <= 1 */
+    double dt_fixed;       /* > 0: fixed step; otherwise dt from eq. 30-32 */
+    double box_lo[2];      /* fluid outside [box_lo, box_hi] becomes inactive; */
+    double box_hi[2];      /*   the box also spans the cell grid */
+    double cell_size;      /* cell edge s; must exceed h (reach 2) or 2h (reach 1).
+                              The neighbour search scans (2R+1)^2 cells, R = 1 if
+                              s > 2h else 2, and needs particles to move less than
+                              (R s - 2h)/2 in half a step (checked, SPH_EUNSTABLE) */
+    double piston_dir[2];  /* unit direction of the piston's motion */
+    double piston_u;       /* piston speed U: U (1 + piston_amp sin(piston_omega t)) */
+    double piston_amp;
+    double piston_omega;
+    double closure_tol;    /* closure only: relative deviation from the plain
+                              curvature above which the plain value is used (0.2) */
+} sph_params;
+
+/* Per-context options. Zero-initialised options select the defaults. */
+typedef struct sph_options {
+    int32_t dtype_bits;    /* 32 or 64 (0 = 32) */
+    int32_t block_sweep;   /* threads per block, neighbour sweeps: 64..1024, multiple of 64 (0 = 256) */
+    int32_t block_stream;  /* threads per block, per-particle kernels (0 = 256) */
+    int32_t use_graph;     /* 1: sph_step replays captured hipGraphs; 0: plain launches; -1: default (1) */
+    int32_t xcd_remap;     /* 1: map workgroups so each XCD sweeps one contiguous range; -1: default (1) */
+    int32_t reserved[3];
+} sph_options;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Readable fields (sph_read). Per-particle fields come back in id order as FP64
+ * (or int32/int64 where noted), whatever the storage dtype. Derivative fields
+ * (DRHODT .. NFLAG) are those of the most recent evaluation: after sph_step the
+ * corrector's (half-step) evaluation, after sph_evaluate the current state's. */
+enum {
+    SPH_F_POS = 0,        /* n x 2 */
+    SPH_F_VEL = 1,        /* n x 2 */
+    SPH_F_RHO = 2,        /* n */
+    SPH_F_PRESSURE = 3,   /* n, eq. 26 */
+    SPH_F_MASS = 4,       /* n */
+    SPH_F_TYPE = 5,       /* n, int32 */
+    SPH_F_DRHODT = 6,     /* n, eq. 7 */
+    SPH_F_ACCEL = 7,      /* n x 2, total acceleration of eq. 25 (0 for boundaries) */
+    SPH_F_COLOUR = 8,     /* n, eq. 14 */
+    SPH_F_NORMAL = 9,     /* n x 2, eq. 18 (0 for boundaries) */
+    SPH_F_CURV = 10,      /* n, curvature used in eq. 24 (0 where N_a = 0) */
+    SPH_F_NFLAG = 11,     /* n, int32, N_a of eq. 20 */
+    SPH_F_DT = 12,        /* n_sys, the last step's dt (after sph_evaluate: eq. 32 at the current state) */
+    SPH_F_TIME = 13,      /* n_sys */
+    SPH_F_NACTIVE = 14,   /* n_sys, int64 */
+    SPH_F_SORT_KEYS = 15, /* n, uint64, cell key of each slot of the sorted arrays */
+    SPH_F_SORT_PERM = 16, /* n, int64, particle id held by each slot of the sorted arrays */
+    SPH_F_FLAGS = 17,     /* 1, int32, instability bits (1 non-finite, 2 density, 4 skin) */
+    SPH_F_CURV_PLAIN = 18,/* n, curvature of eq. 23 (equals CURV unless the closure is on) */
+    SPH_F_COUNT = 19
+};
+
+/* Bytes of device workspace a context with these systems needs.
+ *   opt: options (NULL = defaults); n_sys >= 1; p: n_sys parameter records;
+ *   offsets: n_sys + 1 ascending particle offsets, offsets[0] = 0.
+ * Errors: SPH_EINVAL for invalid parameters (see sph_params). */
+sph_status sph_workspace_bytes(const sph_options* opt, int32_t n_sys, const sph_params* p,
+                               const int64_t* offsets, size_t* bytes_out);
+
+/* Create a context: copies the initial state to the device (on `stream`), sorts
+ * it into cells and, with use_graph, captures the step graphs.
+ *   pos, vel: 2n FP64; rho, mass: n FP64; type: n int32 (SPH_FLUID..SPH_INACTIVE)
+ *   d_workspace: device pointer, 256-byte aligned, at least ws_bytes >= sph_workspace_bytes()
+ *   stream: hipStream_t (NULL = the null stream)
+ * Errors: SPH_EINVAL (bad pointer, parameters or type), SPH_ENOMEM (workspace too
+ * small), SPH_EDEVICE. On error *out is NULL. */
+sph_status sph_init(const sph_options* opt, int32_t n_sys, const sph_params* p,
+                    const int64_t* offsets, const double* pos, const double* vel,
+                    const double* rho, const double* mass, const int32_t* type,
+                    void* d_workspace, size_t ws_bytes, void* stream, sph_ctx** out);
+
+/* Enqueue n_steps >= 0 predictor-corrector steps; returns after enqueueing. */
+sph_status sph_step(sph_ctx* ctx, int32_t n_steps);
+
+/* Re-sort the current state and evaluate every right-hand side (eq. 7-25) and
+ * the eq. 30-32 time step without advancing time (for inspection and tests). */
+sph_status sph_evaluate(sph_ctx* ctx);
+
+/* Copy one field to host memory (waits for the stream). bytes must equal the
+ * field's size (n, 2n or n_sys elements of 4 or 8 bytes, see SPH_F_*).
+ * Returns SPH_EUNSTABLE, after copying, if the device raised an instability flag. */
+sph_status sph_read(sph_ctx* ctx, int32_t field, void* host_dst, size_t bytes);
+
+/* Neighbour lists at the current state (waits for the stream): for every
+ * particle id a, the ids b != a of its system with |r_a - r_b|^2 < (2h)^2,
+ * ascending. start: n + 1 int64; nbr: cap int32. *total receives the number of
+ * pairs; SPH_ECAPACITY (start still filled) if cap < *total. Debug path: uses
+ * its own kernels and the sorted arrays of the last sort. */
+sph_status sph_neighbors(sph_ctx* ctx, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total);
+
+/* Wait for all enqueued work. */
+sph_status sph_sync(sph_ctx* ctx);
+
+/* Per-kernel timing over n_steps steps launched eagerly with a HIP event pair
+ * around every kernel, on the context's stream (advances the simulation).
+ * names/avg_ms/calls: arrays of max_stats entries; *n_stats receives the count. */
+sph_status sph_profile(sph_ctx* ctx, int32_t n_steps, int32_t max_stats, const char** names,
+                       double* avg_ms, int64_t* calls, int32_t* n_stats);
+
+/* Release the context (waits for the stream; the workspace is the caller's). */
+void sph_free(sph_ctx* ctx);
+
+/* Message of the last error on ctx (or of the calling thread if ctx is NULL). */
+const char* sph_last_error(const sph_ctx* ctx);
+
+int32_t sph_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

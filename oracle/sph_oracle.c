@@ -427,7 +427,11 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
         }
         if (out->dt_f) out->dt_f[s] = dtf;
         if (out->dt_cv) out->dt_cv[s] = dtcv;
-        if (out->dt) out->dt[s] = p->dt_fixed > 0.0 ? p->dt_fixed : p->courant * fmin(dtf, dtcv);
+        if (out->dt) {
+            /* a system without active particles has no limit: it does not advance */
+            double d = p->dt_fixed > 0.0 ? p->dt_fixed : p->courant * fmin(dtf, dtcv);
+            out->dt[s] = isfinite(d) ? d : 0.0;
+        }
     }
 
     if (out->colour) memcpy(out->colour, C, sizeof(double) * (size_t)n);

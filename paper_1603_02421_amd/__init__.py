@@ -1,0 +1,11 @@
+"""MI355X (gfx950) SPH particle update: cell-linked-list neighbour search,
+WCSPH sweeps with surface tension and a predictor-corrector step, in HIP,
+behind the C-ABI of include/sph.h.
+
+``Simulation`` is a thin ctypes handle on that library; PyTorch only provides
+device memory and the stream.
+"""
+from . import native  # noqa: F401
+from .sim import Simulation  # noqa: F401
+
+__all__ = ["Simulation", "native"]

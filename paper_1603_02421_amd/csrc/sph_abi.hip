@@ -1,0 +1,847 @@
+// Host side of libsphjet: parameter validation, workspace layout, the step
+// schedule (sort, two evaluations, predictor, corrector), hipGraph capture and
+// the C-ABI of include/sph.h.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sph.h"
+#include "sph_internal.hpp"
+
+using namespace sphjet;
+
+static thread_local std::string g_thread_err;
+
+namespace sphjet {
+
+// ------------------------------------------------------------ kernel timer
+
+hipEvent_t KernelTimer::get_() {
+    if (!pool_.empty()) {
+        hipEvent_t e = pool_.back();
+        pool_.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void KernelTimer::begin(const char* name, hipStream_t st) {
+    if (!enabled) return;
+    cur_ = name;
+    cur_a_ = get_();
+    (void)hipEventRecord(cur_a_, st);
+}
+
+void KernelTimer::end(hipStream_t st) {
+    if (!enabled || !cur_) return;
+    hipEvent_t b = get_();
+    (void)hipEventRecord(b, st);
+    pending_.push_back({cur_, cur_a_, b});
+    cur_ = nullptr;
+}
+
+void KernelTimer::collect() {
+    for (auto& p : pending_) {
+        (void)hipEventSynchronize(p.b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        if (!total_ms.count(p.name)) names.push_back(p.name);
+        total_ms[p.name] += ms;
+        calls[p.name] += 1;
+        pool_.push_back(p.a);
+        pool_.push_back(p.b);
+    }
+    pending_.clear();
+}
+
+void KernelTimer::reset() {
+    collect();
+    names.clear();
+    total_ms.clear();
+    calls.clear();
+}
+
+KernelTimer::~KernelTimer() {
+    for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool_) (void)hipEventDestroy(e);
+}
+
+}  // namespace sphjet
+
+// ------------------------------------------------------------ workspace layout
+
+namespace {
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename P>
+    P* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+        off += count * sizeof(P);
+        return p;
+    }
+};
+
+struct Grid {
+    int64_t nx, ny;
+    int reach;
+};
+
+const char* check_params(const sph_params& p) {
+    if (!(p.h > 0) || !isfinite(p.h)) return "h must be positive";
+    if (!(p.rho0 > 0)) return "rho0 must be positive";
+    if (!(p.c0 > 0)) return "c0 must be positive";
+    if (!(p.gamma > 0)) return "gamma must be positive";
+    if (!(p.alpha >= 0)) return "alpha must be >= 0";
+    if (!(p.eta2_h2 > 0)) return "eta2_h2 must be positive";
+    if (!(p.sigma >= 0)) return "sigma must be >= 0";
+    if (!(p.eps_h >= 0)) return "eps_h must be >= 0";
+    if (!(p.courant > 0 && p.courant <= 1)) return "courant must be in (0, 1]";
+    if (!(p.dt_fixed >= 0)) return "dt_fixed must be >= 0";
+    if (p.kernel != SPH_WENDLAND && p.kernel != SPH_CUBIC) return "kernel must be SPH_WENDLAND or SPH_CUBIC";
+    if (p.closure != 0 && p.closure != 1) return "closure must be 0 or 1";
+    if (!(p.box_hi[0] > p.box_lo[0] && p.box_hi[1] > p.box_lo[1])) return "box_hi must exceed box_lo";
+    if (!(p.cell_size > p.h)) return "cell_size must exceed h";
+    if (!isfinite(p.gravity[0]) || !isfinite(p.gravity[1])) return "gravity must be finite";
+    return nullptr;
+}
+
+Grid grid_of(const sph_params& p) {
+    double inv = 1.0 / p.cell_size;
+    Grid g;
+    g.nx = (int64_t)floor((p.box_hi[0] - p.box_lo[0]) * inv) + 1;
+    g.ny = (int64_t)floor((p.box_hi[1] - p.box_lo[1]) * inv) + 1;
+    g.reach = p.cell_size > 2.0 * p.h ? 1 : 2;
+    return g;
+}
+
+sph_options resolve(const sph_options* o) {
+    sph_options r;
+    memset(&r, 0, sizeof r);
+    if (o) r = *o;
+    if (r.dtype_bits == 0) r.dtype_bits = 32;
+    if (r.block_sweep == 0) r.block_sweep = 256;
+    if (r.block_stream == 0) r.block_stream = 256;
+    if (r.use_graph < 0) r.use_graph = 1;
+    if (r.xcd_remap < 0) r.xcd_remap = 1;
+    return r;
+}
+
+const char* check_options(const sph_options& o) {
+    if (o.dtype_bits != 32 && o.dtype_bits != 64) return "dtype_bits must be 32 or 64";
+    if (o.block_sweep < 64 || o.block_sweep > 1024 || o.block_sweep % 64) return "block_sweep must be a multiple of 64 in [64, 1024]";
+    if (o.block_stream < 64 || o.block_stream > 1024 || o.block_stream % 64) return "block_stream must be a multiple of 64 in [64, 1024]";
+    return nullptr;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ context
+
+struct sph_ctx_base {
+    virtual ~sph_ctx_base() {}
+};
+
+struct sph_ctx {
+    sph_options opt;
+    int n_sys = 0;
+    int64_t n = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+    std::vector<sph_params> params;
+    std::vector<int64_t> offsets;
+    std::vector<uint32_t> cell_base;  // n_sys + 1 (last = trash)
+    KernelTimer timer;
+    std::vector<std::string> prof_names;
+    std::vector<const char*> prof_ptrs;
+    std::unique_ptr<sph_ctx_base> impl;
+    int (*step_fn)(sph_ctx*, int) = nullptr;
+    int (*evaluate_fn)(sph_ctx*) = nullptr;
+    int (*read_fn)(sph_ctx*, int, void*, size_t) = nullptr;
+    int (*nbr_fn)(sph_ctx*, int64_t*, int32_t*, int64_t, int64_t*) = nullptr;
+};
+
+static sph_status fail(sph_ctx* c, sph_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    g_thread_err = msg;
+    return s;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(c, SPH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+namespace {
+
+template <typename T>
+struct Impl : sph_ctx_base {
+    int n = 0, n_sys = 0;
+    LaunchCfg L{};
+    SysDev<T>* sys = nullptr;
+    StateBuf<T> buf[2]{};
+    double2* pos_h = nullptr;
+    V2<T>* vel_h = nullptr;
+    T* dens_h = nullptr;
+    T *colour = nullptr, *drho = nullptr, *kappa = nullptr, *kappa_plain = nullptr, *aux = nullptr;
+    V2<T>* acc = nullptr;
+    V2<T>* nrm = nullptr;
+    SortBufs sb{};
+    unsigned long long* dtmin = nullptr;
+    double* dt = nullptr;
+    double* time = nullptr;
+    uint32_t* flags = nullptr;
+    int64_t* dbg_start = nullptr;
+    int cur = 0;
+    bool graphs = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+
+    ~Impl() override {
+        for (int k = 0; k < 2; ++k) {
+            if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+        }
+    }
+
+    // Lays out every buffer in the workspace (base == nullptr: size only).
+    size_t carve(char* base, int64_t n_, int n_sys_, uint32_t trash, int block_stream) {
+        Carver cv{base};
+        sys = cv.take<SysDev<T>>(n_sys_);
+        for (int k = 0; k < 2; ++k) {
+            buf[k].pos = cv.take<double2>(n_);
+            buf[k].vel = cv.take<V2<T>>(n_);
+            buf[k].dens = cv.take<T>(n_);
+            buf[k].mass = cv.take<T>(n_);
+            buf[k].tag = cv.take<uint32_t>(n_);
+            buf[k].id = cv.take<uint32_t>(n_);
+        }
+        pos_h = cv.take<double2>(n_);
+        vel_h = cv.take<V2<T>>(n_);
+        dens_h = cv.take<T>(n_);
+        colour = cv.take<T>(n_);
+        drho = cv.take<T>(n_);
+        acc = cv.take<V2<T>>(n_);
+        nrm = cv.take<V2<T>>(n_);
+        kappa = cv.take<T>(n_);
+        kappa_plain = cv.take<T>(n_);
+        aux = cv.take<T>(n_ < 2 ? 2 : n_);
+        int64_t nb = (n_ + block_stream - 1) / block_stream;
+        sb.trash = trash;
+        sb.cstart = cv.take<uint32_t>((size_t)trash + 2);
+        sb.key = cv.take<uint32_t>(n_);
+        sb.slot = cv.take<uint32_t>(n_);
+        sb.blk = cv.take<uint32_t>(nb + 1);
+        sb.part = cv.take<uint32_t>(((int64_t)trash + 1 + SCAN_TILE - 1) / SCAN_TILE + 1);
+        sb.part2 = cv.take<uint32_t>((nb + SCAN_TILE - 1) / SCAN_TILE + 1);
+        sb.tmp_src = cv.take<uint32_t>(n_);
+        sb.tmp_id = cv.take<uint32_t>(n_);
+        sb.cell = cv.take<uint32_t>(n_);
+        dtmin = cv.take<unsigned long long>(2 * n_sys_);
+        dt = cv.take<double>(n_sys_);
+        time = cv.take<double>(n_sys_);
+        flags = cv.take<uint32_t>(4);
+        dbg_start = cv.take<int64_t>(n_ + 1);
+        return cv.off + 256;
+    }
+
+    EvalView<T> eval_view(bool half, bool do_dt) const {
+        const StateBuf<T>& S = buf[cur];
+        EvalView<T> v{};
+        v.n = n;
+        v.xcd = L.xcd;
+        v.do_dt = do_dt ? 1 : 0;
+        v.sys = sys;
+        v.pos = half ? pos_h : S.pos;
+        v.vel = half ? vel_h : S.vel;
+        v.dens = half ? dens_h : S.dens;
+        v.mass = S.mass;
+        v.tag = S.tag;
+        v.id = S.id;
+        v.cell = sb.cell;
+        v.cstart = sb.cstart;
+        v.colour = colour;
+        v.drho = drho;
+        v.acc = acc;
+        v.nrm = nrm;
+        v.kappa = kappa;
+        v.kappa_plain = kappa_plain;
+        v.dtmin = dtmin;
+        return v;
+    }
+
+    IntegView<T> integ_view() const {
+        const StateBuf<T>& S = buf[cur];
+        IntegView<T> v{};
+        v.n = n;
+        v.sys = sys;
+        v.pos = S.pos;
+        v.vel = S.vel;
+        v.dens = S.dens;
+        v.tag = S.tag;
+        v.drho = drho;
+        v.acc = acc;
+        v.pos_h = pos_h;
+        v.vel_h = vel_h;
+        v.dens_h = dens_h;
+        v.dt = dt;
+        v.time = time;
+        v.flags = flags;
+        return v;
+    }
+
+    // Sort the current buffer into the other one; the other becomes current.
+    void sort(hipStream_t st, KernelTimer* kt) {
+        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], st, kt);
+        cur ^= 1;
+    }
+
+    // One predictor-corrector step, enqueued on st.
+    void step(hipStream_t st, KernelTimer* kt) {
+        sort(st, kt);
+        launch_eval<T>(L, eval_view(false, true), st, kt);
+        launch_dt<T>(n_sys, sys, dtmin, dt, st, kt);
+        launch_predict<T>(L, integ_view(), st, kt);
+        launch_eval<T>(L, eval_view(true, false), st, kt);
+        launch_correct<T>(L, integ_view(), n_sys, dt, time, st, kt);
+    }
+};
+
+template <typename T>
+Impl<T>* impl_of(sph_ctx* c) { return static_cast<Impl<T>*>(c->impl.get()); }
+
+template <typename T>
+int step_impl(sph_ctx* c, int n_steps) {
+    Impl<T>* m = impl_of<T>(c);
+    for (int s = 0; s < n_steps; ++s) {
+        if (m->graphs) {
+            HIP_OK(hipGraphLaunch(m->gexec[m->cur], c->stream));
+            m->cur ^= 1;
+        } else {
+            m->step(c->stream, &c->timer);
+        }
+    }
+    HIP_OK(hipGetLastError());
+    return SPH_OK;
+}
+
+template <typename T>
+int evaluate_impl(sph_ctx* c) {
+    Impl<T>* m = impl_of<T>(c);
+    m->sort(c->stream, &c->timer);
+    launch_eval<T>(m->L, m->eval_view(false, true), c->stream, &c->timer);
+    launch_dt<T>(m->n_sys, m->sys, m->dtmin, m->dt, c->stream, &c->timer);
+    HIP_OK(hipGetLastError());
+    return SPH_OK;
+}
+
+template <typename T>
+__global__ void k_nflag(int n, const SysDev<T>* sys, const uint32_t* tag, const V2<T>* nrm, int32_t* out) {
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    uint32_t t = tag[a];
+    int f = 0;
+    if (tag_type(t) == T_FLUID) {
+        V2<T> v = nrm[a];
+        f = sqrt_(v.x * v.x + v.y * v.y) > sys[tag_sys(t)].eps ? 1 : 0;
+    }
+    out[a] = f;
+}
+
+template <typename SRC>
+void unpermute(const std::vector<uint32_t>& ids, const SRC* src, int comps, double* dst) {
+    for (size_t j = 0; j < ids.size(); ++j)
+        for (int k = 0; k < comps; ++k) dst[(size_t)ids[j] * comps + k] = (double)src[j * comps + k];
+}
+
+template <typename T>
+int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
+    Impl<T>* m = impl_of<T>(c);
+    const int64_t n = m->n;
+    const int ns = m->n_sys;
+    const StateBuf<T>& S = m->buf[m->cur];
+    hipStream_t st = c->stream;
+    size_t want = 0;
+    switch (field) {
+        case SPH_F_POS: case SPH_F_VEL: case SPH_F_ACCEL: case SPH_F_NORMAL: want = (size_t)n * 16; break;
+        case SPH_F_RHO: case SPH_F_PRESSURE: case SPH_F_MASS: case SPH_F_DRHODT: case SPH_F_COLOUR:
+        case SPH_F_CURV: case SPH_F_CURV_PLAIN: case SPH_F_SORT_KEYS: case SPH_F_SORT_PERM:
+            want = (size_t)n * 8; break;
+        case SPH_F_TYPE: case SPH_F_NFLAG: want = (size_t)n * 4; break;
+        case SPH_F_DT: case SPH_F_TIME: case SPH_F_NACTIVE: want = (size_t)ns * 8; break;
+        case SPH_F_FLAGS: want = 4; break;
+        default: return fail(c, SPH_EINVAL, "unknown field");
+    }
+    if (!host || bytes != want)
+        return fail(c, SPH_EINVAL, "field " + std::to_string(field) + " needs " + std::to_string(want) + " bytes");
+    std::vector<uint32_t> ids(n);
+    HIP_OK(hipMemcpyAsync(ids.data(), S.id, n * 4, hipMemcpyDeviceToHost, st));
+    double* out = static_cast<double*>(host);
+    auto fetch = [&](const void* dev, size_t sz, std::vector<char>& tmp) -> hipError_t {
+        tmp.resize(sz);
+        hipError_t e = hipMemcpyAsync(tmp.data(), dev, sz, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    };
+    std::vector<char> tmp;
+    switch (field) {
+        case SPH_F_POS:
+            HIP_OK(fetch(S.pos, n * 16, tmp));
+            unpermute(ids, reinterpret_cast<const double*>(tmp.data()), 2, out);
+            break;
+        case SPH_F_VEL:
+            HIP_OK(fetch(S.vel, n * sizeof(V2<T>), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 2, out);
+            break;
+        case SPH_F_ACCEL:
+            HIP_OK(fetch(m->acc, n * sizeof(V2<T>), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 2, out);
+            break;
+        case SPH_F_NORMAL:
+            HIP_OK(fetch(m->nrm, n * sizeof(V2<T>), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 2, out);
+            break;
+        case SPH_F_RHO: {
+            HIP_OK(fetch(S.dens, n * sizeof(T), tmp));
+            std::vector<char> tg;
+            HIP_OK(fetch(S.tag, n * 4, tg));
+            const T* d = reinterpret_cast<const T*>(tmp.data());
+            const uint32_t* tgs = reinterpret_cast<const uint32_t*>(tg.data());
+            for (int64_t j = 0; j < n; ++j) out[ids[j]] = c->params[tgs[j] >> 4].rho0 + (double)d[j];
+            break;
+        }
+        case SPH_F_PRESSURE:
+            launch_pressure<T>((int)n, m->sys, S.tag, S.dens, m->aux, st);
+            HIP_OK(fetch(m->aux, n * sizeof(T), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+            break;
+        case SPH_F_MASS:
+            HIP_OK(fetch(S.mass, n * sizeof(T), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+            break;
+        case SPH_F_DRHODT:
+            HIP_OK(fetch(m->drho, n * sizeof(T), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+            break;
+        case SPH_F_COLOUR:
+            HIP_OK(fetch(m->colour, n * sizeof(T), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+            break;
+        case SPH_F_CURV:
+            HIP_OK(fetch(m->kappa, n * sizeof(T), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+            break;
+        case SPH_F_CURV_PLAIN:
+            HIP_OK(fetch(m->kappa_plain, n * sizeof(T), tmp));
+            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+            break;
+        case SPH_F_TYPE: {
+            HIP_OK(fetch(S.tag, n * 4, tmp));
+            const uint32_t* tg = reinterpret_cast<const uint32_t*>(tmp.data());
+            int32_t* o = static_cast<int32_t*>(host);
+            for (int64_t j = 0; j < n; ++j) o[ids[j]] = (int32_t)(tg[j] & 15u);
+            break;
+        }
+        case SPH_F_NFLAG: {
+            int32_t* dev = reinterpret_cast<int32_t*>(m->aux);
+            k_nflag<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, m->sys, S.tag, m->nrm, dev);
+            HIP_OK(fetch(dev, n * 4, tmp));
+            const int32_t* f = reinterpret_cast<const int32_t*>(tmp.data());
+            int32_t* o = static_cast<int32_t*>(host);
+            for (int64_t j = 0; j < n; ++j) o[ids[j]] = f[j];
+            break;
+        }
+        case SPH_F_SORT_KEYS: {
+            HIP_OK(fetch(m->sb.cell, n * 4, tmp));
+            const uint32_t* k = reinterpret_cast<const uint32_t*>(tmp.data());
+            uint64_t* o = static_cast<uint64_t*>(host);
+            for (int64_t j = 0; j < n; ++j) o[j] = k[j];
+            break;
+        }
+        case SPH_F_SORT_PERM: {
+            HIP_OK(hipStreamSynchronize(st));
+            int64_t* o = static_cast<int64_t*>(host);
+            for (int64_t j = 0; j < n; ++j) o[j] = ids[j];
+            break;
+        }
+        case SPH_F_DT:
+            HIP_OK(fetch(m->dt, ns * 8, tmp));
+            memcpy(host, tmp.data(), ns * 8);
+            break;
+        case SPH_F_TIME:
+            HIP_OK(fetch(m->time, ns * 8, tmp));
+            memcpy(host, tmp.data(), ns * 8);
+            break;
+        case SPH_F_NACTIVE: {
+            std::vector<uint32_t> starts(ns + 1);
+            for (int s = 0; s <= ns; ++s)
+                HIP_OK(hipMemcpyAsync(&starts[s], m->sb.cstart + c->cell_base[s], 4, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            int64_t* o = static_cast<int64_t*>(host);
+            for (int s = 0; s < ns; ++s) o[s] = (int64_t)starts[s + 1] - (int64_t)starts[s];
+            break;
+        }
+        case SPH_F_FLAGS:
+            HIP_OK(fetch(m->flags, 4, tmp));
+            memcpy(host, tmp.data(), 4);
+            break;
+    }
+    uint32_t fl = 0;
+    HIP_OK(hipMemcpyAsync(&fl, m->flags, 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (fl) return fail(c, SPH_EUNSTABLE, "instability flags " + std::to_string(fl));
+    return SPH_OK;
+}
+
+template <typename T>
+int nbr_impl(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total) {
+    Impl<T>* m = impl_of<T>(c);
+    const int n = m->n;
+    hipStream_t st = c->stream;
+    EvalView<T> v = m->eval_view(false, false);
+    uint32_t* cnt = m->sb.tmp_src;  // free between steps
+    launch_nbr_count<T>(m->L, v, cnt, st);
+    std::vector<uint32_t> counts(n), ids(n);
+    HIP_OK(hipMemcpyAsync(counts.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(ids.data(), m->buf[m->cur].id, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    std::vector<int64_t> sstart(n + 1, 0);
+    for (int j = 0; j < n; ++j) sstart[j + 1] = sstart[j] + counts[j];
+    int64_t tot = sstart[n];
+    // id-order start
+    std::vector<int64_t> idcount(n, 0);
+    for (int j = 0; j < n; ++j) idcount[ids[j]] = counts[j];
+    start[0] = 0;
+    for (int a = 0; a < n; ++a) start[a + 1] = start[a] + idcount[a];
+    *total = tot;
+    if (cap < tot || !nbr) return fail(c, SPH_ECAPACITY, "neighbour buffer too small");
+    HIP_OK(hipMemcpyAsync(m->dbg_start, sstart.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st));
+    // fill in chunks through the half-step buffers (idle between steps)
+    uint32_t* chunk = reinterpret_cast<uint32_t*>(m->pos_h);
+    const int64_t chunk_cap = (int64_t)n * 4;   // 16 bytes per particle of pos_h
+    std::vector<uint32_t> host_chunk;
+    int a0 = 0;
+    while (a0 < n) {
+        int a1 = a0;
+        while (a1 < n && sstart[a1 + 1] - sstart[a0] <= chunk_cap) ++a1;
+        if (a1 == a0) return fail(c, SPH_ECAPACITY, "a particle has too many neighbours");
+        launch_nbr_fill<T>(v, a0, a1, m->dbg_start, sstart[a0], chunk, st);
+        int64_t len = sstart[a1] - sstart[a0];
+        host_chunk.resize((size_t)len);
+        if (len) HIP_OK(hipMemcpyAsync(host_chunk.data(), chunk, (size_t)len * 4, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        for (int j = a0; j < a1; ++j) {
+            int64_t o = start[ids[j]];
+            int64_t cnt_j = sstart[j + 1] - sstart[j];
+            for (int64_t k = 0; k < cnt_j; ++k) nbr[o + k] = (int32_t)host_chunk[(size_t)(sstart[j] - sstart[a0] + k)];
+            std::sort(nbr + o, nbr + o + cnt_j);
+        }
+        a0 = a1;
+    }
+    return SPH_OK;
+}
+
+template <typename T>
+SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
+    SysDev<T> s;
+    memset(&s, 0, sizeof s);
+    Grid g = grid_of(p);
+    const double PI = 3.14159265358979323846;
+    s.x0 = p.box_lo[0];
+    s.y0 = p.box_lo[1];
+    s.inv_s = 1.0 / p.cell_size;
+    s.R2 = (2.0 * p.h) * (2.0 * p.h);
+    double skin = g.reach * p.cell_size - 2.0 * p.h;
+    s.skin2 = 0.25 * skin * skin;
+    s.nx = (int32_t)g.nx;
+    s.ny = (int32_t)g.ny;
+    s.reach = g.reach;
+    s.kernel = p.kernel;
+    s.cell_base = base;
+    double h = p.h;
+    double wn = p.kernel == SPH_WENDLAND ? 7.0 / (4.0 * PI * h * h) : 10.0 / (7.0 * PI * h * h);
+    double gn = p.kernel == SPH_WENDLAND ? -5.0 * wn / (h * h) : wn / (h * h);
+    s.h = (T)h;
+    s.inv_h = (T)(1.0 / h);
+    s.wnorm = (T)wn;
+    s.gnorm = (T)gn;
+    s.W0 = (T)wn;
+    s.rho0 = (T)p.rho0;
+    s.inv_rho0 = (T)(1.0 / p.rho0);
+    s.B = (T)(p.rho0 * p.c0 * p.c0 / p.gamma);
+    s.c0 = (T)p.c0;
+    s.gamma = (T)p.gamma;
+    s.half_gm1 = (T)(0.5 * (p.gamma - 1.0));
+    s.alpha_h = (T)(p.alpha * h);
+    s.eta2 = (T)(p.eta2_h2 * h * h);
+    s.sigma = (T)p.sigma;
+    s.eps = (T)(p.eps_h / h);
+    s.gx = (T)p.gravity[0];
+    s.gy = (T)p.gravity[1];
+    s.gamma7 = p.gamma == 7.0 ? 1 : 0;
+    s.closure = p.closure;
+    s.closure_tol = (T)(p.closure_tol > 0 ? p.closure_tol : 0.2);
+    s.courant = p.courant;
+    s.dt_fixed = p.dt_fixed;
+    s.box_lo_x = p.box_lo[0];
+    s.box_lo_y = p.box_lo[1];
+    s.box_hi_x = p.box_hi[0];
+    s.box_hi_y = p.box_hi[1];
+    double pn = hypot(p.piston_dir[0], p.piston_dir[1]);
+    s.pdx = pn > 0 ? p.piston_dir[0] / pn : 0.0;
+    s.pdy = pn > 0 ? p.piston_dir[1] / pn : 0.0;
+    s.pu = p.piston_u;
+    s.pamp = p.piston_amp;
+    s.pomega = p.piston_omega;
+    return s;
+}
+
+// Validates systems and computes cell bases; returns an error message or null.
+const char* plan(const sph_options& o, int n_sys, const sph_params* p, const int64_t* off,
+                 std::vector<uint32_t>& base) {
+    if (const char* e = check_options(o)) return e;
+    if (n_sys < 1 || n_sys >= (1 << 27)) return "n_sys must be in [1, 2^27)";
+    if (!p || !off) return "params and offsets must not be NULL";
+    if (off[0] != 0) return "offsets[0] must be 0";
+    for (int s = 0; s < n_sys; ++s)
+        if (off[s + 1] < off[s]) return "offsets must be non-decreasing";
+    if (off[n_sys] < 1 || off[n_sys] > ((int64_t)1 << 30)) return "particle count must be in [1, 2^30]";
+    base.assign(n_sys + 1, 0);
+    uint64_t acc = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        if (const char* e = check_params(p[s])) return e;
+        Grid g = grid_of(p[s]);
+        if (g.nx < 1 || g.ny < 1 || g.nx > (1 << 30) || g.ny > (1 << 30)) return "cell grid out of range";
+        base[s] = (uint32_t)acc;
+        acc += (uint64_t)g.nx * (uint64_t)g.ny;
+        if (acc > ((uint64_t)1 << 31)) return "too many cells (box / cell_size too large)";
+    }
+    base[n_sys] = (uint32_t)acc;
+    return nullptr;
+}
+
+template <typename T>
+int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rho, const double* mass,
+              const int32_t* type, void* ws, size_t ws_bytes) {
+    auto* m = new Impl<T>();
+    c->impl.reset(m);
+    m->n = (int)c->n;
+    m->n_sys = c->n_sys;
+    m->L.n = m->n;
+    m->L.block_sweep = c->opt.block_sweep;
+    m->L.block_stream = c->opt.block_stream;
+    m->L.xcd = c->opt.xcd_remap;
+    const uint32_t trash = c->cell_base[c->n_sys];
+    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream);
+    if (ws_bytes < need)
+        return fail(c, SPH_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ws) & 255) return fail(c, SPH_EINVAL, "workspace must be 256-byte aligned");
+    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream);
+    const int64_t n = c->n;
+    hipStream_t st = c->stream;
+    // host staging in device format
+    std::vector<SysDev<T>> sd(c->n_sys);
+    for (int s = 0; s < c->n_sys; ++s) sd[s] = make_sysdev<T>(c->params[s], c->cell_base[s]);
+    std::vector<double2> hp(n);
+    std::vector<V2<T>> hv(n);
+    std::vector<T> hd(n), hm(n);
+    std::vector<uint32_t> ht(n), hi(n);
+    for (int s = 0; s < c->n_sys; ++s) {
+        for (int64_t a = c->offsets[s]; a < c->offsets[s + 1]; ++a) {
+            if (type[a] < SPH_FLUID || type[a] > SPH_INACTIVE)
+                return fail(c, SPH_EINVAL, "particle type out of range at id " + std::to_string(a));
+            if (!isfinite(pos[2 * a]) || !isfinite(pos[2 * a + 1]) || !isfinite(rho[a]) || !(mass[a] > 0))
+                return fail(c, SPH_EINVAL, "non-finite position/density or non-positive mass at id " + std::to_string(a));
+            hp[a].x = pos[2 * a];
+            hp[a].y = pos[2 * a + 1];
+            hv[a].x = (T)vel[2 * a];
+            hv[a].y = (T)vel[2 * a + 1];
+            hd[a] = (T)(rho[a] - c->params[s].rho0);
+            hm[a] = (T)mass[a];
+            ht[a] = ((uint32_t)s << 4) | (uint32_t)type[a];
+            hi[a] = (uint32_t)a;
+        }
+    }
+    StateBuf<T>& X = m->buf[0];
+    HIP_OK(hipMemcpyAsync(m->sys, sd.data(), sizeof(SysDev<T>) * c->n_sys, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.pos, hp.data(), n * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.vel, hv.data(), n * sizeof(V2<T>), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.dens, hd.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.mass, hm.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.tag, ht.data(), n * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.id, hi.data(), n * 4, hipMemcpyHostToDevice, st));
+    // derived arrays start at zero; dt minima at +inf; time 0; flags 0
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->colour), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->drho), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->acc), n * sizeof(V2<T>) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->nrm), n * sizeof(V2<T>) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->kappa), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->kappa_plain), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u64(m->dtmin, 2 * c->n_sys, (unsigned long long)0x7ff0000000000000ull, st);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(m->dt), c->n_sys, 0ull, st);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(m->time), c->n_sys, 0ull, st);
+    launch_fill_u32(m->flags, 4, 0u, st);
+    launch_fill_u32(m->sb.cell, n, 0u, st);
+    // a first sort so the state is cell-ordered from the start
+    m->sort(st, &c->timer);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    if (c->opt.use_graph) {
+        HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        int saved = m->cur;
+        KernelTimer off;
+        for (int k = 0; k < 2; ++k) {
+            m->cur = k;
+            HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            m->step(c->cap_stream, &off);
+            HIP_OK(hipStreamEndCapture(c->cap_stream, &m->graph[k]));
+            HIP_OK(hipGraphInstantiate(&m->gexec[k], m->graph[k], nullptr, nullptr, 0));
+        }
+        m->cur = saved;
+        m->graphs = true;
+    }
+    c->step_fn = step_impl<T>;
+    c->evaluate_fn = evaluate_impl<T>;
+    c->read_fn = read_impl<T>;
+    c->nbr_fn = nbr_impl<T>;
+    return SPH_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ C-ABI
+
+extern "C" {
+
+int32_t sph_abi_version(void) { return SPH_ABI_VERSION; }
+
+const char* sph_last_error(const sph_ctx* c) { return c ? c->err.c_str() : g_thread_err.c_str(); }
+
+sph_status sph_workspace_bytes(const sph_options* opt, int32_t n_sys, const sph_params* p,
+                               const int64_t* offsets, size_t* bytes_out) {
+    sph_ctx* c = nullptr;
+    if (!bytes_out) return fail(c, SPH_EINVAL, "bytes_out is NULL");
+    sph_options o = resolve(opt);
+    std::vector<uint32_t> base;
+    if (const char* e = plan(o, n_sys, p, offsets, base)) return fail(c, SPH_EINVAL, e);
+    int64_t n = offsets[n_sys];
+    if (o.dtype_bits == 32) {
+        Impl<float> m;
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream);
+    } else {
+        Impl<double> m;
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream);
+    }
+    return SPH_OK;
+}
+
+sph_status sph_init(const sph_options* opt, int32_t n_sys, const sph_params* p, const int64_t* offsets,
+                    const double* pos, const double* vel, const double* rho, const double* mass,
+                    const int32_t* type, void* d_workspace, size_t ws_bytes, void* stream, sph_ctx** out) {
+    sph_ctx* c = nullptr;
+    if (!out) return fail(c, SPH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!pos || !vel || !rho || !mass || !type || !d_workspace)
+        return fail(c, SPH_EINVAL, "NULL array or workspace");
+    sph_options o = resolve(opt);
+    std::vector<uint32_t> base;
+    if (const char* e = plan(o, n_sys, p, offsets, base)) return fail(c, SPH_EINVAL, e);
+    std::unique_ptr<sph_ctx> ctx(new sph_ctx());
+    c = ctx.get();
+    c->opt = o;
+    c->n_sys = n_sys;
+    c->n = offsets[n_sys];
+    c->stream = static_cast<hipStream_t>(stream);
+    c->params.assign(p, p + n_sys);
+    c->offsets.assign(offsets, offsets + n_sys + 1);
+    c->cell_base = base;
+    int rc = o.dtype_bits == 32 ? init_impl<float>(c, pos, vel, rho, mass, type, d_workspace, ws_bytes)
+                                : init_impl<double>(c, pos, vel, rho, mass, type, d_workspace, ws_bytes);
+    if (rc != SPH_OK) {
+        g_thread_err = c->err;
+        return (sph_status)rc;
+    }
+    *out = ctx.release();
+    return SPH_OK;
+}
+
+sph_status sph_step(sph_ctx* c, int32_t n_steps) {
+    if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(c, SPH_EINVAL, "n_steps must be >= 0");
+    return (sph_status)c->step_fn(c, n_steps);
+}
+
+sph_status sph_evaluate(sph_ctx* c) {
+    if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
+    return (sph_status)c->evaluate_fn(c);
+}
+
+sph_status sph_read(sph_ctx* c, int32_t field, void* host_dst, size_t bytes) {
+    if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
+    return (sph_status)c->read_fn(c, field, host_dst, bytes);
+}
+
+sph_status sph_neighbors(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total) {
+    if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
+    if (!start || !total) return fail(c, SPH_EINVAL, "start/total is NULL");
+    return (sph_status)c->nbr_fn(c, start, nbr, cap, total);
+}
+
+sph_status sph_sync(sph_ctx* c) {
+    if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+sph_status sph_profile(sph_ctx* c, int32_t n_steps, int32_t max_stats, const char** names, double* avg_ms,
+                       int64_t* calls, int32_t* n_stats) {
+    if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
+    if (n_steps < 0 || !n_stats) return fail(c, SPH_EINVAL, "bad arguments");
+    c->timer.reset();
+    c->timer.enabled = true;
+    int rc = SPH_OK;
+    if (c->opt.dtype_bits == 32) {
+        auto* m = impl_of<float>(c);
+        for (int s = 0; s < n_steps; ++s) m->step(c->stream, &c->timer);
+    } else {
+        auto* m = impl_of<double>(c);
+        for (int s = 0; s < n_steps; ++s) m->step(c->stream, &c->timer);
+    }
+    c->timer.enabled = false;
+    c->timer.collect();
+    HIP_OK(hipGetLastError());
+    c->prof_names = c->timer.names;
+    c->prof_ptrs.clear();
+    for (auto& s : c->prof_names) c->prof_ptrs.push_back(s.c_str());
+    int k = 0;
+    for (size_t i = 0; i < c->prof_names.size() && k < max_stats; ++i, ++k) {
+        const std::string& nm = c->prof_names[i];
+        if (names) names[k] = c->prof_ptrs[i];
+        if (avg_ms) avg_ms[k] = c->timer.total_ms[nm] / (double)c->timer.calls[nm];
+        if (calls) calls[k] = c->timer.calls[nm];
+    }
+    *n_stats = (int32_t)c->prof_names.size();
+    return (sph_status)rc;
+}
+
+void sph_free(sph_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->impl.reset();
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+}  // extern "C"

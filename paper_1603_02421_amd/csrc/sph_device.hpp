@@ -1,0 +1,191 @@
+// Device-side definitions of libsphjet (gfx950, wave64).
+//
+// Data layout on the device (structure of arrays, one slot per particle, slots
+// ordered by (cell key, particle id) after every sort):
+//   pos   double2   FP64 positions (exact pair predicate, no drift at 1e-4 dx)
+//   vel   V2<T>     velocity
+//   dens  T         rho - rho0 (keeps the Tait pressure accurate in FP32)
+//   mass  T
+//   tag   uint32    (system << 4) | type
+//   id    uint32    caller's particle id
+//   cell  uint32    global cell key of the slot (system base + cx * ny + cy)
+// Cell keys put the y index fastest, so the (2R+1) x (2R+1) block of cells
+// around a particle is 2R+1 contiguous slot ranges, one per cell row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphjet {
+
+enum : uint32_t { T_FLUID = 0, T_WALL = 1, T_PISTON = 2, T_INACTIVE = 3 };
+enum : uint32_t { FLAG_NONFINITE = 1, FLAG_DENSITY = 2, FLAG_SKIN = 4 };
+
+template <typename T> struct V2t;
+template <> struct V2t<float> { using type = float2; };
+template <> struct V2t<double> { using type = double2; };
+template <typename T> using V2 = typename V2t<T>::type;
+
+// Per-system constants, precomputed on the host.
+template <typename T>
+struct SysDev {
+    // neighbour grid (FP64, so keys and the predicate are exact)
+    double x0, y0, inv_s, R2;      // grid origin, 1/cell size, (2h)^2
+    double skin2;                  // (half the skin)^2: allowed half-step displacement squared
+    int32_t nx, ny, reach, kernel;
+    uint32_t cell_base, pad_;
+    // physics in the working precision
+    T h, inv_h, wnorm, gnorm;      // W = wnorm * w(q); grad_a W = gnorm * g(q) * r_ab
+    T W0;                          // W(0)
+    T rho0, inv_rho0, B, c0;       // Tait: P = B((1 + delta)^gamma - 1), delta = dens / rho0
+    T gamma, half_gm1;             // gamma, (gamma - 1)/2
+    T alpha_h, eta2;               // alpha * h, eta^2
+    T sigma, eps;                  // surface tension, eps = eps_h / h
+    T gx, gy;
+    int32_t gamma7, closure;
+    T closure_tol;
+    // time stepping (FP64)
+    double courant, dt_fixed;
+    double box_lo_x, box_lo_y, box_hi_x, box_hi_y;
+    double pdx, pdy, pu, pamp, pomega;
+};
+
+__device__ __forceinline__ uint32_t tag_type(uint32_t t) { return t & 15u; }
+__device__ __forceinline__ uint32_t tag_sys(uint32_t t) { return t >> 4; }
+
+// Cell coordinate of x on an axis with origin lo and ncell cells; out-of-range
+// (and NaN) values clamp to the edge cells. No FMA: the key must be bit-exact.
+__device__ __forceinline__ int cell_coord(double x, double lo, double inv, int ncell) {
+#pragma clang fp contract(off)
+    double t = floor((x - lo) * inv);
+    if (!(t >= 0.0)) t = 0.0;
+    double top = (double)(ncell - 1);
+    if (t > top) t = top;
+    return (int)t;
+}
+
+// Exact FP64 pair predicate pieces: r_ab = r_a - r_b and |r_ab|^2 without FMA.
+__device__ __forceinline__ double pair_r2(double2 pa, double2 pb, double& dx, double& dy) {
+#pragma clang fp contract(off)
+    dx = pa.x - pb.x;
+    dy = pa.y - pb.y;
+    return dx * dx + dy * dy;
+}
+
+template <typename T> __device__ __forceinline__ T rcp(T x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+
+template <typename T> __device__ __forceinline__ T sqrt_(T x);
+template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ double sqrt_<double>(double x) { return __builtin_sqrt(x); }
+
+// Kernel value and gradient factor at distance r (< 2h): W(r) and F(r) with
+// grad_a W_ab = F(r) r_ab.
+//   Wendland: W = wn (1 - q/2)^4 (1 + 2q),  F = -5 wn / h^2 (1 - q/2)^3
+//   cubic:    W = wn [1 - 1.5 q^2 + 0.75 q^3 | 0.25 (2 - q)^3],
+//             F = wn / h^2 [-3 + 2.25 q | -0.75 (2 - q)^2 / q]
+template <typename T>
+__device__ __forceinline__ void kernel_wf(const SysDev<T>& S, T r, T& W, T& F) {
+    T q = r * S.inv_h;
+    if (S.kernel == 0) {
+        T u = T(1) - T(0.5) * q;
+        T u3 = u * u * u;
+        W = S.wnorm * u3 * u * (T(1) + T(2) * q);
+        F = S.gnorm * u3;
+    } else {
+        if (q <= T(1)) {
+            W = S.wnorm * (T(1) + q * q * (T(-1.5) + T(0.75) * q));
+            F = S.gnorm * (T(-3) + T(2.25) * q);
+        } else {
+            T u = T(2) - q;
+            W = S.wnorm * T(0.25) * u * u * u;
+            F = S.gnorm * T(-0.75) * u * u * rcp(q);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T kernel_w(const SysDev<T>& S, T r) {
+    T W, F;
+    kernel_wf(S, r, W, F);
+    return W;
+}
+
+template <typename T>
+__device__ __forceinline__ T kernel_f(const SysDev<T>& S, T r) {
+    T q = r * S.inv_h;
+    if (S.kernel == 0) {
+        T u = T(1) - T(0.5) * q;
+        return S.gnorm * u * u * u;
+    }
+    if (q <= T(1)) return S.gnorm * (T(-3) + T(2.25) * q);
+    T u = T(2) - q;
+    return S.gnorm * T(-0.75) * u * u * rcp(q);
+}
+
+// Tait equation: P / rho^2 and the sound speed from the stored deviation
+// dens = rho - rho0. With gamma = 7, (1 + d)^7 - 1 is expanded in d so a small
+// compression keeps its relative precision.
+template <typename T>
+__device__ __forceinline__ void tait(const SysDev<T>& S, T dens, T& rho, T& p_over_rho2, T& c) {
+    T d = dens * S.inv_rho0;
+    rho = S.rho0 + dens;
+    T irho = rcp(rho);
+    T P, cr;
+    if (S.gamma7) {
+        T e = d * (T(7) + d * (T(21) + d * (T(35) + d * (T(35) + d * (T(21) + d * (T(7) + d))))));
+        P = S.B * e;
+        T s = T(1) + d;
+        cr = s * s * s;
+    } else {
+        T l = log1p(d);
+        P = S.B * expm1(S.gamma * l);
+        cr = exp(S.half_gm1 * l);
+    }
+    p_over_rho2 = P * irho * irho;
+    c = S.c0 * cr;
+}
+
+template <typename T>
+__device__ __forceinline__ T tait_pressure(const SysDev<T>& S, T dens) {
+    T rho, pr, c;
+    tait(S, dens, rho, pr, c);
+    return pr * rho * rho;
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Minimum of non-negative values v into dst[sys] (stored as FP64 bits, whose
+// unsigned order equals the numeric order for non-negative numbers). Every lane
+// of the wave must call this; lanes with valid = false contribute nothing.
+__device__ __forceinline__ void atomic_min_per_system(unsigned long long* dst, int stride, int sys,
+                                                      double v, bool valid) {
+    int s_first = __builtin_amdgcn_readfirstlane(valid ? sys : -1);
+    bool uniform = __all(!valid || sys == s_first);
+    if (uniform) {
+        double m = wave_min(valid ? v : __builtin_inf());
+        if (__lane_id() == 0 && s_first >= 0 && m < __builtin_inf())
+            atomicMin(dst + (size_t)s_first * stride, (unsigned long long)__double_as_longlong(m));
+    } else if (valid && v < __builtin_inf()) {
+        atomicMin(dst + (size_t)sys * stride, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// Workgroup id remapped so that the workgroups one XCD receives (hardware
+// dispatches them round-robin over the 8 XCDs) cover one contiguous range of
+// slots: neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ int tile_index(int xcd_remap) {
+    int g = (int)gridDim.x, i = (int)blockIdx.x;
+    if (!xcd_remap) return i;
+    int q = g >> 3, r = g & 7, x = i & 7, k = i >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+}  // namespace sphjet

@@ -1,0 +1,142 @@
+// Internal declarations shared by the kernels and the host side of libsphjet.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sph_device.hpp"
+
+namespace sphjet {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// One full set of per-slot state arrays.
+template <typename T>
+struct StateBuf {
+    double2* pos;
+    V2<T>* vel;
+    T* dens;
+    T* mass;
+    uint32_t* tag;
+    uint32_t* id;
+};
+
+struct SortBufs {
+    uint32_t trash;     // number of cells of all systems = key of inactive particles
+    uint32_t* cstart;   // trash + 2: first slot of every cell (+ inactive start + end)
+    uint32_t* key;      // n: key of each slot before the sort
+    uint32_t* slot;     // n: position inside its cell (atomic order)
+    uint32_t* blk;      // workgroups + 1: inactive counts, then their offsets
+    uint32_t* part;     // tile sums of the cell scan
+    uint32_t* part2;    // tile sums of the workgroup scan
+    uint32_t* tmp_src;  // n: source slot of each destination slot
+    uint32_t* tmp_id;   // n: particle id of each destination slot
+    uint32_t* cell;     // n: cell key of each sorted slot
+};
+
+// What the three sweeps read and write.
+template <typename T>
+struct EvalView {
+    int n;
+    int xcd;
+    int do_dt;
+    int pad_;
+    const SysDev<T>* sys;
+    const double2* pos;
+    const V2<T>* vel;
+    const T* dens;
+    const T* mass;
+    const uint32_t* tag;
+    const uint32_t* id;
+    const uint32_t* cell;
+    const uint32_t* cstart;
+    T* colour;
+    T* drho;
+    V2<T>* acc;
+    V2<T>* nrm;
+    T* kappa;
+    T* kappa_plain;
+    unsigned long long* dtmin;  // 2 per system: [h/(c+sig) min, sqrt(h/|a|) min]
+};
+
+// What the predictor and corrector read and write.
+template <typename T>
+struct IntegView {
+    int n;
+    int pad_;
+    const SysDev<T>* sys;
+    double2* pos;          // state n (corrector updates it in place)
+    V2<T>* vel;
+    T* dens;
+    uint32_t* tag;
+    const T* drho;         // derivatives of the last evaluation
+    const V2<T>* acc;
+    double2* pos_h;        // half-step state (predictor output)
+    V2<T>* vel_h;
+    T* dens_h;
+    const double* dt;
+    const double* time;
+    uint32_t* flags;
+};
+
+struct LaunchCfg {
+    int n;
+    int block_sweep;
+    int block_stream;
+    int xcd;
+};
+
+// Optional per-kernel timing with HIP events on the launch stream.
+class KernelTimer {
+public:
+    bool enabled = false;
+    void begin(const char* name, hipStream_t st);
+    void end(hipStream_t st);
+    // Waits for the events and accumulates elapsed times per name.
+    void collect();
+    void reset();
+    std::vector<std::string> names;
+    std::map<std::string, double> total_ms;
+    std::map<std::string, long long> calls;
+    ~KernelTimer();
+
+private:
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending_;
+    std::vector<hipEvent_t> pool_;
+    hipEvent_t get_();
+    const char* cur_ = nullptr;
+    hipEvent_t cur_a_ = nullptr;
+};
+
+void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
+void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st);
+
+template <typename T>
+void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
+                 hipStream_t st, KernelTimer* kt);
+template <typename T>
+void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt);
+template <typename T>
+void launch_dt(int n_sys, const SysDev<T>* sys, unsigned long long* dtmin, double* dt, hipStream_t st,
+               KernelTimer* kt);
+template <typename T>
+void launch_predict(const LaunchCfg& L, const IntegView<T>& v, hipStream_t st, KernelTimer* kt);
+template <typename T>
+void launch_correct(const LaunchCfg& L, const IntegView<T>& v, int n_sys, const double* dt, double* time,
+                    hipStream_t st, KernelTimer* kt);
+template <typename T>
+void launch_nbr_count(const LaunchCfg& L, const EvalView<T>& v, uint32_t* count, hipStream_t st);
+template <typename T>
+void launch_nbr_fill(const EvalView<T>& v, int a0, int a1, const int64_t* start, int64_t base, uint32_t* out,
+                     hipStream_t st);
+template <typename T>
+void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* dens, T* out, hipStream_t st);
+
+}  // namespace sphjet

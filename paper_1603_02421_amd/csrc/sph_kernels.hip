@@ -1,0 +1,626 @@
+// HIP kernels of libsphjet (gfx950). One thread per particle slot throughout;
+// every per-particle sum is a gather over the slot ranges of the neighbouring
+// cells, so no floating-point atomics are used and results are bit-for-bit
+// reproducible run to run.
+#include "sph_internal.hpp"
+
+namespace sphjet {
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Exclusive scan inside one workgroup of SCAN_THREADS threads (wave64 shuffles
+// + one LDS pass over the wave totals). Returns the exclusive prefix of x and
+// writes the workgroup total to *total.
+__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total) {
+    __shared__ uint32_t wsum[17];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nw; ++w) { uint32_t t = wsum[w]; wsum[w] = run; run += t; }
+        wsum[16] = run;
+    }
+    __syncthreads();
+    uint32_t r = wsum[wid] + incl - x;
+    *total = wsum[16];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ scan (u32)
+// Exclusive prefix sum of data[0..m) in place, total stored at data[m].
+// Tiles of SCAN_TILE elements: reduce, scan of tile sums, apply.
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* data, int64_t m, uint32_t* part) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + (int64_t)k * SCAN_THREADS + threadIdx.x;
+        if (i < m) s += data[i];
+    }
+    uint32_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_parts(uint32_t* part, int64_t nb) {
+    // one workgroup of 1024 threads, each owning a contiguous chunk
+    int64_t per = (nb + 1023) / 1024;
+    int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    uint32_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += part[i];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot);
+    for (int64_t i = b0; i < b1; ++i) { uint32_t t = part[i]; part[i] = run; run += t; }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(uint32_t* data, int64_t m, const uint32_t* part) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    // each thread owns SCAN_ITEMS consecutive elements
+    int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (i0 + k < m) ? data[i0 + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (i0 + k < m) data[i0 + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) data[m] = run;
+}
+
+// ------------------------------------------------------------------ sort
+// Cell key of every slot, slot within its cell (atomic counter: the order
+// inside a cell is fixed afterwards by k_cellsort), and per-workgroup counts
+// of inactive particles (their order comes from a stable compaction).
+
+template <typename T>
+__global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uint32_t* tag,
+                      uint32_t* key, uint32_t* slot, uint32_t* counts, uint32_t trash,
+                      uint32_t* blk_inactive) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool inactive = false;
+    if (i < n) {
+        uint32_t t = tag[i];
+        uint32_t k = trash, sl = 0;
+        if (tag_type(t) != T_INACTIVE) {
+            const SysDev<T>& S = sys[tag_sys(t)];
+            double2 p = pos[i];
+            int cx = cell_coord(p.x, S.x0, S.inv_s, S.nx);
+            int cy = cell_coord(p.y, S.y0, S.inv_s, S.ny);
+            k = S.cell_base + (uint32_t)cx * (uint32_t)S.ny + (uint32_t)cy;
+            sl = atomicAdd(&counts[k], 1u);
+        } else {
+            inactive = true;
+        }
+        key[i] = k;
+        slot[i] = sl;
+    }
+    int c = __syncthreads_count(inactive);
+    if (threadIdx.x == 0) blk_inactive[blockIdx.x] = (uint32_t)c;
+}
+
+__global__ void k_scatter(int n, const uint32_t* key, const uint32_t* slot, const uint32_t* id,
+                          const uint32_t* cstart, uint32_t trash, const uint32_t* blk_off,
+                          uint32_t* tmp_src, uint32_t* tmp_id) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t k = i < n ? key[i] : 0u;
+    bool inactive = i < n && k == trash;
+    uint32_t tot;
+    uint32_t rank = block_exclusive_scan(inactive ? 1u : 0u, &tot);
+    if (i >= n) return;
+    uint32_t dst = inactive ? cstart[trash] + blk_off[blockIdx.x] + rank : cstart[k] + slot[i];
+    tmp_src[dst] = (uint32_t)i;
+    tmp_id[dst] = id[i];
+}
+
+// Order every cell's slots by particle id (cells hold ~8 particles).
+__global__ void k_cellsort(uint32_t ncells, const uint32_t* cstart, uint32_t* tmp_src, uint32_t* tmp_id) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    uint32_t s = cstart[c], e = cstart[c + 1];
+    if (e - s < 2) return;
+    for (uint32_t j = s + 1; j < e; ++j) {
+        uint32_t kid = tmp_id[j], ksrc = tmp_src[j];
+        uint32_t m = j;
+        while (m > s && tmp_id[m - 1] > kid) {
+            tmp_id[m] = tmp_id[m - 1];
+            tmp_src[m] = tmp_src[m - 1];
+            --m;
+        }
+        tmp_id[m] = kid;
+        tmp_src[m] = ksrc;
+    }
+}
+
+template <typename T>
+__global__ void k_permute(int n, const uint32_t* tmp_src, const uint32_t* tmp_id, const uint32_t* key,
+                          StateBuf<T> X, StateBuf<T> Y, uint32_t* cell) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    uint32_t s = tmp_src[j];
+    Y.pos[j] = X.pos[s];
+    Y.vel[j] = X.vel[s];
+    Y.dens[j] = X.dens[s];
+    Y.mass[j] = X.mass[s];
+    Y.tag[j] = X.tag[s];
+    Y.id[j] = tmp_id[j];
+    cell[j] = key[s];
+}
+
+// ------------------------------------------------------------------ sweeps
+// Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that
+// passes the exact predicate |r_ab|^2 < (2h)^2, calling f(b, dx, dy, r2) with
+// r_ab = r_a - r_b in the working precision.
+
+template <typename T, typename Fn>
+__device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_t* cstart, uint32_t cell,
+                                               int a, double2 pa, const double2* pos, Fn&& f) {
+    uint32_t local = cell - S.cell_base;
+    int cx = (int)(local / (uint32_t)S.ny);
+    int cy = (int)(local - (uint32_t)cx * (uint32_t)S.ny);
+    int R = S.reach;
+    int ylo = cy - R < 0 ? 0 : cy - R;
+    int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
+    int xlo = cx - R < 0 ? 0 : cx - R;
+    int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
+    for (int X = xlo; X <= xhi; ++X) {
+        uint32_t row = S.cell_base + (uint32_t)X * (uint32_t)S.ny;
+        uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
+        for (uint32_t b = b0; b < b1; ++b) {
+            if ((int)b == a) continue;
+            double dx, dy;
+            double r2 = pair_r2(pa, pos[b], dx, dy);
+            if (r2 < S.R2) f((int)b, (T)dx, (T)dy);
+        }
+    }
+}
+
+// Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included (eq. 14).
+template <typename T>
+__global__ void k_colour(EvalView<T> v) {
+    int a = tile_index(v.xcd) * blockDim.x + threadIdx.x;
+    if (a >= v.n) return;
+    uint32_t t = v.tag[a];
+    if (tag_type(t) == T_INACTIVE) return;
+    const SysDev<T>& S = v.sys[tag_sys(t)];
+    double2 pa = v.pos[a];
+    T sum = v.mass[a] * rcp(S.rho0 + v.dens[a]) * S.W0;
+    for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
+        T r = sqrt_(dx * dx + dy * dy);
+        sum += v.mass[b] * rcp(S.rho0 + v.dens[b]) * kernel_w(S, r);
+    });
+    v.colour[a] = sum;
+}
+
+// Sweep 2: continuity (eq. 7) for every active particle; for fluid particles
+// also the pressure + artificial-viscosity acceleration (eq. 9-10) and the
+// interface normal n_a = sum_b (m_b/rho_b)(C_b - C_a) grad_a W_ab (eq. 18);
+// the signal term max_b |h v_ab . r_ab| / r_ab^2 feeds the eq. 31 limit.
+template <typename T>
+__global__ void k_main(EvalView<T> v) {
+    int a = tile_index(v.xcd) * blockDim.x + threadIdx.x;
+    bool valid = a < v.n;
+    uint32_t t = valid ? v.tag[a] : (uint32_t)T_INACTIVE;
+    valid = valid && tag_type(t) != T_INACTIVE;
+    int sys = (int)tag_sys(t);
+    double dtcv = __builtin_inf();
+    if (valid) {
+        const SysDev<T>& S = v.sys[sys];
+        const bool fluid = tag_type(t) == T_FLUID;
+        double2 pa = v.pos[a];
+        V2<T> va = v.vel[a];
+        T rho_a, pr_a, c_a;
+        tait(S, v.dens[a], rho_a, pr_a, c_a);
+        T Ca = v.colour[a];
+        T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, vsig = 0;
+        if (fluid) {
+            for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
+                T r2 = dx * dx + dy * dy;
+                T r = sqrt_(r2);
+                T F = kernel_f(S, r);
+                V2<T> vb = v.vel[b];
+                T ux = va.x - vb.x, uy = va.y - vb.y;
+                T vr = ux * dx + uy * dy;
+                T mb = v.mass[b];
+                drho += mb * F * vr;
+                T sg = fabs(S.h * vr * rcp(r2));
+                vsig = sg > vsig ? sg : vsig;
+                T rho_b, pr_b, c_b;
+                tait(S, v.dens[b], rho_b, pr_b, c_b);
+                T pi = 0;
+                if (vr < T(0)) {
+                    T cbar = T(0.5) * (c_a + c_b);
+                    T rbar = T(0.5) * (rho_a + rho_b);
+                    pi = -S.alpha_h * cbar * vr * rcp(rbar * (r2 + S.eta2));
+                }
+                T coef = mb * (pr_a + pr_b + pi) * F;
+                ax -= coef * dx;
+                ay -= coef * dy;
+                T cn = mb * rcp(rho_b) * (v.colour[b] - Ca) * F;
+                nx += cn * dx;
+                ny += cn * dy;
+            });
+        } else {
+            for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
+                T r2 = dx * dx + dy * dy;
+                T F = kernel_f(S, sqrt_(r2));
+                V2<T> vb = v.vel[b];
+                T vr = (va.x - vb.x) * dx + (va.y - vb.y) * dy;
+                drho += v.mass[b] * F * vr;
+                T sg = fabs(S.h * vr * rcp(r2));
+                vsig = sg > vsig ? sg : vsig;
+            });
+        }
+        v.drho[a] = drho;
+        V2<T> acc, nrm;
+        acc.x = ax; acc.y = ay;
+        nrm.x = nx; nrm.y = ny;
+        v.acc[a] = acc;
+        v.nrm[a] = nrm;
+        dtcv = (double)(S.h / (c_a + vsig));
+    }
+    if (v.do_dt) atomic_min_per_system(v.dtmin, 2, sys, dtcv, valid);
+}
+
+// Sweep 3 (fluid only): normal filter N_a = [|n_a| > eps] (eq. 20-21),
+// curvature kappa_a = sum_b min(N_a,N_b)(m_b/rho_b)(nh_b - nh_a).grad_a W_ab /
+// sum_b min(N_a,N_b)(m_b/rho_b) W_ab (eq. 23, self in the denominator),
+// surface-tension acceleration -(sigma/rho_a) kappa_a n_a (eq. 24) and the
+// total acceleration (eq. 25); |a| feeds the eq. 30 limit.
+template <typename T>
+__global__ void k_surface(EvalView<T> v) {
+    int a = tile_index(v.xcd) * blockDim.x + threadIdx.x;
+    bool valid = a < v.n;
+    uint32_t t = valid ? v.tag[a] : (uint32_t)T_INACTIVE;
+    valid = valid && tag_type(t) == T_FLUID;
+    int sys = (int)tag_sys(t);
+    double dtf = __builtin_inf();
+    if (valid) {
+        const SysDev<T>& S = v.sys[sys];
+        V2<T> n_a = v.nrm[a];
+        T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
+        V2<T> acc = v.acc[a];
+        T kappa = 0;
+        T rho_a = S.rho0 + v.dens[a];
+        if (mag > S.eps) {
+            T im = rcp(mag);
+            T hx = n_a.x * im, hy = n_a.y * im;
+            T num = 0;
+            T den = v.mass[a] * rcp(rho_a) * S.W0;
+            double2 pa = v.pos[a];
+            for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
+                V2<T> n_b = v.nrm[b];
+                T mb = sqrt_(n_b.x * n_b.x + n_b.y * n_b.y);
+                if (mb > S.eps) {
+                    T ib = rcp(mb);
+                    T r = sqrt_(dx * dx + dy * dy);
+                    T W, F;
+                    kernel_wf(S, r, W, F);
+                    T vol = v.mass[b] * rcp(S.rho0 + v.dens[b]);
+                    num += vol * F * ((n_b.x * ib - hx) * dx + (n_b.y * ib - hy) * dy);
+                    den += vol * W;
+                }
+            });
+            kappa = num / den;
+        }
+        v.kappa_plain[a] = kappa;
+        T f = -S.sigma * rcp(rho_a) * kappa;
+        acc.x += f * n_a.x + S.gx;
+        acc.y += f * n_a.y + S.gy;
+        v.acc[a] = acc;
+        v.kappa[a] = kappa;
+        T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
+        if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
+    }
+    if (v.do_dt) atomic_min_per_system(v.dtmin, 2, sys, dtf, valid);
+}
+
+// ------------------------------------------------------------------ time step
+
+template <typename T>
+__global__ void k_dt_finalize(int n_sys, const SysDev<T>* sys, unsigned long long* dtmin, double* dt) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sys) return;
+    const SysDev<T>& S = sys[s];
+    double f = __longlong_as_double((long long)dtmin[2 * s + 1]);   // sqrt(h/|a|)
+    double cv = __longlong_as_double((long long)dtmin[2 * s + 0]);  // h/(c + sig)
+    double d = S.dt_fixed > 0.0 ? S.dt_fixed : S.courant * fmin(f, cv);
+    if (!(d < __builtin_inf())) d = 0.0;
+    dt[s] = d;
+    unsigned long long inf_bits = (unsigned long long)__double_as_longlong(__builtin_inf());
+    dtmin[2 * s] = inf_bits;
+    dtmin[2 * s + 1] = inf_bits;
+}
+
+__device__ __forceinline__ double piston_travel(double U, double A, double w, double t) {
+    if (w == 0.0) return U * t;
+    return U * (t + A * (1.0 - cos(w * t)) / w);
+}
+__device__ __forceinline__ double piston_speed(double U, double A, double w, double t) {
+    return U * (1.0 + A * sin(w * t));
+}
+
+// Predictor: half-step state from state n and its derivatives.
+template <typename T>
+__global__ void k_predict(IntegView<T> v) {
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= v.n) return;
+    uint32_t t = v.tag[a];
+    uint32_t ty = tag_type(t);
+    if (ty == T_INACTIVE) return;
+    const SysDev<T>& S = v.sys[tag_sys(t)];
+    double dt = v.dt[tag_sys(t)];
+    double hd = 0.5 * dt;
+    T hdt = (T)hd;
+    double2 p = v.pos[a];
+    V2<T> u = v.vel[a];
+    v.dens_h[a] = v.dens[a] + hdt * v.drho[a];
+    if (ty == T_FLUID) {
+        V2<T> acc = v.acc[a];
+        double2 q;
+        q.x = p.x + hd * (double)u.x;
+        q.y = p.y + hd * (double)u.y;
+        double ddx = q.x - p.x, ddy = q.y - p.y;
+        if (ddx * ddx + ddy * ddy > S.skin2) atomicOr(v.flags, FLAG_SKIN);
+        v.pos_h[a] = q;
+        V2<T> w;
+        w.x = u.x + hdt * acc.x;
+        w.y = u.y + hdt * acc.y;
+        v.vel_h[a] = w;
+    } else if (ty == T_PISTON) {
+        double tn = v.time[tag_sys(t)];
+        double dX = piston_travel(S.pu, S.pamp, S.pomega, tn + hd) - piston_travel(S.pu, S.pamp, S.pomega, tn);
+        double U = piston_speed(S.pu, S.pamp, S.pomega, tn + hd);
+        double2 q;
+        q.x = p.x + S.pdx * dX;
+        q.y = p.y + S.pdy * dX;
+        v.pos_h[a] = q;
+        V2<T> w;
+        w.x = (T)(S.pdx * U);
+        w.y = (T)(S.pdy * U);
+        v.vel_h[a] = w;
+    } else {
+        v.pos_h[a] = p;
+        v.vel_h[a] = u;
+    }
+}
+
+// Corrector: state n+1 from state n and the half-step derivatives, in place;
+// fluid leaving the box becomes inactive; instability checks.
+template <typename T>
+__global__ void k_correct(IntegView<T> v) {
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= v.n) return;
+    uint32_t t = v.tag[a];
+    uint32_t ty = tag_type(t);
+    if (ty == T_INACTIVE) return;
+    const SysDev<T>& S = v.sys[tag_sys(t)];
+    double dt = v.dt[tag_sys(t)];
+    T tdt = (T)dt;
+    T dens = v.dens[a] + tdt * v.drho[a];
+    v.dens[a] = dens;
+    uint32_t flags = 0;
+    if (!isfinite(dens)) flags |= FLAG_NONFINITE;
+    else if (dens < T(-0.5) * S.rho0 || dens > S.rho0) flags |= FLAG_DENSITY;
+    double2 p = v.pos[a];
+    if (ty == T_FLUID) {
+        V2<T> u = v.vel[a];
+        V2<T> acc = v.acc[a];
+        p.x = p.x + dt * ((double)u.x + 0.5 * dt * (double)acc.x);
+        p.y = p.y + dt * ((double)u.y + 0.5 * dt * (double)acc.y);
+        u.x += tdt * acc.x;
+        u.y += tdt * acc.y;
+        v.pos[a] = p;
+        v.vel[a] = u;
+        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(u.x) || !isfinite(u.y)) flags |= FLAG_NONFINITE;
+        if (p.x < S.box_lo_x || p.x > S.box_hi_x || p.y < S.box_lo_y || p.y > S.box_hi_y)
+            v.tag[a] = (t & ~15u) | T_INACTIVE;
+    } else if (ty == T_PISTON) {
+        double tn = v.time[tag_sys(t)];
+        double dX = piston_travel(S.pu, S.pamp, S.pomega, tn + dt) - piston_travel(S.pu, S.pamp, S.pomega, tn);
+        double U = piston_speed(S.pu, S.pamp, S.pomega, tn + dt);
+        p.x += S.pdx * dX;
+        p.y += S.pdy * dX;
+        v.pos[a] = p;
+        V2<T> w;
+        w.x = (T)(S.pdx * U);
+        w.y = (T)(S.pdy * U);
+        v.vel[a] = w;
+    }
+    if (flags) atomicOr(v.flags, flags);
+}
+
+__global__ void k_advance_time(int n_sys, const double* dt, double* time) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_sys) time[s] += dt[s];
+}
+
+// ------------------------------------------------------------------ debug: neighbour lists
+
+template <typename T>
+__global__ void k_nbr_count(EvalView<T> v, uint32_t* count) {
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= v.n) return;
+    uint32_t t = v.tag[a];
+    uint32_t c = 0;
+    if (tag_type(t) != T_INACTIVE) {
+        const SysDev<T>& S = v.sys[tag_sys(t)];
+        for_neighbours<T>(S, v.cstart, v.cell[a], a, v.pos[a], v.pos, [&](int, T, T) { ++c; });
+    }
+    count[a] = c;
+}
+
+template <typename T>
+__global__ void k_nbr_fill(EvalView<T> v, int a0, int a1, const int64_t* start, int64_t base, uint32_t* out) {
+    int a = a0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= a1) return;
+    uint32_t t = v.tag[a];
+    if (tag_type(t) == T_INACTIVE) return;
+    const SysDev<T>& S = v.sys[tag_sys(t)];
+    int64_t k = start[a] - base;
+    for_neighbours<T>(S, v.cstart, v.cell[a], a, v.pos[a], v.pos, [&](int b, T, T) { out[k++] = v.id[b]; });
+}
+
+// Derived per-slot quantities for sph_read.
+template <typename T>
+__global__ void k_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* dens, T* out) {
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    uint32_t t = tag[a];
+    out[a] = tait_pressure(sys[tag_sys(t)], dens[a]);
+}
+
+// A plain copy of known size: the reference point for HBM byte counters.
+__global__ void k_copy_u32x4(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+    if (n) k_fill_u32<<<nblk((int64_t)n, 256), 256, 0, st>>>(p, n, v);
+}
+void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st) {
+    if (n) k_fill_u64<<<nblk((int64_t)n, 256), 256, 0, st>>>(p, n, v);
+}
+
+void launch_scan(uint32_t* data, int64_t m, uint32_t* part, hipStream_t st, KernelTimer* kt) {
+    unsigned nb = nblk(m, SCAN_TILE);
+    kt->begin("scan", st);
+    k_scan_reduce<<<nb, SCAN_THREADS, 0, st>>>(data, m, part);
+    k_scan_parts<<<1, 1024, 0, st>>>(part, nb);
+    k_scan_apply<<<nb, SCAN_THREADS, 0, st>>>(data, m, part);
+    kt->end(st);
+}
+
+void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st) {
+    size_t n = bytes / 16;
+    k_copy_u32x4<<<nblk((int64_t)n, 256), 256, 0, st>>>((const uint4*)src, (uint4*)dst, n);
+}
+
+template <typename T>
+void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
+                 hipStream_t st, KernelTimer* kt) {
+    const int n = L.n;
+    const int bs = L.block_stream;
+    const uint32_t trash = B.trash;
+    const unsigned nb = nblk(n, bs);
+    kt->begin("sort_clear", st);
+    launch_fill_u32(B.cstart, (size_t)trash + 2, 0u, st);
+    kt->end(st);
+    kt->begin("sort_key", st);
+    k_key<T><<<nb, bs, 0, st>>>(n, sys, X.pos, X.tag, B.key, B.slot, B.cstart, trash, B.blk);
+    kt->end(st);
+    launch_scan(B.cstart, (int64_t)trash + 1, B.part, st, kt);
+    launch_scan(B.blk, (int64_t)nb, B.part2, st, kt);
+    kt->begin("sort_scatter", st);
+    k_scatter<<<nb, bs, 0, st>>>(n, B.key, B.slot, X.id, B.cstart, trash, B.blk, B.tmp_src, B.tmp_id);
+    kt->end(st);
+    kt->begin("sort_cells", st);
+    k_cellsort<<<nblk(trash, 256), 256, 0, st>>>(trash, B.cstart, B.tmp_src, B.tmp_id);
+    kt->end(st);
+    kt->begin("sort_permute", st);
+    k_permute<T><<<nb, bs, 0, st>>>(n, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell);
+    kt->end(st);
+}
+
+template <typename T>
+void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt) {
+    const int bs = L.block_sweep;
+    const unsigned nb = nblk(L.n, bs);
+    kt->begin("colour", st);
+    k_colour<T><<<nb, bs, 0, st>>>(v);
+    kt->end(st);
+    kt->begin("main", st);
+    k_main<T><<<nb, bs, 0, st>>>(v);
+    kt->end(st);
+    kt->begin("surface", st);
+    k_surface<T><<<nb, bs, 0, st>>>(v);
+    kt->end(st);
+}
+
+template <typename T>
+void launch_dt(int n_sys, const SysDev<T>* sys, unsigned long long* dtmin, double* dt, hipStream_t st,
+               KernelTimer* kt) {
+    kt->begin("dt", st);
+    k_dt_finalize<T><<<nblk(n_sys, 64), 64, 0, st>>>(n_sys, sys, dtmin, dt);
+    kt->end(st);
+}
+
+template <typename T>
+void launch_predict(const LaunchCfg& L, const IntegView<T>& v, hipStream_t st, KernelTimer* kt) {
+    kt->begin("predict", st);
+    k_predict<T><<<nblk(L.n, L.block_stream), L.block_stream, 0, st>>>(v);
+    kt->end(st);
+}
+
+template <typename T>
+void launch_correct(const LaunchCfg& L, const IntegView<T>& v, int n_sys, const double* dt, double* time,
+                    hipStream_t st, KernelTimer* kt) {
+    kt->begin("correct", st);
+    k_correct<T><<<nblk(L.n, L.block_stream), L.block_stream, 0, st>>>(v);
+    kt->end(st);
+    kt->begin("time", st);
+    k_advance_time<<<nblk(n_sys, 64), 64, 0, st>>>(n_sys, dt, time);
+    kt->end(st);
+}
+
+template <typename T>
+void launch_nbr_count(const LaunchCfg& L, const EvalView<T>& v, uint32_t* count, hipStream_t st) {
+    k_nbr_count<T><<<nblk(L.n, 256), 256, 0, st>>>(v, count);
+}
+
+template <typename T>
+void launch_nbr_fill(const EvalView<T>& v, int a0, int a1, const int64_t* start, int64_t base, uint32_t* out,
+                     hipStream_t st) {
+    if (a1 > a0) k_nbr_fill<T><<<nblk(a1 - a0, 256), 256, 0, st>>>(v, a0, a1, start, base, out);
+}
+
+template <typename T>
+void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* dens, T* out, hipStream_t st) {
+    k_pressure<T><<<nblk(n, 256), 256, 0, st>>>(n, sys, tag, dens, out);
+}
+
+#define SPHJET_INSTANTIATE(T)                                                                               \
+    template void launch_sort<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,        \
+                                 StateBuf<T>, hipStream_t, KernelTimer*);                                  \
+    template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t, KernelTimer*);         \
+    template void launch_dt<T>(int, const SysDev<T>*, unsigned long long*, double*, hipStream_t,           \
+                               KernelTimer*);                                                              \
+    template void launch_predict<T>(const LaunchCfg&, const IntegView<T>&, hipStream_t, KernelTimer*);     \
+    template void launch_correct<T>(const LaunchCfg&, const IntegView<T>&, int, const double*, double*,    \
+                                    hipStream_t, KernelTimer*);                                            \
+    template void launch_nbr_count<T>(const LaunchCfg&, const EvalView<T>&, uint32_t*, hipStream_t);       \
+    template void launch_nbr_fill<T>(const EvalView<T>&, int, int, const int64_t*, int64_t, uint32_t*,    \
+                                     hipStream_t);                                                         \
+    template void launch_pressure<T>(int, const SysDev<T>*, const uint32_t*, const T*, T*, hipStream_t);
+
+SPHJET_INSTANTIATE(float)
+SPHJET_INSTANTIATE(double)
+
+}  // namespace sphjet
