@@ -65,9 +65,12 @@ typedef enum {
 enum { SPH_WENDLAND = 0,   /* eq. 28, normalised: 7/(4 pi h^2) (1 - q/2)^4 (1 + 2q) */
        SPH_CUBIC = 1 };    /* eq. 27, 10/(7 pi h^2) times the cubic B-spline */
 
-/* Particle types. Walls and the piston are dynamic boundary particles: they
- * enter every neighbour sum and their density obeys eq. 7 and eq. 26; walls do
- * not move, the piston follows its prescribed motion. A fluid particle that
+/* Particle types. Walls and the piston are dynamic boundary particles standing
+ * in for the paper's repulsive wall (Section 2-6): they enter every neighbour
+ * sum of a fluid particle; their own density obeys eq. 7 summed over fluid
+ * neighbours only, is held at or above rho0 (so they push fluid away but never
+ * pull it) and sets their pressure through eq. 26; walls do not move, the
+ * piston follows its prescribed motion. A fluid particle that
  * leaves its system's box at the end of a step becomes INACTIVE for good and is
  * excluded from every sum. */
 enum { SPH_FLUID = 0, SPH_WALL = 1, SPH_PISTON = 2, SPH_INACTIVE = 3 };

@@ -15,9 +15,14 @@
  *  - eq. 24 uses the constant sigma and the un-normalised n_a.
  *  - eq. 31 is read as |h v_ab . r_ab| / r_ab^2 with c_s = c_a.
  *  - |f_a| in eq. 30 is the total acceleration (eq. 25) of a fluid particle.
- *  - Boundaries are dynamic particles: they take part in every sum, their
- *    density follows eq. 7 and eq. 26, walls stay fixed, the piston follows its
- *    prescribed motion, and they carry no normal (N = 0) or surface force.
+ *  - Boundaries are dynamic particles: they enter every sum of a fluid
+ *    particle; their own density follows eq. 7 summed over fluid neighbours only
+ *    (a boundary interacts with the fluid, never with another boundary, as in a
+ *    force-type wall) and eq. 26, and it is held at or above rho0 after every
+ *    update so a boundary pushes fluid away but never pulls it (the paper's
+ *    wall of Section 2-6 is a purely repulsive force); walls stay fixed, the
+ *    piston follows its prescribed motion, and boundaries carry no normal
+ *    (N = 0) or surface force.
  *  - The predictor-corrector (Section 2-8 cites it without equations):
  *    half step phi_1/2 = phi_n + dt/2 D_n; full step rho_{n+1} = rho_n + dt Drho_1/2,
  *    v_{n+1} = v_n + dt a_1/2, r_{n+1} = r_n + dt (v_n + dt/2 a_1/2); dt from
@@ -331,6 +336,8 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
             double nx = 0.0, ny = 0.0, sn = 0.0, vmax = 0.0;
             for (int64_t k = start[a]; k < start[a + 1]; ++k) {
                 int64_t b = nbr[k];
+                /* a boundary particle's density responds to the fluid only */
+                if (!fluid && type[b] != ORC_FLUID) continue;
                 double rx = pos[2 * a] - pos[2 * b], ry = pos[2 * a + 1] - pos[2 * b + 1];
                 double r2 = rx * rx + ry * ry;
                 double r = sqrt(r2);
@@ -497,6 +504,7 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
                 rh[a] = rho[a];
                 if (type[a] == ORC_INACTIVE) continue;
                 rh[a] = rho[a] + hdt * d0[a];
+                if (type[a] != ORC_FLUID && rh[a] < p->rho0) rh[a] = p->rho0;  /* walls only repel */
                 if (type[a] == ORC_FLUID) {
                     ph[2 * a] = pos[2 * a] + hdt * vel[2 * a];
                     ph[2 * a + 1] = pos[2 * a + 1] + hdt * vel[2 * a + 1];
@@ -525,6 +533,7 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
             for (int64_t a = off[s]; a < off[s + 1]; ++a) {
                 if (type[a] == ORC_INACTIVE) continue;
                 rho[a] = rho[a] + T * d1[a];
+                if (type[a] != ORC_FLUID && rho[a] < p->rho0) rho[a] = p->rho0;  /* walls only repel */
                 if (type[a] == ORC_FLUID) {
                     double vx = vel[2 * a], vy = vel[2 * a + 1];
                     pos[2 * a] = pos[2 * a] + T * (vx + 0.5 * T * a1[2 * a]);

@@ -214,7 +214,8 @@ __global__ void k_colour(EvalView<T> v) {
     v.colour[a] = sum;
 }
 
-// Sweep 2: continuity (eq. 7) for every active particle; for fluid particles
+// Sweep 2: continuity (eq. 7) for every active particle (a boundary particle
+// sums over fluid neighbours only); for fluid particles
 // also the pressure + artificial-viscosity acceleration (eq. 9-10) and the
 // interface normal n_a = sum_b (m_b/rho_b)(C_b - C_a) grad_a W_ab (eq. 18);
 // the signal term max_b |h v_ab . r_ab| / r_ab^2 feeds the eq. 31 limit.
@@ -263,7 +264,9 @@ __global__ void k_main(EvalView<T> v) {
                 ny += cn * dy;
             });
         } else {
+            // a boundary particle's density responds to fluid neighbours only
             for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
+                if (tag_type(v.tag[b]) != T_FLUID) return;
                 T r2 = dx * dx + dy * dy;
                 T F = kernel_f(S, sqrt_(r2));
                 V2<T> vb = v.vel[b];
@@ -376,7 +379,9 @@ __global__ void k_predict(IntegView<T> v) {
     T hdt = (T)hd;
     double2 p = v.pos[a];
     V2<T> u = v.vel[a];
-    v.dens_h[a] = v.dens[a] + hdt * v.drho[a];
+    T dh = v.dens[a] + hdt * v.drho[a];
+    if (ty != T_FLUID && dh < T(0)) dh = T(0);   // boundaries never below rho0: they only repel
+    v.dens_h[a] = dh;
     if (ty == T_FLUID) {
         V2<T> acc = v.acc[a];
         double2 q;
@@ -420,6 +425,7 @@ __global__ void k_correct(IntegView<T> v) {
     double dt = v.dt[tag_sys(t)];
     T tdt = (T)dt;
     T dens = v.dens[a] + tdt * v.drho[a];
+    if (ty != T_FLUID && dens < T(0)) dens = T(0);   // boundaries never below rho0
     v.dens[a] = dens;
     uint32_t flags = 0;
     if (!isfinite(dens)) flags |= FLAG_NONFINITE;

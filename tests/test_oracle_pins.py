@@ -268,6 +268,32 @@ def test_mass_ledger_with_deactivation(orc):
     assert np.all(st.pos[~act, 0] > 0)  # they left through the right face
 
 
+def test_boundaries_only_repel(orc):
+    """Dynamic boundary particles stand in for a purely repulsive wall: their
+    density responds to the fluid only and never falls below rho0, so their
+    pressure is never negative. A piston sliding along fixed walls leaves them
+    at rest density."""
+    s = wl.dam_break()
+    st = orc.State(s)
+    st.step(60)
+    wall = s.type == wl.WALL
+    assert st.rho[wall].min() >= s.params["rho0"]
+    P, _ = orc.eos(s.params, st.rho[wall])
+    assert P.min() >= 0.0
+    # piston sliding along a wall, no fluid anywhere: nothing changes density
+    w = wl.lattice_block(20, 2, dx=1.0)
+    w.type[:] = wl.WALL
+    p = wl.lattice_block(3, 4, dx=1.0)
+    p.type[:] = wl.PISTON
+    p.pos[:, 1] += 2.0
+    both = wl.scenarios._assemble(w.params, [(w.pos, (0.0, 0.0), 1.0, wl.WALL),
+                                             (p.pos, (0.0, 0.0), 1.0, wl.PISTON)])
+    both.params.update(piston_u=0.5, dt_fixed=0.01, box_lo=(-5.0, -5.0), box_hi=(30.0, 10.0))
+    st2 = orc.State(both)
+    st2.step(100)
+    assert np.all(st2.rho == 1.0)
+
+
 # ------------------------------------------------ colour, normal, curvature
 
 def test_colour_bulk_and_surface(orc):

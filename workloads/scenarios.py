@@ -224,7 +224,8 @@ def jet(n_target: int = 300_000, nD: int = 20, Re: float = 500.0, We: float = 20
     of `wall_layers` particle layers at x in [0, t] with an opening |y| < D/2; a
     free region x in [t, t + free_length]. The tank is sized so the total particle
     count is about `n_target` (aspect Lt/W = tank_aspect, W >= 2D). A column of
-    fluid `prefill` D long already leaves the orifice at speed U. The piston moves
+    fluid up to `prefill` D long (at most a quarter of the particles) already
+    leaves the orifice at speed U. The piston moves
     at U (D/W)(1 + 0.01 sin(k U t)), k = kD/D, so the mean orifice speed is U.
     Fluid positions carry seeded uniform jitter in [-jitter dx, jitter dx].
     """
@@ -232,7 +233,9 @@ def jet(n_target: int = 300_000, nD: int = 20, Re: float = 500.0, We: float = 20
     dx = 1.0 / nD
     nl = wall_layers
     t_plate = nl * dx
-    n_pre = int(round(prefill / dx))
+    # the pre-formed column takes at most a quarter of the particles: the tank
+    # keeps the rest, so the piston stays far from the orifice plate
+    n_pre = min(int(round(prefill / dx)), int(0.25 * n_target / nD))
     # tank width in lattice units, same parity as nD so the orifice is symmetric
     area_particles = max(n_target - n_pre * nD, 4 * nD * nD)
     ny = int(math.sqrt(area_particles / tank_aspect))
@@ -241,18 +244,21 @@ def jet(n_target: int = 300_000, nD: int = 20, Re: float = 500.0, We: float = 20
         ny += 1
     W = ny * dx
     # solve for the tank length so that the total count is about n_target
+    # Piston and front plate span the tank interior only and the side walls start
+    # at the piston face, so no two boundary particles coincide and no wall is
+    # left behind the moving piston.
     def count(nx):
-        walls = nl * (ny + 2 * nl) + 2 * nl * (nx + 2 * nl) + nl * (ny + 2 * nl - nD)
+        walls = nl * ny + 2 * nl * (nx + nl) + nl * (ny - nD)
         return nx * ny + walls + nl * nD + n_pre * nD
     nx = max(int((n_target - count(0)) / (ny + 2 * nl)), 4)
     while count(nx) < n_target and nx < 10_000_000:
         nx += 1
     Lt = nx * dx
     tank = _lattice(-Lt, -W / 2, nx, ny, dx)
-    piston = _lattice(-Lt - nl * dx, -W / 2 - nl * dx, nl, ny + 2 * nl, dx)
-    side_lo = _lattice(-Lt - nl * dx, -W / 2 - nl * dx, nx + 2 * nl, nl, dx)
-    side_hi = _lattice(-Lt - nl * dx, W / 2, nx + 2 * nl, nl, dx)
-    plate_all = _lattice(0.0, -W / 2 - nl * dx, nl, ny + 2 * nl, dx)
+    piston = _lattice(-Lt - nl * dx, -W / 2, nl, ny, dx)
+    side_lo = _lattice(-Lt, -W / 2 - nl * dx, nx + nl, nl, dx)
+    side_hi = _lattice(-Lt, W / 2, nx + nl, nl, dx)
+    plate_all = _lattice(0.0, -W / 2, nl, ny, dx)
     hole = np.abs(plate_all[:, 1]) < 0.5
     plate = plate_all[~hole]
     channel = plate_all[hole]
