@@ -107,7 +107,7 @@ typedef struct sph_params {
 /* Per-context options. Zero-initialised options select the defaults. */
 typedef struct sph_options {
     int32_t dtype_bits;    /* 32 or 64 (0 = 32) */
-    int32_t block_sweep;   /* threads per block, neighbour sweeps: 64..1024, multiple of 64 (0 = 256) */
+    int32_t block_sweep;   /* threads per block, neighbour sweeps: 64, 128, 192 or 256 (0 = 256) */
     int32_t block_stream;  /* threads per block, per-particle kernels (0 = 256) */
     int32_t use_graph;     /* 1: sph_step replays captured hipGraphs; 0: plain launches; -1: default (1) */
     int32_t xcd_remap;     /* 1: map workgroups so each XCD sweeps one contiguous range; -1: default (1) */

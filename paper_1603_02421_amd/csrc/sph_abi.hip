@@ -138,7 +138,7 @@ sph_options resolve(const sph_options* o) {
 
 const char* check_options(const sph_options& o) {
     if (o.dtype_bits != 32 && o.dtype_bits != 64) return "dtype_bits must be 32 or 64";
-    if (o.block_sweep < 64 || o.block_sweep > 1024 || o.block_sweep % 64) return "block_sweep must be a multiple of 64 in [64, 1024]";
+    if (o.block_sweep < 64 || o.block_sweep > 256 || o.block_sweep % 64) return "block_sweep must be 64, 128, 192 or 256";
     if (o.block_stream < 64 || o.block_stream > 1024 || o.block_stream % 64) return "block_stream must be a multiple of 64 in [64, 1024]";
     return nullptr;
 }
@@ -249,6 +249,10 @@ struct Impl : sph_ctx_base {
         sb.tmp_src = cv.take<uint32_t>(n_);
         sb.tmp_id = cv.take<uint32_t>(n_);
         sb.cell = cv.take<uint32_t>(n_);
+        sb.sys_cell_base = cv.take<uint32_t>(n_sys_ + 1);
+        sb.sys_lo = cv.take<uint32_t>(n_sys_);
+        sb.sys_hi = cv.take<uint32_t>(n_sys_);
+        sb.chunk_base = cv.take<uint32_t>(n_sys_ + 1);
         dtmin = cv.take<unsigned long long>(2 * n_sys_);
         dt = cv.take<double>(n_sys_);
         time = cv.take<double>(n_sys_);
@@ -263,6 +267,10 @@ struct Impl : sph_ctx_base {
         v.n = n;
         v.xcd = L.xcd;
         v.do_dt = do_dt ? 1 : 0;
+        v.n_sys = n_sys;
+        v.sys_lo = sb.sys_lo;
+        v.sys_hi = sb.sys_hi;
+        v.chunk_base = sb.chunk_base;
         v.sys = sys;
         v.pos = half ? pos_h : S.pos;
         v.vel = half ? vel_h : S.vel;
@@ -640,6 +648,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     m->n = (int)c->n;
     m->n_sys = c->n_sys;
     m->L.n = m->n;
+    m->L.n_sys = m->n_sys;
     m->L.block_sweep = c->opt.block_sweep;
     m->L.block_stream = c->opt.block_stream;
     m->L.xcd = c->opt.xcd_remap;
@@ -676,6 +685,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     }
     StateBuf<T>& X = m->buf[0];
     HIP_OK(hipMemcpyAsync(m->sys, sd.data(), sizeof(SysDev<T>) * c->n_sys, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(m->sb.sys_cell_base, c->cell_base.data(), 4 * (c->n_sys + 1), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(X.pos, hp.data(), n * sizeof(double2), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(X.vel, hv.data(), n * sizeof(V2<T>), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(X.dens, hd.data(), n * sizeof(T), hipMemcpyHostToDevice, st));

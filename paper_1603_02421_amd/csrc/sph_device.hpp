@@ -77,7 +77,7 @@ template <> __device__ __forceinline__ float rcp<float>(float x) { return __buil
 template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
 
 template <typename T> __device__ __forceinline__ T sqrt_(T x);
-template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double sqrt_<double>(double x) { return __builtin_sqrt(x); }
 
 // Kernel value and gradient factor at distance r (< 2h): W(r) and F(r) with

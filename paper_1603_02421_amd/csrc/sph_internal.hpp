@@ -37,6 +37,10 @@ struct SortBufs {
     uint32_t* tmp_src;  // n: source slot of each destination slot
     uint32_t* tmp_id;   // n: particle id of each destination slot
     uint32_t* cell;     // n: cell key of each sorted slot
+    uint32_t* sys_cell_base;  // n_sys + 1: first cell of every system (last = trash)
+    uint32_t* sys_lo;         // n_sys: first sorted slot of every system
+    uint32_t* sys_hi;         // n_sys: one past its last active slot
+    uint32_t* chunk_base;     // n_sys + 1: first 64-slot wave chunk of every system
 };
 
 // What the three sweeps read and write.
@@ -45,7 +49,10 @@ struct EvalView {
     int n;
     int xcd;
     int do_dt;
-    int pad_;
+    int n_sys;
+    const uint32_t* sys_lo;
+    const uint32_t* sys_hi;
+    const uint32_t* chunk_base;
     const SysDev<T>* sys;
     const double2* pos;
     const V2<T>* vel;
@@ -86,6 +93,7 @@ struct IntegView {
 
 struct LaunchCfg {
     int n;
+    int n_sys;
     int block_sweep;
     int block_stream;
     int xcd;

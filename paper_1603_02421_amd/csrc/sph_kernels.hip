@@ -2,6 +2,8 @@
 // every per-particle sum is a gather over the slot ranges of the neighbouring
 // cells, so no floating-point atomics are used and results are bit-for-bit
 // reproducible run to run.
+#include <type_traits>
+
 #include "sph_internal.hpp"
 
 namespace sphjet {
@@ -170,10 +172,106 @@ __global__ void k_permute(int n, const uint32_t* tmp_src, const uint32_t* tmp_id
 }
 
 // ------------------------------------------------------------------ sweeps
-// Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that
-// passes the exact predicate |r_ab|^2 < (2h)^2, calling f(b, dx, dy, r2) with
-// r_ab = r_a - r_b in the working precision.
+// Work assignment: every wavefront owns up to 64 consecutive slots of a single
+// system (the wave table is rebuilt after every sort), so the system's
+// constants are wave-uniform and live in scalar registers.
 
+__global__ void __launch_bounds__(1024) k_wave_table(int n_sys, const uint32_t* cell_base, const uint32_t* cstart,
+                                                    uint32_t* sys_lo, uint32_t* sys_hi, uint32_t* chunk_base) {
+    int per = (n_sys + 1023) / 1024;
+    int s0 = (int)threadIdx.x * per, s1 = s0 + per < n_sys ? s0 + per : n_sys;
+    uint32_t sum = 0;
+    for (int s = s0; s < s1; ++s) {
+        uint32_t lo = cstart[cell_base[s]], hi = cstart[cell_base[s + 1]];
+        sys_lo[s] = lo;
+        sys_hi[s] = hi;
+        sum += (hi - lo + 63u) >> 6;
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(sum, &tot);
+    for (int s = s0; s < s1; ++s) {
+        chunk_base[s] = run;
+        run += (sys_hi[s] - sys_lo[s] + 63u) >> 6;
+    }
+    if (threadIdx.x == 0) chunk_base[n_sys] = tot;
+}
+
+// The system and slot of this lane; false (for the whole wave) when the wave
+// has no chunk. Slots past the end of the system are not valid.
+template <typename T>
+__device__ __forceinline__ bool wave_assign(const EvalView<T>& v, int& sys, uint32_t& a) {
+    const int wpb = (int)(blockDim.x >> 6);
+    const uint32_t wave = (uint32_t)(tile_index(v.xcd) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    const uint32_t total = v.chunk_base[v.n_sys];
+    if (wave >= total) return false;
+    int lo = 0, hi = v.n_sys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (v.chunk_base[mid] <= wave) lo = mid;
+        else hi = mid - 1;
+    }
+    sys = __builtin_amdgcn_readfirstlane(lo);
+    a = v.sys_lo[sys] + (wave - v.chunk_base[sys]) * 64u + (uint32_t)__lane_id();
+    return true;
+}
+
+// Minimum of non-negative values over the wave into dst (one system per wave).
+__device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double v, bool valid) {
+    double m = wave_min(valid ? v : __builtin_inf());
+    if (__lane_id() == 0 && m < __builtin_inf())
+        atomicMin(dst, (unsigned long long)__double_as_longlong(m));
+}
+
+// Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that
+// passes the exact predicate |r_ab|^2 < (2h)^2. Candidates are taken four at a
+// time: their positions are loaded together, then the per-neighbour payload of
+// the accepted ones (load(b)), then compute(b, dx, dy, payload) with
+// r_ab = r_a - r_b in the working precision. Slot ranges come straight from
+// the cell starts: with the y index fastest, each cell row is one range.
+template <typename T, typename LoadFn, typename ComputeFn>
+__device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
+                                           uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
+                                           ComputeFn&& compute) {
+    using P = typename std::decay<decltype(load(0u))>::type;
+    const uint32_t ny = (uint32_t)S.ny;
+    const uint32_t local = cell - S.cell_base;
+    const int cx = (int)(local / ny);
+    const int cy = (int)(local - (uint32_t)cx * ny);
+    const int R = S.reach;
+    const int ylo = cy - R < 0 ? 0 : cy - R;
+    const int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
+    const int xlo = cx - R < 0 ? 0 : cx - R;
+    const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
+    const double R2 = S.R2;
+    for (int X = xlo; X <= xhi; ++X) {
+        const uint32_t row = S.cell_base + (uint32_t)X * ny;
+        const uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
+        for (uint32_t b = b0; b < b1; b += 4) {
+            double2 q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = pos[b + k < b1 ? b + k : b1 - 1];
+            bool ok[4];
+            T dx[4], dy[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double ex, ey;
+                double r2 = pair_r2(pa, q[k], ex, ey);
+                ok[k] = (b + k < b1) && (b + k != a) && (r2 < R2);
+                dx[k] = (T)ex;
+                dy[k] = (T)ey;
+            }
+            P pl[4] = {};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (ok[k]) pl[k] = load(b + k);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (ok[k]) compute(b + k, dx[k], dy[k], pl[k]);
+        }
+    }
+}
+
+// Reference-style visitor, one candidate at a time (debug neighbour lists).
 template <typename T, typename Fn>
 __device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_t* cstart, uint32_t cell,
                                                int a, double2 pa, const double2* pos, Fn&& f) {
@@ -197,135 +295,143 @@ __device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_
     }
 }
 
+template <typename T> struct Pay1 { T mass, dens; };
+template <typename T> struct Pay2 { V2<T> vel; T dens, mass, col; uint32_t tag; };
+template <typename T> struct Pay3 { V2<T> nrm; T mass, dens; };
+
 // Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included (eq. 14).
 template <typename T>
-__global__ void k_colour(EvalView<T> v) {
-    int a = tile_index(v.xcd) * blockDim.x + threadIdx.x;
-    if (a >= v.n) return;
-    uint32_t t = v.tag[a];
-    if (tag_type(t) == T_INACTIVE) return;
-    const SysDev<T>& S = v.sys[tag_sys(t)];
-    double2 pa = v.pos[a];
-    T sum = v.mass[a] * rcp(S.rho0 + v.dens[a]) * S.W0;
-    for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
-        T r = sqrt_(dx * dx + dy * dy);
-        sum += v.mass[b] * rcp(S.rho0 + v.dens[b]) * kernel_w(S, r);
-    });
+__global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
+    int sys;
+    uint32_t a;
+    if (!wave_assign(v, sys, a)) return;
+    const SysDev<T>& S = v.sys[sys];
+    if (a >= v.sys_hi[sys]) return;
+    const T rho0 = S.rho0;
+    const double2 pa = v.pos[a];
+    T sum = v.mass[a] * rcp(rho0 + v.dens[a]) * S.W0;
+    scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
+        [&](uint32_t b) { return Pay1<T>{v.mass[b], v.dens[b]}; },
+        [&](uint32_t, T dx, T dy, const Pay1<T>& p) {
+            T r = sqrt_(dx * dx + dy * dy);
+            sum += p.mass * rcp(rho0 + p.dens) * kernel_w(S, r);
+        });
     v.colour[a] = sum;
 }
 
 // Sweep 2: continuity (eq. 7) for every active particle (a boundary particle
-// sums over fluid neighbours only); for fluid particles
-// also the pressure + artificial-viscosity acceleration (eq. 9-10) and the
-// interface normal n_a = sum_b (m_b/rho_b)(C_b - C_a) grad_a W_ab (eq. 18);
-// the signal term max_b |h v_ab . r_ab| / r_ab^2 feeds the eq. 31 limit.
+// sums over fluid neighbours only); for fluid particles also the pressure +
+// artificial-viscosity acceleration (eq. 9-10) and the interface normal
+// n_a = sum_b (m_b/rho_b)(C_b - C_a) grad_a W_ab (eq. 18); the signal term
+// max_b |h v_ab . r_ab| / r_ab^2 feeds the eq. 31 limit.
 template <typename T>
-__global__ void k_main(EvalView<T> v) {
-    int a = tile_index(v.xcd) * blockDim.x + threadIdx.x;
-    bool valid = a < v.n;
-    uint32_t t = valid ? v.tag[a] : (uint32_t)T_INACTIVE;
-    valid = valid && tag_type(t) != T_INACTIVE;
-    int sys = (int)tag_sys(t);
+__global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
+    int sys;
+    uint32_t a;
+    if (!wave_assign(v, sys, a)) return;
+    const SysDev<T>& S = v.sys[sys];
+    const bool valid = a < v.sys_hi[sys];
     double dtcv = __builtin_inf();
     if (valid) {
-        const SysDev<T>& S = v.sys[sys];
-        const bool fluid = tag_type(t) == T_FLUID;
-        double2 pa = v.pos[a];
-        V2<T> va = v.vel[a];
+        const bool fluid = tag_type(v.tag[a]) == T_FLUID;
+        const double2 pa = v.pos[a];
+        const V2<T> va = v.vel[a];
         T rho_a, pr_a, c_a;
         tait(S, v.dens[a], rho_a, pr_a, c_a);
-        T Ca = v.colour[a];
+        const T Ca = v.colour[a];
+        const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, vsig = 0;
-        if (fluid) {
-            for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
+        scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
+            [&](uint32_t b) {
+                Pay2<T> p;
+                p.vel = v.vel[b];
+                p.dens = v.dens[b];
+                p.mass = v.mass[b];
+                p.col = fluid ? v.colour[b] : T(0);
+                p.tag = fluid ? 0u : v.tag[b];
+                return p;
+            },
+            [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
+                if (!fluid && tag_type(p.tag) != T_FLUID) return;
                 T r2 = dx * dx + dy * dy;
                 T r = sqrt_(r2);
                 T F = kernel_f(S, r);
-                V2<T> vb = v.vel[b];
-                T ux = va.x - vb.x, uy = va.y - vb.y;
+                T ux = va.x - p.vel.x, uy = va.y - p.vel.y;
                 T vr = ux * dx + uy * dy;
-                T mb = v.mass[b];
-                drho += mb * F * vr;
-                T sg = fabs(S.h * vr * rcp(r2));
+                drho += p.mass * F * vr;
+                T sg = fabs(h * vr * rcp(r2));
                 vsig = sg > vsig ? sg : vsig;
-                T rho_b, pr_b, c_b;
-                tait(S, v.dens[b], rho_b, pr_b, c_b);
-                T pi = 0;
-                if (vr < T(0)) {
-                    T cbar = T(0.5) * (c_a + c_b);
-                    T rbar = T(0.5) * (rho_a + rho_b);
-                    pi = -S.alpha_h * cbar * vr * rcp(rbar * (r2 + S.eta2));
+                if (fluid) {
+                    T rho_b, pr_b, c_b;
+                    tait(S, p.dens, rho_b, pr_b, c_b);
+                    T pi = 0;
+                    if (vr < T(0)) {
+                        T cbar = T(0.5) * (c_a + c_b);
+                        T rbar = T(0.5) * (rho_a + rho_b);
+                        pi = -alpha_h * cbar * vr * rcp(rbar * (r2 + eta2));
+                    }
+                    T coef = p.mass * (pr_a + pr_b + pi) * F;
+                    ax -= coef * dx;
+                    ay -= coef * dy;
+                    T cn = p.mass * rcp(rho_b) * (p.col - Ca) * F;
+                    nx += cn * dx;
+                    ny += cn * dy;
                 }
-                T coef = mb * (pr_a + pr_b + pi) * F;
-                ax -= coef * dx;
-                ay -= coef * dy;
-                T cn = mb * rcp(rho_b) * (v.colour[b] - Ca) * F;
-                nx += cn * dx;
-                ny += cn * dy;
             });
-        } else {
-            // a boundary particle's density responds to fluid neighbours only
-            for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
-                if (tag_type(v.tag[b]) != T_FLUID) return;
-                T r2 = dx * dx + dy * dy;
-                T F = kernel_f(S, sqrt_(r2));
-                V2<T> vb = v.vel[b];
-                T vr = (va.x - vb.x) * dx + (va.y - vb.y) * dy;
-                drho += v.mass[b] * F * vr;
-                T sg = fabs(S.h * vr * rcp(r2));
-                vsig = sg > vsig ? sg : vsig;
-            });
-        }
         v.drho[a] = drho;
         V2<T> acc, nrm;
-        acc.x = ax; acc.y = ay;
-        nrm.x = nx; nrm.y = ny;
+        acc.x = ax;
+        acc.y = ay;
+        nrm.x = nx;
+        nrm.y = ny;
         v.acc[a] = acc;
         v.nrm[a] = nrm;
-        dtcv = (double)(S.h / (c_a + vsig));
+        dtcv = (double)(h / (c_a + vsig));
     }
-    if (v.do_dt) atomic_min_per_system(v.dtmin, 2, sys, dtcv, valid);
+    if (v.do_dt) wave_atomic_min(v.dtmin + 2 * sys, dtcv, valid);
 }
 
 // Sweep 3 (fluid only): normal filter N_a = [|n_a| > eps] (eq. 20-21),
 // curvature kappa_a = sum_b min(N_a,N_b)(m_b/rho_b)(nh_b - nh_a).grad_a W_ab /
 // sum_b min(N_a,N_b)(m_b/rho_b) W_ab (eq. 23, self in the denominator),
 // surface-tension acceleration -(sigma/rho_a) kappa_a n_a (eq. 24) and the
-// total acceleration (eq. 25); |a| feeds the eq. 30 limit.
+// total acceleration (eq. 25); |a| feeds the eq. 30 limit. Boundary particles
+// carry n = 0, so they fail the filter and drop out of both sums.
 template <typename T>
-__global__ void k_surface(EvalView<T> v) {
-    int a = tile_index(v.xcd) * blockDim.x + threadIdx.x;
-    bool valid = a < v.n;
-    uint32_t t = valid ? v.tag[a] : (uint32_t)T_INACTIVE;
-    valid = valid && tag_type(t) == T_FLUID;
-    int sys = (int)tag_sys(t);
+__global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
+    int sys;
+    uint32_t a;
+    if (!wave_assign(v, sys, a)) return;
+    const SysDev<T>& S = v.sys[sys];
+    const bool valid = a < v.sys_hi[sys] && tag_type(v.tag[a]) == T_FLUID;
     double dtf = __builtin_inf();
     if (valid) {
-        const SysDev<T>& S = v.sys[sys];
-        V2<T> n_a = v.nrm[a];
-        T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
+        const T eps = S.eps, rho0 = S.rho0;
+        const V2<T> n_a = v.nrm[a];
+        const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
         V2<T> acc = v.acc[a];
         T kappa = 0;
-        T rho_a = S.rho0 + v.dens[a];
-        if (mag > S.eps) {
-            T im = rcp(mag);
-            T hx = n_a.x * im, hy = n_a.y * im;
+        const T rho_a = rho0 + v.dens[a];
+        if (mag > eps) {
+            const T im = rcp(mag);
+            const T hx = n_a.x * im, hy = n_a.y * im;
             T num = 0;
             T den = v.mass[a] * rcp(rho_a) * S.W0;
-            double2 pa = v.pos[a];
-            for_neighbours<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](int b, T dx, T dy) {
-                V2<T> n_b = v.nrm[b];
-                T mb = sqrt_(n_b.x * n_b.x + n_b.y * n_b.y);
-                if (mb > S.eps) {
-                    T ib = rcp(mb);
-                    T r = sqrt_(dx * dx + dy * dy);
-                    T W, F;
-                    kernel_wf(S, r, W, F);
-                    T vol = v.mass[b] * rcp(S.rho0 + v.dens[b]);
-                    num += vol * F * ((n_b.x * ib - hx) * dx + (n_b.y * ib - hy) * dy);
-                    den += vol * W;
-                }
-            });
+            const double2 pa = v.pos[a];
+            scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
+                [&](uint32_t b) { return Pay3<T>{v.nrm[b], v.mass[b], v.dens[b]}; },
+                [&](uint32_t, T dx, T dy, const Pay3<T>& p) {
+                    T mb = sqrt_(p.nrm.x * p.nrm.x + p.nrm.y * p.nrm.y);
+                    if (mb > eps) {
+                        T ib = rcp(mb);
+                        T r = sqrt_(dx * dx + dy * dy);
+                        T W, F;
+                        kernel_wf(S, r, W, F);
+                        T vol = p.mass * rcp(rho0 + p.dens);
+                        num += vol * F * ((p.nrm.x * ib - hx) * dx + (p.nrm.y * ib - hy) * dy);
+                        den += vol * W;
+                    }
+                });
             kappa = num / den;
         }
         v.kappa_plain[a] = kappa;
@@ -337,7 +443,7 @@ __global__ void k_surface(EvalView<T> v) {
         T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
         if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
     }
-    if (v.do_dt) atomic_min_per_system(v.dtmin, 2, sys, dtf, valid);
+    if (v.do_dt) wave_atomic_min(v.dtmin + 2 * sys + 1, dtf, valid);
 }
 
 // ------------------------------------------------------------------ time step
@@ -553,12 +659,16 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     kt->begin("sort_permute", st);
     k_permute<T><<<nb, bs, 0, st>>>(n, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell);
     kt->end(st);
+    kt->begin("wave_table", st);
+    k_wave_table<<<1, 1024, 0, st>>>(L.n_sys, B.sys_cell_base, B.cstart, B.sys_lo, B.sys_hi, B.chunk_base);
+    kt->end(st);
 }
 
 template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt) {
     const int bs = L.block_sweep;
-    const unsigned nb = nblk(L.n, bs);
+    const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
+    const unsigned nb = nblk(max_waves, bs / 64);
     kt->begin("colour", st);
     k_colour<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
