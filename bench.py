@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block-sweep", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
+    ap.add_argument("--cell-factor", type=float, default=0.0,
+                    help="override every system's cell size as this multiple of h")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -122,6 +124,10 @@ def main():
     import paper_1603_02421_amd as sph
 
     batch, desc, bits = make_workload(args.workload)
+    if args.cell_factor > 0:
+        for sy in batch.systems:
+            sy.params["cell_size"] = args.cell_factor * sy.params["h"]
+        desc += f", cell size {args.cell_factor} h"
     print(f"[bench] workload {args.workload}: {desc}; n={batch.n}", flush=True)
     t0 = time.perf_counter()
     sim = sph.Simulation(batch, dtype_bits=bits, block_sweep=args.block_sweep, xcd_remap=args.xcd)

@@ -196,6 +196,10 @@ struct Impl : sph_ctx_base {
     V2<T>* vel_h = nullptr;
     T* dens_h = nullptr;
     T *colour = nullptr, *drho = nullptr, *kappa = nullptr, *kappa_plain = nullptr, *aux = nullptr;
+    T* vol = nullptr;
+    V4<T>* eos = nullptr;
+    unsigned long long* nmask0 = nullptr;
+    unsigned long long* nmask1 = nullptr;
     V2<T>* acc = nullptr;
     V2<T>* nrm = nullptr;
     SortBufs sb{};
@@ -238,6 +242,10 @@ struct Impl : sph_ctx_base {
         kappa = cv.take<T>(n_);
         kappa_plain = cv.take<T>(n_);
         aux = cv.take<T>(n_ < 2 ? 2 : n_);
+        vol = cv.take<T>(n_);
+        eos = cv.take<V4<T>>(n_);
+        nmask0 = cv.take<unsigned long long>(n_);
+        nmask1 = cv.take<unsigned long long>(n_);
         int64_t nb = (n_ + block_stream - 1) / block_stream;
         sb.trash = trash;
         sb.cstart = cv.take<uint32_t>((size_t)trash + 2);
@@ -287,6 +295,10 @@ struct Impl : sph_ctx_base {
         v.kappa = kappa;
         v.kappa_plain = kappa_plain;
         v.dtmin = dtmin;
+        v.vol = vol;
+        v.eos = eos;
+        v.nmask0 = nmask0;
+        v.nmask1 = nmask1;
         return v;
     }
 
@@ -307,12 +319,15 @@ struct Impl : sph_ctx_base {
         v.dt = dt;
         v.time = time;
         v.flags = flags;
+        v.mass = S.mass;
+        v.vol = vol;
+        v.eos = eos;
         return v;
     }
 
     // Sort the current buffer into the other one; the other becomes current.
     void sort(hipStream_t st, KernelTimer* kt) {
-        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], st, kt);
+        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], vol, eos, st, kt);
         cur ^= 1;
     }
 

@@ -25,6 +25,17 @@ template <typename T> struct V2t;
 template <> struct V2t<float> { using type = float2; };
 template <> struct V2t<double> { using type = double2; };
 template <typename T> using V2 = typename V2t<T>::type;
+template <typename T> struct V4t;
+template <> struct V4t<float> { using type = float4; };
+template <> struct V4t<double> { using type = double4; };
+template <typename T> using V4 = typename V4t<T>::type;
+
+// The colour sweep records which of a particle's candidates (the slots of its
+// neighbouring cells, numbered row by row) passed the pair predicate, as a
+// 128-bit mask. Bit 127 marks a particle with more than 127 candidates; the
+// later sweeps then scan its cells again instead of reading the mask.
+constexpr uint32_t MASK_BITS = 127;
+constexpr unsigned long long MASK_OVERFLOW = 1ull << 63;
 
 // Per-system constants, precomputed on the host.
 template <typename T>
@@ -145,6 +156,19 @@ __device__ __forceinline__ void tait(const SysDev<T>& S, T dens, T& rho, T& p_ov
     }
     p_over_rho2 = P * irho * irho;
     c = S.c0 * cr;
+}
+
+// Per-particle quantities every neighbour sum needs, computed once per
+// evaluation: vol = m / rho and eos = (P / rho^2, c, rho, m).
+template <typename T>
+__device__ __forceinline__ void particle_props(const SysDev<T>& S, T dens, T mass, T& vol, V4<T>& eos) {
+    T rho, pr, c;
+    tait(S, dens, rho, pr, c);
+    vol = mass * rcp(rho);
+    eos.x = pr;
+    eos.y = c;
+    eos.z = rho;
+    eos.w = mass;
 }
 
 template <typename T>

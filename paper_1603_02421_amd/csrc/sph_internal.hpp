@@ -69,6 +69,10 @@ struct EvalView {
     T* kappa;
     T* kappa_plain;
     unsigned long long* dtmin;  // 2 per system: [h/(c+sig) min, sqrt(h/|a|) min]
+    const T* vol;               // m / rho of every slot (this evaluation's state)
+    const V4<T>* eos;           // (P / rho^2, c, rho, m)
+    unsigned long long* nmask0;  // n: neighbour mask, candidates 0..63
+    unsigned long long* nmask1;  // n: candidates 64..126 (+ overflow bit)
 };
 
 // What the predictor and corrector read and write.
@@ -81,6 +85,7 @@ struct IntegView {
     V2<T>* vel;
     T* dens;
     uint32_t* tag;
+    const T* mass;
     const T* drho;         // derivatives of the last evaluation
     const V2<T>* acc;
     double2* pos_h;        // half-step state (predictor output)
@@ -89,6 +94,8 @@ struct IntegView {
     const double* dt;
     const double* time;
     uint32_t* flags;
+    T* vol;                // per-particle quantities of the half-step state
+    V4<T>* eos;
 };
 
 struct LaunchCfg {
@@ -128,7 +135,7 @@ void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st);
 
 template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
-                 hipStream_t st, KernelTimer* kt);
+                 T* vol, V4<T>* eos, hipStream_t st, KernelTimer* kt);
 template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt);
 template <typename T>

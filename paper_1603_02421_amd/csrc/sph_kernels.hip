@@ -102,22 +102,42 @@ __global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uin
                       uint32_t* key, uint32_t* slot, uint32_t* counts, uint32_t trash,
                       uint32_t* blk_inactive) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool inactive = false;
+    bool inactive = false, act = false;
+    uint32_t k = trash;
     if (i < n) {
         uint32_t t = tag[i];
-        uint32_t k = trash, sl = 0;
         if (tag_type(t) != T_INACTIVE) {
             const SysDev<T>& S = sys[tag_sys(t)];
             double2 p = pos[i];
             int cx = cell_coord(p.x, S.x0, S.inv_s, S.nx);
             int cy = cell_coord(p.y, S.y0, S.inv_s, S.ny);
             k = S.cell_base + (uint32_t)cx * (uint32_t)S.ny + (uint32_t)cy;
-            sl = atomicAdd(&counts[k], 1u);
+            act = true;
         } else {
             inactive = true;
         }
+    }
+    // One atomic per run of consecutive lanes with the same key: the head of
+    // the run reserves the run's slots, members take consecutive ones.
+    const int lane = __lane_id();
+    const uint32_t kk = act ? k : 0xFFFFFFFFu;
+    const uint32_t prev = __shfl_up(kk, 1, 64);
+    const bool head = act && (lane == 0 || prev != kk);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long actm = __ballot(act);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const unsigned long long hm = heads & upto;
+    const int hlane = hm ? 63 - __clzll((long long)hm) : lane;
+    uint32_t base = 0;
+    if (head) {
+        const unsigned long long brk = (heads | ~actm) & (lane == 63 ? 0ull : (~0ull << (lane + 1)));
+        const int next = brk ? __ffsll((long long)brk) - 1 : 64;
+        base = atomicAdd(&counts[k], (uint32_t)(next - lane));
+    }
+    base = __shfl(base, hlane, 64);
+    if (i < n) {
         key[i] = k;
-        slot[i] = sl;
+        slot[i] = act ? base + (uint32_t)(lane - hlane) : 0u;
     }
     int c = __syncthreads_count(inactive);
     if (threadIdx.x == 0) blk_inactive[blockIdx.x] = (uint32_t)c;
@@ -156,19 +176,30 @@ __global__ void k_cellsort(uint32_t ncells, const uint32_t* cstart, uint32_t* tm
     }
 }
 
+// Gather the state into cell order; also the per-particle quantities of the
+// first evaluation of the step.
 template <typename T>
-__global__ void k_permute(int n, const uint32_t* tmp_src, const uint32_t* tmp_id, const uint32_t* key,
-                          StateBuf<T> X, StateBuf<T> Y, uint32_t* cell) {
+__global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* tmp_src, const uint32_t* tmp_id,
+                          const uint32_t* key, StateBuf<T> X, StateBuf<T> Y, uint32_t* cell, T* vol, V4<T>* eos) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     uint32_t s = tmp_src[j];
+    T dens = X.dens[s], mass = X.mass[s];
+    uint32_t t = X.tag[s];
     Y.pos[j] = X.pos[s];
     Y.vel[j] = X.vel[s];
-    Y.dens[j] = X.dens[s];
-    Y.mass[j] = X.mass[s];
-    Y.tag[j] = X.tag[s];
+    Y.dens[j] = dens;
+    Y.mass[j] = mass;
+    Y.tag[j] = t;
     Y.id[j] = tmp_id[j];
     cell[j] = key[s];
+    if (tag_type(t) != T_INACTIVE) {
+        T vl;
+        V4<T> e;
+        particle_props(sys[tag_sys(t)], dens, mass, vl, e);
+        vol[j] = vl;
+        eos[j] = e;
+    }
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -229,9 +260,9 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 // r_ab = r_a - r_b in the working precision. Slot ranges come straight from
 // the cell starts: with the y index fastest, each cell row is one range.
 template <typename T, typename LoadFn, typename ComputeFn>
-__device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
-                                           uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
-                                           ComputeFn&& compute) {
+__device__ __forceinline__ void scan_cells_ord(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
+                                               uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
+                                               ComputeFn&& compute) {
     using P = typename std::decay<decltype(load(0u))>::type;
     const uint32_t ny = (uint32_t)S.ny;
     const uint32_t local = cell - S.cell_base;
@@ -243,6 +274,7 @@ __device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* _
     const int xlo = cx - R < 0 ? 0 : cx - R;
     const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
     const double R2 = S.R2;
+    uint32_t ord0 = 0;   // ordinal of the first candidate of the row
     for (int X = xlo; X <= xhi; ++X) {
         const uint32_t row = S.cell_base + (uint32_t)X * ny;
         const uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
@@ -266,9 +298,18 @@ __device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* _
                 if (ok[k]) pl[k] = load(b + k);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (ok[k]) compute(b + k, dx[k], dy[k], pl[k]);
+                if (ok[k]) compute(b + k, ord0 + (b + k - b0), dx[k], dy[k], pl[k]);
         }
+        ord0 += b1 - b0;
     }
+}
+
+template <typename T, typename LoadFn, typename ComputeFn>
+__device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
+                                           uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
+                                           ComputeFn&& compute) {
+    scan_cells_ord<T>(S, cstart, cell, a, pa, pos, load,
+                      [&](uint32_t b, uint32_t, T dx, T dy, const auto& p) { compute(b, dx, dy, p); });
 }
 
 // Reference-style visitor, one candidate at a time (debug neighbour lists).
@@ -295,11 +336,92 @@ __device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_
     }
 }
 
-template <typename T> struct Pay1 { T mass, dens; };
-template <typename T> struct Pay2 { V2<T> vel; T dens, mass, col; uint32_t tag; };
-template <typename T> struct Pay3 { V2<T> nrm; T mass, dens; };
+// Visit the neighbours recorded in slot a's candidate mask, four at a time
+// (positions and payloads, then compute). A mask bit is a candidate ordinal;
+// the row ranges of the cell block turn it back into a slot. r_ab = r_a - r_b
+// is formed in FP64 exactly as in the scan.
+template <typename T, typename LoadFn, typename ComputeFn>
+__device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
+                                                unsigned long long m0, unsigned long long m1, LoadFn&& load,
+                                                ComputeFn&& compute) {
+    using P = typename std::decay<decltype(load(0u))>::type;
+    const uint32_t ny = (uint32_t)S.ny;
+    const uint32_t local = v.cell[a] - S.cell_base;
+    const int cx = (int)(local / ny);
+    const int cy = (int)(local - (uint32_t)cx * ny);
+    const int R = S.reach;
+    const int ylo = cy - R < 0 ? 0 : cy - R;
+    const int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
+    const int xlo = cx - R < 0 ? 0 : cx - R;
+    const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
+    // slot = ordinal + shift[row], rows ending at ordinal end[row]
+    uint32_t shift[5], end[4];
+    uint32_t ord0 = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const int X = xlo + r;
+        uint32_t b0 = 0, len = 0;
+        if (X <= xhi) {
+            const uint32_t row = S.cell_base + (uint32_t)X * ny;
+            b0 = v.cstart[row + ylo];
+            len = v.cstart[row + yhi + 1] - b0;
+        }
+        shift[r] = b0 - ord0;
+        ord0 += len;
+        if (r < 4) end[r] = X <= xhi ? ord0 : 0xFFFFFFFFu;
+    }
+    while (m0 | m1) {
+        uint32_t bb[4];
+        bool ok[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t o = 0;
+            ok[j] = (m0 | m1) != 0ull;
+            if (m0) {
+                o = (uint32_t)__ffsll((long long)m0) - 1u;
+                m0 &= m0 - 1ull;
+            } else if (m1) {
+                o = 64u + (uint32_t)__ffsll((long long)m1) - 1u;
+                m1 &= m1 - 1ull;
+            }
+            uint32_t sh = o < end[0] ? shift[0] : o < end[1] ? shift[1] : o < end[2] ? shift[2]
+                        : o < end[3] ? shift[3] : shift[4];
+            bb[j] = ok[j] ? o + sh : a;
+        }
+        double2 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = v.pos[bb[j]];
+        P pl[4] = {};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ok[j]) pl[j] = load(bb[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (ok[j]) {
+                double ex, ey;
+                pair_r2(pa, q[j], ex, ey);
+                compute(bb[j], (T)ex, (T)ey, pl[j]);
+            }
+        }
+    }
+}
 
-// Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included (eq. 14).
+// The neighbours of slot a: from its mask, or by scanning its cells when it
+// had more candidates than the mask holds.
+template <typename T, typename LoadFn, typename ComputeFn>
+__device__ __forceinline__ void neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
+                                           LoadFn&& load, ComputeFn&& compute) {
+    const unsigned long long m0 = v.nmask0[a], m1 = v.nmask1[a];
+    if (!(m1 & MASK_OVERFLOW)) mask_neighbours<T>(v, S, a, pa, m0, m1, load, compute);
+    else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute);
+}
+
+template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; T col; uint32_t tag; };
+template <typename T> struct Pay3 { V2<T> nrm; T vol; };
+
+// Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included
+// (eq. 14). The cell scan of this sweep also records which candidates passed
+// the pair predicate, for the two sweeps that follow.
 template <typename T>
 __global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
     int sys;
@@ -307,16 +429,22 @@ __global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
     if (!wave_assign(v, sys, a)) return;
     const SysDev<T>& S = v.sys[sys];
     if (a >= v.sys_hi[sys]) return;
-    const T rho0 = S.rho0;
     const double2 pa = v.pos[a];
-    T sum = v.mass[a] * rcp(rho0 + v.dens[a]) * S.W0;
-    scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
-        [&](uint32_t b) { return Pay1<T>{v.mass[b], v.dens[b]}; },
-        [&](uint32_t, T dx, T dy, const Pay1<T>& p) {
+    T sum = v.vol[a] * S.W0;
+    unsigned long long m0 = 0, m1 = 0;
+    bool overflow = false;
+    scan_cells_ord<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
+        [&](uint32_t b) { return v.vol[b]; },
+        [&](uint32_t, uint32_t ord, T dx, T dy, T vol_b) {
             T r = sqrt_(dx * dx + dy * dy);
-            sum += p.mass * rcp(rho0 + p.dens) * kernel_w(S, r);
+            sum += vol_b * kernel_w(S, r);
+            if (ord < 64u) m0 |= 1ull << ord;
+            else if (ord < MASK_BITS) m1 |= 1ull << (ord - 64u);
+            else overflow = true;
         });
     v.colour[a] = sum;
+    v.nmask0[a] = m0;
+    v.nmask1[a] = overflow ? (m1 | MASK_OVERFLOW) : m1;
 }
 
 // Sweep 2: continuity (eq. 7) for every active particle (a boundary particle
@@ -336,44 +464,42 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
         const bool fluid = tag_type(v.tag[a]) == T_FLUID;
         const double2 pa = v.pos[a];
         const V2<T> va = v.vel[a];
-        T rho_a, pr_a, c_a;
-        tait(S, v.dens[a], rho_a, pr_a, c_a);
+        const V4<T> ea = v.eos[a];
+        const T pr_a = ea.x, c_a = ea.y, rho_a = ea.z;
         const T Ca = v.colour[a];
         const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, vsig = 0;
-        scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
+        neighbours<T>(v, S, a, pa,
             [&](uint32_t b) {
                 Pay2<T> p;
                 p.vel = v.vel[b];
-                p.dens = v.dens[b];
-                p.mass = v.mass[b];
+                p.eos = v.eos[b];
                 p.col = fluid ? v.colour[b] : T(0);
                 p.tag = fluid ? 0u : v.tag[b];
                 return p;
             },
             [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
                 if (!fluid && tag_type(p.tag) != T_FLUID) return;
+                const T pr_b = p.eos.x, c_b = p.eos.y, rho_b = p.eos.z, m_b = p.eos.w;
                 T r2 = dx * dx + dy * dy;
-                T r = sqrt_(r2);
-                T F = kernel_f(S, r);
+                T F = kernel_f(S, sqrt_(r2));
                 T ux = va.x - p.vel.x, uy = va.y - p.vel.y;
                 T vr = ux * dx + uy * dy;
-                drho += p.mass * F * vr;
-                T sg = fabs(h * vr * rcp(r2));
+                drho += m_b * F * vr;
+                T ir2 = rcp(r2);
+                T sg = fabs(h * vr * ir2);
                 vsig = sg > vsig ? sg : vsig;
                 if (fluid) {
-                    T rho_b, pr_b, c_b;
-                    tait(S, p.dens, rho_b, pr_b, c_b);
                     T pi = 0;
                     if (vr < T(0)) {
                         T cbar = T(0.5) * (c_a + c_b);
                         T rbar = T(0.5) * (rho_a + rho_b);
                         pi = -alpha_h * cbar * vr * rcp(rbar * (r2 + eta2));
                     }
-                    T coef = p.mass * (pr_a + pr_b + pi) * F;
+                    T coef = m_b * (pr_a + pr_b + pi) * F;
                     ax -= coef * dx;
                     ay -= coef * dy;
-                    T cn = p.mass * rcp(rho_b) * (p.col - Ca) * F;
+                    T cn = m_b * rcp(rho_b) * (p.col - Ca) * F;
                     nx += cn * dx;
                     ny += cn * dy;
                 }
@@ -406,20 +532,20 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
     const bool valid = a < v.sys_hi[sys] && tag_type(v.tag[a]) == T_FLUID;
     double dtf = __builtin_inf();
     if (valid) {
-        const T eps = S.eps, rho0 = S.rho0;
+        const T eps = S.eps;
         const V2<T> n_a = v.nrm[a];
         const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
         V2<T> acc = v.acc[a];
         T kappa = 0;
-        const T rho_a = rho0 + v.dens[a];
+        const T rho_a = v.eos[a].z;
         if (mag > eps) {
             const T im = rcp(mag);
             const T hx = n_a.x * im, hy = n_a.y * im;
             T num = 0;
-            T den = v.mass[a] * rcp(rho_a) * S.W0;
+            T den = v.vol[a] * S.W0;
             const double2 pa = v.pos[a];
-            scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
-                [&](uint32_t b) { return Pay3<T>{v.nrm[b], v.mass[b], v.dens[b]}; },
+            neighbours<T>(v, S, a, pa,
+                [&](uint32_t b) { return Pay3<T>{v.nrm[b], v.vol[b]}; },
                 [&](uint32_t, T dx, T dy, const Pay3<T>& p) {
                     T mb = sqrt_(p.nrm.x * p.nrm.x + p.nrm.y * p.nrm.y);
                     if (mb > eps) {
@@ -427,9 +553,8 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
                         T r = sqrt_(dx * dx + dy * dy);
                         T W, F;
                         kernel_wf(S, r, W, F);
-                        T vol = p.mass * rcp(rho0 + p.dens);
-                        num += vol * F * ((p.nrm.x * ib - hx) * dx + (p.nrm.y * ib - hy) * dy);
-                        den += vol * W;
+                        num += p.vol * F * ((p.nrm.x * ib - hx) * dx + (p.nrm.y * ib - hy) * dy);
+                        den += p.vol * W;
                     }
                 });
             kappa = num / den;
@@ -488,6 +613,13 @@ __global__ void k_predict(IntegView<T> v) {
     T dh = v.dens[a] + hdt * v.drho[a];
     if (ty != T_FLUID && dh < T(0)) dh = T(0);   // boundaries never below rho0: they only repel
     v.dens_h[a] = dh;
+    {
+        T vl;
+        V4<T> e;
+        particle_props(S, dh, v.mass[a], vl, e);
+        v.vol[a] = vl;
+        v.eos[a] = e;
+    }
     if (ty == T_FLUID) {
         V2<T> acc = v.acc[a];
         double2 q;
@@ -637,7 +769,7 @@ void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st) {
 
 template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
-                 hipStream_t st, KernelTimer* kt) {
+                 T* vol, V4<T>* eos, hipStream_t st, KernelTimer* kt) {
     const int n = L.n;
     const int bs = L.block_stream;
     const uint32_t trash = B.trash;
@@ -657,7 +789,7 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     k_cellsort<<<nblk(trash, 256), 256, 0, st>>>(trash, B.cstart, B.tmp_src, B.tmp_id);
     kt->end(st);
     kt->begin("sort_permute", st);
-    k_permute<T><<<nb, bs, 0, st>>>(n, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell);
+    k_permute<T><<<nb, bs, 0, st>>>(n, sys, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell, vol, eos);
     kt->end(st);
     kt->begin("wave_table", st);
     k_wave_table<<<1, 1024, 0, st>>>(L.n_sys, B.sys_cell_base, B.cstart, B.sys_lo, B.sys_hi, B.chunk_base);
@@ -724,7 +856,7 @@ void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* 
 
 #define SPHJET_INSTANTIATE(T)                                                                               \
     template void launch_sort<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,        \
-                                 StateBuf<T>, hipStream_t, KernelTimer*);                                  \
+                                 StateBuf<T>, T*, V4<T>*, hipStream_t, KernelTimer*);                      \
     template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t, KernelTimer*);         \
     template void launch_dt<T>(int, const SysDev<T>*, unsigned long long*, double*, hipStream_t,           \
                                KernelTimer*);                                                              \

@@ -58,8 +58,20 @@ def _cases():
     walls_only.type[:] = wl.WALL
     overlap = wl.lattice_block(10, 10)
     overlap.pos[5] = overlap.pos[6]          # two particles on the same spot
+    # 5 x 5 cell blocks (cell size 1.1 h): the candidate mask spans five cell rows
+    jet_reach2 = wl.jet(n_target=12_000, nD=12, Re=400, We=15, seed=2, free_length=8.0, prefill=4.0)
+    jet_reach2.params["cell_size"] = 1.1 * jet_reach2.params["h"]
+    # a dense clump inside a lattice: its particles exceed the 127-candidate mask
+    # and fall back to scanning while their neighbours use the mask
+    clump = wl.lattice_block(30, 30, dx=1.0)
+    rng = np.random.Generator(np.random.PCG64(5))
+    extra = 15.0 + rng.uniform(-1.5, 1.5, size=(300, 2))
+    clump = wl.scenarios._assemble(clump.params, [(clump.pos, (0.0, 0.0), 1.0, wl.FLUID),
+                                                  (extra, (0.0, 0.0), 1.0, wl.FLUID)])
+    clump.vel = rng.normal(0, 0.05, size=clump.vel.shape)
     return dict(small_jet=small_jet, cubic_jet=cubic_jet, cloud=cloud, reach2=reach2, disc=disc,
-                batch=batch, empty_mid=empty_mid, walls_only=walls_only, overlap=overlap)
+                batch=batch, empty_mid=empty_mid, walls_only=walls_only, overlap=overlap,
+                jet_reach2=jet_reach2, clump=clump)
 
 
 CASES = _cases()
@@ -96,7 +108,7 @@ def test_neighbour_lists_bit_exact(gpu, orc, name):
 
 
 @pytest.mark.parametrize("name", ["small_jet", "cubic_jet", "cloud", "reach2", "disc", "batch", "overlap",
-                                  "empty_mid", "walls_only"])
+                                  "empty_mid", "walls_only", "jet_reach2", "clump"])
 def test_single_evaluation_fp32(gpu, orc, name):
     obj = _rounded(CASES[name], 32)
     say(f"[eval fp32] case={name} n={obj.n}")
