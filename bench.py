@@ -102,7 +102,8 @@ def main():
     ap.add_argument("--block-sweep", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
     ap.add_argument("--cell-factor", type=float, default=0.0,
-                    help="override every system's cell size as this multiple of h")
+                    help="override every system's cell size as this multiple of h (skips the autotuner)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (keep the scenario cell size)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -129,8 +130,17 @@ def main():
             sy.params["cell_size"] = args.cell_factor * sy.params["h"]
         desc += f", cell size {args.cell_factor} h"
     print(f"[bench] workload {args.workload}: {desc}; n={batch.n}", flush=True)
+    tune = None
+    cell_factor, block_sweep = args.cell_factor, args.block_sweep
+    if not args.no_tune and args.cell_factor <= 0 and args.block_sweep == 0:
+        t0 = time.perf_counter()
+        tune = sph.autotune(batch, dtype_bits=bits, trial_steps=10)
+        cell_factor, block_sweep = tune["cell_factor"], tune["block_sweep"]
+        print(f"[bench] autotune {time.perf_counter() - t0:.1f} s: {tune}", flush=True)
+        desc += f", autotuned cell size {cell_factor} h, {block_sweep}-thread sweep blocks"
     t0 = time.perf_counter()
-    sim = sph.Simulation(batch, dtype_bits=bits, block_sweep=args.block_sweep, xcd_remap=args.xcd)
+    sim = sph.Simulation(batch, dtype_bits=bits, block_sweep=block_sweep, xcd_remap=args.xcd,
+                         cell_factor=cell_factor)
     print(f"[bench] init {time.perf_counter() - t0:.1f} s, workspace {sim.workspace_bytes / 2**30:.2f} GiB",
           flush=True)
     sim.step(args.warmup)
@@ -178,7 +188,8 @@ def main():
         "dtype": "f32" if bits == 32 else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_particles": batch.n, "n_systems": len(batch.systems),
-                   "n_active": n_act, "closure": "plain", "graph": True, "instability_flags": flags},
+                   "n_active": n_act, "closure": "plain", "graph": True, "instability_flags": flags,
+                   "autotune": tune},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algo_bytes_per_particle": ALGO_BYTES[dom], "avg_launch_ms": avg},

@@ -111,8 +111,20 @@ typedef struct sph_options {
     int32_t block_stream;  /* threads per block, per-particle kernels (0 = 256) */
     int32_t use_graph;     /* 1: sph_step replays captured hipGraphs; 0: plain launches; -1: default (1) */
     int32_t xcd_remap;     /* 1: map workgroups so each XCD sweeps one contiguous range; -1: default (1) */
-    int32_t reserved[3];
+    int32_t graph_steps;   /* steps per replayed graph with use_graph (even, 0 = 8); odd remainders
+                              replay a one-step graph */
+    int32_t reserved[2];
 } sph_options;
+
+/* Result of sph_autotune. */
+typedef struct sph_tune_result {
+    double cell_factor;    /* chosen cell size as a multiple of each system's h */
+    int32_t block_sweep;   /* chosen threads per block of the neighbour sweeps */
+    int32_t n_tried;       /* configurations timed (0 when served from the cache) */
+    double ms_per_step;    /* measured time per step of the chosen configuration */
+    int32_t from_cache;    /* 1: an earlier call on the same problem class decided */
+    int32_t pad_;
+} sph_tune_result;
 
 typedef struct sph_ctx sph_ctx;
 
@@ -189,6 +201,22 @@ sph_status sph_sync(sph_ctx* ctx);
  * names/avg_ms/calls: arrays of max_stats entries; *n_stats receives the count. */
 sph_status sph_profile(sph_ctx* ctx, int32_t n_steps, int32_t max_stats, const char** names,
                        double* avg_ms, int64_t* calls, int32_t* n_stats);
+
+/* Pick the cell size and sweep block shape for these systems by timing: for
+ * cell sizes 1.05, 1.1, 1.2 h (5 x 5 cell blocks) and 2.05, 2.2 h (3 x 3) and
+ * block_sweep 128 and 256, a throwaway context is built from the given initial
+ * state inside d_workspace (the caller's arrays are not modified), run for two
+ * warm-up steps and trial_steps timed steps, and freed. Configurations whose
+ * workspace exceeds ws_bytes are skipped; size the workspace with
+ * sph_workspace_bytes() at cell_size = 1.05 h to allow all of them. The winner
+ * is cached per process by (dtype, number of systems, log2 of the particle
+ * count, kernels used) and reused without timing. Arguments as for sph_init;
+ * opt's other fields are kept. Errors: those of sph_init; SPH_ENOMEM if no
+ * configuration fits. */
+sph_status sph_autotune(const sph_options* opt, int32_t n_sys, const sph_params* p, const int64_t* offsets,
+                        const double* pos, const double* vel, const double* rho, const double* mass,
+                        const int32_t* type, void* d_workspace, size_t ws_bytes, void* stream,
+                        int32_t trial_steps, sph_tune_result* out);
 
 /* Release the context (waits for the stream; the workspace is the caller's). */
 void sph_free(sph_ctx* ctx);

@@ -6,6 +6,6 @@ behind the C-ABI of include/sph.h.
 device memory and the stream.
 """
 from . import native  # noqa: F401
-from .sim import Simulation  # noqa: F401
+from .sim import Simulation, autotune  # noqa: F401
 
-__all__ = ["Simulation", "native"]
+__all__ = ["Simulation", "autotune", "native"]

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <cstdio>
 #include <memory>
 #include <string>
@@ -133,6 +134,8 @@ sph_options resolve(const sph_options* o) {
     if (r.block_stream == 0) r.block_stream = 256;
     if (r.use_graph < 0) r.use_graph = 1;
     if (r.xcd_remap < 0) r.xcd_remap = 1;
+    if (r.graph_steps <= 0) r.graph_steps = 8;
+    if (r.graph_steps & 1) r.graph_steps += 1;
     return r;
 }
 
@@ -210,13 +213,18 @@ struct Impl : sph_ctx_base {
     int64_t* dbg_start = nullptr;
     int cur = 0;
     bool graphs = false;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_steps = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // one step from buffer k
     hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t mexec[2] = {nullptr, nullptr};   // graph_steps steps from buffer k (back to k)
+    hipGraph_t mgraph[2] = {nullptr, nullptr};
 
     ~Impl() override {
         for (int k = 0; k < 2; ++k) {
             if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
             if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            if (mexec[k]) (void)hipGraphExecDestroy(mexec[k]);
+            if (mgraph[k]) (void)hipGraphDestroy(mgraph[k]);
         }
     }
 
@@ -348,14 +356,18 @@ Impl<T>* impl_of(sph_ctx* c) { return static_cast<Impl<T>*>(c->impl.get()); }
 template <typename T>
 int step_impl(sph_ctx* c, int n_steps) {
     Impl<T>* m = impl_of<T>(c);
-    for (int s = 0; s < n_steps; ++s) {
-        if (m->graphs) {
+    int left = n_steps;
+    if (m->graphs) {
+        while (left >= m->graph_steps) {
+            HIP_OK(hipGraphLaunch(m->mexec[m->cur], c->stream));
+            left -= m->graph_steps;
+        }
+        for (; left > 0; --left) {
             HIP_OK(hipGraphLaunch(m->gexec[m->cur], c->stream));
             m->cur ^= 1;
-        } else {
-            m->step(c->stream, &c->timer);
         }
     }
+    for (; left > 0; --left) m->step(c->stream, &c->timer);
     HIP_OK(hipGetLastError());
     return SPH_OK;
 }
@@ -733,8 +745,14 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
             m->step(c->cap_stream, &off);
             HIP_OK(hipStreamEndCapture(c->cap_stream, &m->graph[k]));
             HIP_OK(hipGraphInstantiate(&m->gexec[k], m->graph[k], nullptr, nullptr, 0));
+            m->cur = k;
+            HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < c->opt.graph_steps; ++i) m->step(c->cap_stream, &off);
+            HIP_OK(hipStreamEndCapture(c->cap_stream, &m->mgraph[k]));
+            HIP_OK(hipGraphInstantiate(&m->mexec[k], m->mgraph[k], nullptr, nullptr, 0));
         }
         m->cur = saved;
+        m->graph_steps = c->opt.graph_steps;
         m->graphs = true;
     }
     c->step_fn = step_impl<T>;
@@ -859,6 +877,75 @@ sph_status sph_profile(sph_ctx* c, int32_t n_steps, int32_t max_stats, const cha
     }
     *n_stats = (int32_t)c->prof_names.size();
     return (sph_status)rc;
+}
+
+sph_status sph_autotune(const sph_options* opt, int32_t n_sys, const sph_params* p, const int64_t* offsets,
+                        const double* pos, const double* vel, const double* rho, const double* mass,
+                        const int32_t* type, void* d_workspace, size_t ws_bytes, void* stream,
+                        int32_t trial_steps, sph_tune_result* out) {
+    sph_ctx* c = nullptr;
+    if (!out || !p || !offsets || n_sys < 1) return fail(c, SPH_EINVAL, "bad arguments");
+    if (trial_steps < 1) return fail(c, SPH_EINVAL, "trial_steps must be >= 1");
+    sph_options base = resolve(opt);
+    memset(out, 0, sizeof *out);
+    // problem class for the cache
+    int64_t n = offsets[n_sys];
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= n) ++lg;
+    int kernels = 0;
+    for (int s = 0; s < n_sys; ++s) kernels |= 1 << p[s].kernel;
+    char keybuf[96];
+    snprintf(keybuf, sizeof keybuf, "%d/%d/%d/%d", base.dtype_bits, n_sys, lg, kernels);
+    static std::map<std::string, sph_tune_result> cache;
+    auto hit = cache.find(keybuf);
+    if (hit != cache.end()) {
+        *out = hit->second;
+        out->from_cache = 1;
+        out->n_tried = 0;
+        return SPH_OK;
+    }
+    const double factors[] = {1.05, 1.1, 1.2, 2.05, 2.2};
+    const int blocks[] = {128, 256};
+    std::vector<sph_params> q(p, p + n_sys);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(c, SPH_EDEVICE, "hipEventCreate failed");
+    double best = 1e300;
+    int tried = 0;
+    sph_status last = SPH_ENOMEM;
+    for (double f : factors) {
+        for (int s = 0; s < n_sys; ++s) q[s].cell_size = f * p[s].h;
+        for (int bsw : blocks) {
+            sph_options o = base;
+            o.block_sweep = bsw;
+            size_t need = 0;
+            if (sph_workspace_bytes(&o, n_sys, q.data(), offsets, &need) != SPH_OK || need > ws_bytes) continue;
+            sph_ctx* t = nullptr;
+            last = sph_init(&o, n_sys, q.data(), offsets, pos, vel, rho, mass, type, d_workspace, ws_bytes, stream, &t);
+            if (last != SPH_OK) continue;
+            float ms = 0.f;
+            bool ok = sph_step(t, 2) == SPH_OK && hipEventRecord(e0, st) == hipSuccess &&
+                      sph_step(t, trial_steps) == SPH_OK && hipEventRecord(e1, st) == hipSuccess &&
+                      hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            sph_free(t);
+            if (!ok) continue;
+            ++tried;
+            double per = (double)ms / trial_steps;
+            if (per < best) {
+                best = per;
+                out->cell_factor = f;
+                out->block_sweep = bsw;
+                out->ms_per_step = per;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!tried) return fail(c, last == SPH_OK ? SPH_ENOMEM : last, "no configuration could be timed");
+    out->n_tried = tried;
+    cache[keybuf] = *out;
+    return SPH_OK;
 }
 
 void sph_free(sph_ctx* c) {

@@ -25,7 +25,7 @@ FIELDS = {
 # Exported entry points, as declared in include/sph.h.
 EXPORTS = [
     "sph_workspace_bytes", "sph_init", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
-    "sph_sync", "sph_profile", "sph_free", "sph_last_error", "sph_abi_version",
+    "sph_sync", "sph_profile", "sph_autotune", "sph_free", "sph_last_error", "sph_abi_version",
 ]
 
 
@@ -44,7 +44,15 @@ class SphParams(C.Structure):
 class SphOptions(C.Structure):
     _fields_ = [
         ("dtype_bits", C.c_int32), ("block_sweep", C.c_int32), ("block_stream", C.c_int32),
-        ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("reserved", C.c_int32 * 3),
+        ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("graph_steps", C.c_int32),
+        ("reserved", C.c_int32 * 2),
+    ]
+
+
+class SphTuneResult(C.Structure):
+    _fields_ = [
+        ("cell_factor", C.c_double), ("block_sweep", C.c_int32), ("n_tried", C.c_int32),
+        ("ms_per_step", C.c_double), ("from_cache", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -75,13 +83,14 @@ def load():
     L.sph_neighbors.argtypes = [vp, vp, vp, i64, C.POINTER(i64)]
     L.sph_sync.argtypes = [vp]
     L.sph_profile.argtypes = [vp, i32, i32, C.POINTER(C.c_char_p), vp, vp, C.POINTER(i32)]
+    L.sph_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, i32, vp]
     L.sph_free.argtypes = [vp]
     L.sph_free.restype = None
     L.sph_last_error.argtypes = [vp]
     L.sph_last_error.restype = C.c_char_p
     L.sph_abi_version.restype = i32
     for name in ("sph_workspace_bytes", "sph_init", "sph_step", "sph_evaluate", "sph_read",
-                 "sph_neighbors", "sph_sync", "sph_profile"):
+                 "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune"):
         getattr(L, name).restype = i32
     _lib = L
     return L

@@ -53,12 +53,15 @@ class Simulation:
     """
 
     def __init__(self, systems, dtype_bits: int = 32, block_sweep: int = 0, block_stream: int = 0,
-                 use_graph: int = -1, xcd_remap: int = -1, device: str = "cuda:0", stream=None):
+                 use_graph: int = -1, xcd_remap: int = -1, graph_steps: int = 0, cell_factor: float = 0.0,
+                 device: str = "cuda:0", stream=None):
         import torch
 
         L = native.load()
         self._L = L
         plist, off, pos, vel, rho, mass, typ = _unpack(systems)
+        if cell_factor > 0:
+            plist = [dict(d, cell_size=cell_factor * d["h"]) for d in plist]
         self.n = int(off[-1])
         self.n_sys = len(plist)
         self.params = plist
@@ -69,7 +72,7 @@ class Simulation:
         self._P = P
         opt = native.SphOptions()
         opt.dtype_bits, opt.block_sweep, opt.block_stream = dtype_bits, block_sweep, block_stream
-        opt.use_graph, opt.xcd_remap = use_graph, xcd_remap
+        opt.use_graph, opt.xcd_remap, opt.graph_steps = use_graph, xcd_remap, graph_steps
         self._opt = opt
         self.dtype_bits = dtype_bits
         nbytes = C.c_size_t(0)
@@ -166,3 +169,36 @@ class Simulation:
 
     def __exit__(self, *a):
         self.close()
+
+
+def autotune(systems, dtype_bits: int = 32, trial_steps: int = 5, device: str = "cuda:0", stream=None,
+             **opts) -> Dict:
+    """Time the candidate cell sizes and sweep block shapes on a copy of the
+    initial state (sph_autotune) and return the winner."""
+    import torch
+
+    L = native.load()
+    plist, off, pos, vel, rho, mass, typ = _unpack(systems)
+    n_sys = len(plist)
+    opt = native.SphOptions()
+    opt.dtype_bits = dtype_bits
+    for k, v in opts.items():
+        setattr(opt, k, v)
+    fine = (native.SphParams * n_sys)()
+    P = (native.SphParams * n_sys)()
+    for i, d in enumerate(plist):
+        P[i] = native.params_struct(d)
+        fine[i] = native.params_struct(dict(d, cell_size=1.05 * d["h"]))
+    nbytes = C.c_size_t(0)
+    native.check(L.sph_workspace_bytes(C.byref(opt), n_sys, fine, _ptr(off), C.byref(nbytes)))
+    dev = torch.device(device)
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    res = native.SphTuneResult()
+    native.check(L.sph_autotune(C.byref(opt), n_sys, P, _ptr(off), _ptr(pos), _ptr(vel), _ptr(rho), _ptr(mass),
+                                _ptr(typ), C.c_void_p(ws.data_ptr()), int(nbytes.value),
+                                C.c_void_p(stream.cuda_stream), int(trial_steps), C.byref(res)))
+    del ws
+    return dict(cell_factor=res.cell_factor, block_sweep=res.block_sweep, ms_per_step=res.ms_per_step,
+                n_tried=res.n_tried, from_cache=bool(res.from_cache))

@@ -213,3 +213,43 @@ def test_piston_and_deactivation(gpu, orc):
         pis = slice(s.n, s.n + p.n)
         assert np.allclose(pos[pis], st.pos[pis], atol=1e-9)
         assert np.isclose(sim.read("mass").sum(), obj.cat("mass").sum(), rtol=1e-6)
+
+
+@pytest.mark.parametrize("factor", [1.05, 1.2, 2.05, 2.2])
+def test_neighbours_independent_of_cell_size(gpu, orc, factor):
+    """The pair predicate decides membership, so every cell size the autotuner
+    may pick gives the same neighbour lists and sort order."""
+    obj = _rounded(CASES["small_jet"], 32)
+    say(f"[cell size] factor={factor} n={obj.n}")
+    with _sim(gpu, obj, cell_factor=factor) as sim:
+        start, nbr = sim.neighbors()
+        g = gpu_eval(sim)
+    ostart, onbr = orc.neighbors(obj)
+    assert np.array_equal(start, ostart) and np.array_equal(nbr, onbr)
+    o = orc.evaluate(obj)
+    compare_eval(g, o, _eps_per_particle(obj), ostart, onbr, 1e-5, obj.type == wl.FLUID)
+
+
+def test_graph_replay_matches_eager_launches(gpu):
+    obj = _rounded(CASES["batch"], 32)
+    say(f"[graph vs eager] batch n={obj.n}")
+    outs = []
+    for use_graph in (0, 1):
+        with _sim(gpu, obj, use_graph=use_graph, graph_steps=4) as sim:
+            sim.step(11)
+            outs.append((sim.read("pos"), sim.read("vel"), sim.read("rho"), sim.read("time")))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_picks_a_candidate_and_caches(gpu):
+    obj = _rounded(CASES["batch"], 32)
+    say(f"[autotune] batch n={obj.n}")
+    r1 = gpu.autotune(obj, dtype_bits=32, trial_steps=2)
+    assert r1["cell_factor"] in (1.05, 1.1, 1.2, 2.05, 2.2)
+    assert r1["block_sweep"] in (128, 256) and r1["n_tried"] >= 1 and r1["ms_per_step"] > 0
+    r2 = gpu.autotune(obj, dtype_bits=32, trial_steps=2)
+    assert r2["from_cache"] and r2["cell_factor"] == r1["cell_factor"]
+    with _sim(gpu, obj, cell_factor=r1["cell_factor"], block_sweep=r1["block_sweep"]) as sim:
+        sim.step(3)
+        assert sim.read("flags")[0] == 0
