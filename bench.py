@@ -35,17 +35,18 @@ HBM_PEAK_GBS = 8000.0
 # per-slot array the kernel needs read once and every output written once
 # (neighbour re-reads are the reuse the cell order provides and are not
 # counted). Layout: pos 16 (FP64 pair), vel 8, dens 4, mass 4, tag 4, id 4,
-# cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4.
+# cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, c,
+# rho, m), neighbour mask 16.
 ALGO_BYTES = {
-    "colour": 16 + 4 + 4 + 4 + 4 + 4,                 # pos, dens, mass, tag, cell -> colour
-    "main": 16 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 8 + 8,   # pos vel dens mass tag cell colour -> drho acc nrm
-    "surface": 4 + 8 + 8 + 4 + 8 + 4 + 4,             # tag nrm acc dens -> acc kappa kappa_plain
-    "predict": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,   # tag pos vel dens drho acc -> pos_h vel_h dens_h
-    "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,   # tag pos vel dens drho acc -> pos vel dens
-    "sort_key": 16 + 4 + 4 + 4 + 4,                   # pos tag -> key slot (+ count)
-    "sort_scatter": 4 + 4 + 4 + 4 + 4 + 4,            # key slot id cstart -> tmp_src tmp_id
-    "sort_cells": 16,                                 # tmp_src tmp_id read + write
-    "sort_permute": 4 + 4 + 4 + 40 + 40 + 4,          # tmp_src tmp_id key X -> Y cell
+    "colour": 16 + 4 + 4 + 4 + 16,                        # pos vol cell -> colour mask
+    "main": 4 + 16 + 8 + 16 + 4 + 16 + 4 + 4 + 8 + 8,     # tag pos vel eos colour mask cell -> drho acc nrm
+    "surface": 4 + 8 + 8 + 4 + 8 + 4 + 4,                 # tag nrm acc rho -> acc kappa kappa_plain (bulk)
+    "predict": 4 + 16 + 8 + 4 + 4 + 8 + 4 + 16 + 8 + 4 + 4 + 16,  # tag pos vel dens drho acc mass -> half state, vol, eos
+    "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,       # tag pos vel dens drho acc -> pos vel dens
+    "sort_key": 16 + 4 + 4 + 4,                           # pos tag -> key slot
+    "sort_scatter": 4 + 4 + 4 + 4 + 4,                    # key slot id -> tmp_src tmp_id
+    "sort_cells": 16,                                     # tmp_src tmp_id read + write
+    "sort_permute": 4 + 4 + 4 + 36 + 40 + 4 + 4 + 16,     # tmp_src tmp_id key X -> Y cell vol eos
 }
 
 

@@ -152,7 +152,11 @@ enum {
     SPH_F_SORT_PERM = 16, /* n, int64, particle id held by each slot of the sorted arrays */
     SPH_F_FLAGS = 17,     /* 1, int32, instability bits (1 non-finite, 2 density, 4 skin) */
     SPH_F_CURV_PLAIN = 18,/* n, curvature of eq. 23 (equals CURV unless the closure is on) */
-    SPH_F_COUNT = 19
+    SPH_F_STENCIL = 19,   /* n x 64, closure input of every particle the closure saw at the last
+                             evaluation (BF16 values as FP64), zeros elsewhere */
+    SPH_F_CLOSURE = 20,   /* n x 4, network output (n_x, n_y, kappa h, 0) of those particles */
+    SPH_F_FALLBACK = 21,  /* n, int32, 1 where the plain curvature replaced the network's */
+    SPH_F_COUNT = 22
 };
 
 /* Bytes of device workspace a context with these systems needs.
@@ -217,6 +221,53 @@ sph_status sph_autotune(const sph_options* opt, int32_t n_sys, const sph_params*
                         const double* pos, const double* vel, const double* rho, const double* mass,
                         const int32_t* type, void* d_workspace, size_t ws_bytes, void* stream,
                         int32_t trial_steps, sph_tune_result* out);
+
+/* ------------------------------------------------------------------------
+ * Learned curvature closure (for systems with sph_params.closure = 1)
+ *
+ * For every fluid particle that passes the normal filter (eq. 20), the
+ * closure builds a stencil -- the relative positions (r_b - r_a)/h of its
+ * fluid neighbours within 2h, the 32 nearest (ties by particle id), ordered by
+ * angle in (-pi, pi] (ties: nearer, then lower id), zero-padded to 32 pairs --
+ * and feeds it to a 64 -> 64 -> 64 -> 3 network (tanh hidden layers, linear
+ * output (n_x, n_y, kappa h)) evaluated on BF16 matrix cores with FP32
+ * accumulation. The network's curvature and unit normal replace those of
+ * eq. 21-23 in the surface-tension acceleration of eq. 24,
+ * a_s = -(sigma / rho_a) kappa |n_a| n_hat, except where the network's
+ * curvature differs from the plain estimate of eq. 23 by more than
+ * closure_tol times its magnitude: there the plain estimate is used.
+ *
+ * Parameters are a flat FP32 vector of SPH_MLP_NPARAMS values: W1 (64 x 64,
+ * row-major, input index first), b1 (64), W2 (64 x 64), b2 (64), W3 (64 x 3),
+ * b3 (3). They are rounded to BF16 for the matrix products; biases stay FP32.
+ * ------------------------------------------------------------------------ */
+#define SPH_MLP_NPARAMS 8515
+
+/* Install network parameters (host array of SPH_MLP_NPARAMS floats, copied)
+ * in a context; until called, a closure context's network is all zeros. */
+sph_status sph_set_closure(sph_ctx* ctx, const float* params);
+
+/* Trainer: FP32 master parameters, Adam moments and BF16 working copies on the
+ * device, and the forward / backward kernels. Device arrays: x (m x 64 BF16
+ * stencils, row-major), targets t and outputs y (m x 3 FP32), all in device
+ * memory owned by the caller; m <= max_batch. Loss is the mean squared error
+ * over the m rows and 3 outputs. */
+typedef struct sph_mlp sph_mlp;
+sph_status sph_mlp_workspace_bytes(int64_t max_batch, size_t* bytes_out);
+sph_status sph_mlp_create(const float* params, int64_t max_batch, void* d_workspace, size_t ws_bytes,
+                          void* stream, sph_mlp** out);
+sph_status sph_mlp_forward(sph_mlp* t, const uint16_t* d_x, int64_t m, float* d_y);
+/* Gradient of the loss w.r.t. the parameters (d_grad: SPH_MLP_NPARAMS FP32,
+ * flat order above) and the loss itself (d_loss: one FP32; may be NULL). */
+sph_status sph_mlp_gradient(sph_mlp* t, const uint16_t* d_x, const float* d_t, int64_t m, float* d_grad,
+                            float* d_loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * masters with learning rate lr; the BF16 copies follow. */
+sph_status sph_mlp_train_step(sph_mlp* t, const uint16_t* d_x, const float* d_t, int64_t m, float lr,
+                              float* d_loss);
+/* Copy the FP32 master parameters to host memory (SPH_MLP_NPARAMS floats). */
+sph_status sph_mlp_params(sph_mlp* t, float* params);
+void sph_mlp_free(sph_mlp* t);
 
 /* Release the context (waits for the stream; the workspace is the caller's). */
 void sph_free(sph_ctx* ctx);

@@ -1,0 +1,160 @@
+"""FP64 reference for the learned curvature closure (test infrastructure only).
+
+Stencil of a surface particle a: the relative positions (r_b - r_a)/h of its
+fluid neighbours (r_ab < 2h, b != a); at most the 32 nearest are kept (ties by
+particle id), then ordered by angle atan2(y, x) in (-pi, pi] (ties: nearer
+first, then lower id), and zero-padded to 32 entries; the network input is
+(x0, y0, x1, y1, ...), 64 numbers.
+
+Network: 64 -> 64 -> 64 -> 3, tanh on both hidden layers, linear output
+(n_x, n_y, kappa h). Loss: mean squared error over the batch and the three
+outputs, equal weights. Training: Adam on FP32 master weights whose BF16
+copies feed the forward pass.
+
+Everything here is plain numpy in float64: definitions written out, no
+blocking, so it can be read against the description above.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Tuple
+
+import numpy as np
+
+K_STENCIL = 32
+N_IN, N_H, N_OUT = 64, 64, 3
+
+
+# ----------------------------------------------------------------- stencils
+
+def stencil_of(a: int, pos: np.ndarray, nbrs, types: np.ndarray, h: float) -> np.ndarray:
+    """64-vector stencil of particle a from its neighbour list (ids b != a with
+    r_ab < 2h). Only fluid neighbours enter."""
+    cand = [b for b in nbrs if types[b] == 0]
+    d = [(float((pos[b, 0] - pos[a, 0]) ** 2 + (pos[b, 1] - pos[a, 1]) ** 2), int(b)) for b in cand]
+    d.sort()
+    keep = [b for _, b in d[:K_STENCIL]]
+    items = []
+    for b in keep:
+        x = (pos[b, 0] - pos[a, 0]) / h
+        y = (pos[b, 1] - pos[a, 1]) / h
+        ang = math.atan2(y, x)
+        if ang == -math.pi:
+            ang = math.pi
+        items.append((ang, x * x + y * y, b, x, y))
+    items.sort(key=lambda t: (t[0], t[1], t[2]))
+    out = np.zeros(2 * K_STENCIL)
+    for i, (_, _, _, x, y) in enumerate(items):
+        out[2 * i] = x
+        out[2 * i + 1] = y
+    return out
+
+
+def stencils(pos, start, nbr, types, h, which) -> np.ndarray:
+    """Stencils of the particles `which` (ids) from CSR neighbour lists."""
+    return np.stack([stencil_of(int(a), pos, nbr[start[a]:start[a + 1]], types, h) for a in which]) \
+        if len(which) else np.zeros((0, 2 * K_STENCIL))
+
+
+# ----------------------------------------------------------------- network
+
+def init_params(seed: int = 0) -> Dict[str, np.ndarray]:
+    """Xavier-uniform weights, zero biases (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def xavier(fan_in, fan_out):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-lim, lim, size=(fan_in, fan_out))
+
+    return dict(W1=xavier(N_IN, N_H), b1=np.zeros(N_H), W2=xavier(N_H, N_H), b2=np.zeros(N_H),
+                W3=xavier(N_H, N_OUT), b3=np.zeros(N_OUT))
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round float64 values to bfloat16 (round to nearest even on the float32
+    bit pattern), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(p: Dict[str, np.ndarray], X: np.ndarray):
+    """Returns (Y, cache) with Y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3 per row."""
+    Z1 = X @ p["W1"] + p["b1"]
+    H1 = np.tanh(Z1)
+    Z2 = H1 @ p["W2"] + p["b2"]
+    H2 = np.tanh(Z2)
+    Y = H2 @ p["W3"] + p["b3"]
+    return Y, (X, H1, H2)
+
+
+def loss(Y: np.ndarray, T: np.ndarray) -> float:
+    return float(np.mean((Y - T) ** 2))
+
+
+def backward(p: Dict[str, np.ndarray], cache, Y: np.ndarray, T: np.ndarray) -> Dict[str, np.ndarray]:
+    """Gradients of the mean squared error (chain rule, layer by layer)."""
+    X, H1, H2 = cache
+    B = Y.shape[0]
+    dY = 2.0 * (Y - T) / (B * Y.shape[1])
+    g = {}
+    g["W3"] = H2.T @ dY
+    g["b3"] = dY.sum(0)
+    dH2 = dY @ p["W3"].T
+    dZ2 = dH2 * (1.0 - H2 ** 2)
+    g["W2"] = H1.T @ dZ2
+    g["b2"] = dZ2.sum(0)
+    dH1 = dZ2 @ p["W2"].T
+    dZ1 = dH1 * (1.0 - H1 ** 2)
+    g["W1"] = X.T @ dZ1
+    g["b1"] = dZ1.sum(0)
+    return g
+
+
+def adam_step(p, g, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (t counts from 1) of params p in place."""
+    for k in p:
+        m[k] = b1 * m[k] + (1 - b1) * g[k]
+        v[k] = b2 * v[k] + (1 - b2) * g[k] ** 2
+        mh = m[k] / (1 - b1 ** t)
+        vh = v[k] / (1 - b2 ** t)
+        p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v
+
+
+def flat_params(p) -> np.ndarray:
+    """Parameter order of the packed buffers: W1 (row-major 64x64), b1, W2, b2,
+    W3 (64x3), b3."""
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(), p["b3"]])
+
+
+def unflat_params(w: np.ndarray) -> Dict[str, np.ndarray]:
+    w = np.asarray(w, dtype=np.float64)
+    o = 0
+    out = {}
+    for k, shp in (("W1", (N_IN, N_H)), ("b1", (N_H,)), ("W2", (N_H, N_H)), ("b2", (N_H,)),
+                   ("W3", (N_H, N_OUT)), ("b3", (N_OUT,))):
+        n = int(np.prod(shp))
+        out[k] = w[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+N_PARAMS = N_IN * N_H + N_H + N_H * N_H + N_H + N_H * N_OUT + N_OUT
+
+
+# ----------------------------------------------------------------- closure
+
+def closure_curvature(Y: np.ndarray, h: np.ndarray):
+    """Network output -> (unit normal, kappa)."""
+    nrm = Y[:, :2]
+    m = np.linalg.norm(nrm, axis=1, keepdims=True)
+    nh = np.where(m > 0, nrm / np.where(m > 0, m, 1.0), 0.0)
+    return nh, Y[:, 2] / h
+
+
+def fallback(kappa_mlp: np.ndarray, kappa_plain: np.ndarray, tol: float = 0.2) -> np.ndarray:
+    """True where the plain estimate replaces the network's: a relative
+    deviation above tol."""
+    return np.abs(kappa_mlp - kappa_plain) > tol * np.abs(kappa_plain)

@@ -172,6 +172,21 @@ struct sph_ctx {
     int (*evaluate_fn)(sph_ctx*) = nullptr;
     int (*read_fn)(sph_ctx*, int, void*, size_t) = nullptr;
     int (*nbr_fn)(sph_ctx*, int64_t*, int32_t*, int64_t, int64_t*) = nullptr;
+    int (*closure_fn)(sph_ctx*, const float*) = nullptr;
+};
+
+// Trainer of the closure network (see sph_mlp_* in include/sph.h).
+struct sph_mlp {
+    hipStream_t stream = nullptr;
+    int64_t max_batch = 0;
+    int tiles_per_wave = 2;
+    int t = 0;
+    MlpBufs B{};
+    float* grad = nullptr;
+    float* loss = nullptr;
+    float* partial = nullptr;
+    float* loss_part = nullptr;
+    float* staging = nullptr;
 };
 
 static sph_status fail(sph_ctx* c, sph_status s, const std::string& msg) {
@@ -203,6 +218,10 @@ struct Impl : sph_ctx_base {
     V4<T>* eos = nullptr;
     unsigned long long* nmask0 = nullptr;
     unsigned long long* nmask1 = nullptr;
+    // learned closure (only when some system uses it)
+    bool closure = false;
+    ClosureView cl{};
+    MlpBufs net{};
     V2<T>* acc = nullptr;
     V2<T>* nrm = nullptr;
     SortBufs sb{};
@@ -229,8 +248,26 @@ struct Impl : sph_ctx_base {
     }
 
     // Lays out every buffer in the workspace (base == nullptr: size only).
-    size_t carve(char* base, int64_t n_, int n_sys_, uint32_t trash, int block_stream) {
+    size_t carve(char* base, int64_t n_, int n_sys_, uint32_t trash, int block_stream, bool with_closure) {
         Carver cv{base};
+        closure = with_closure;
+        if (with_closure) {
+            cl.count = cv.take<uint32_t>(4);
+            cl.list = cv.take<uint32_t>(n_);
+            cl.stencil = cv.take<uint16_t>((size_t)64 * n_);
+            cl.out = cv.take<float>((size_t)4 * n_);
+            cl.fallback = cv.take<uint32_t>(n_);
+            cl.capacity = (uint32_t)n_;
+            net.master = cv.take<float>(MLP_NPARAMS);
+            net.wt1 = cv.take<uint16_t>(64 * 64);
+            net.wt2 = cv.take<uint16_t>(64 * 64);
+            net.wt3 = cv.take<uint16_t>(16 * 64);
+            net.w2 = cv.take<uint16_t>(64 * 64);
+            net.w3 = cv.take<uint16_t>(64 * 16);
+            net.b1 = cv.take<float>(64);
+            net.b2 = cv.take<float>(64);
+            net.b3 = cv.take<float>(16);
+        }
         sys = cv.take<SysDev<T>>(n_sys_);
         for (int k = 0; k < 2; ++k) {
             buf[k].pos = cv.take<double2>(n_);
@@ -307,7 +344,20 @@ struct Impl : sph_ctx_base {
         v.eos = eos;
         v.nmask0 = nmask0;
         v.nmask1 = nmask1;
+        if (closure) {
+            v.cl_count = cl.count;
+            v.cl_list = cl.list;
+            v.cl_capacity = cl.capacity;
+        }
         return v;
+    }
+
+    // One evaluation of every right-hand side at the current (or half-step) state.
+    void evaluate(bool half, bool do_dt, hipStream_t st, KernelTimer* kt) {
+        if (closure) launch_fill_u32(cl.count, 1, 0u, st);
+        EvalView<T> v = eval_view(half, do_dt);
+        launch_eval<T>(L, v, st, kt);
+        if (closure) launch_closure<T>(v, cl, net.view(), cl.capacity, st, kt);
     }
 
     IntegView<T> integ_view() const {
@@ -342,10 +392,10 @@ struct Impl : sph_ctx_base {
     // One predictor-corrector step, enqueued on st.
     void step(hipStream_t st, KernelTimer* kt) {
         sort(st, kt);
-        launch_eval<T>(L, eval_view(false, true), st, kt);
+        evaluate(false, true, st, kt);
         launch_dt<T>(n_sys, sys, dtmin, dt, st, kt);
         launch_predict<T>(L, integ_view(), st, kt);
-        launch_eval<T>(L, eval_view(true, false), st, kt);
+        evaluate(true, false, st, kt);
         launch_correct<T>(L, integ_view(), n_sys, dt, time, st, kt);
     }
 };
@@ -376,7 +426,7 @@ template <typename T>
 int evaluate_impl(sph_ctx* c) {
     Impl<T>* m = impl_of<T>(c);
     m->sort(c->stream, &c->timer);
-    launch_eval<T>(m->L, m->eval_view(false, true), c->stream, &c->timer);
+    m->evaluate(false, true, c->stream, &c->timer);
     launch_dt<T>(m->n_sys, m->sys, m->dtmin, m->dt, c->stream, &c->timer);
     HIP_OK(hipGetLastError());
     return SPH_OK;
@@ -414,7 +464,9 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
         case SPH_F_RHO: case SPH_F_PRESSURE: case SPH_F_MASS: case SPH_F_DRHODT: case SPH_F_COLOUR:
         case SPH_F_CURV: case SPH_F_CURV_PLAIN: case SPH_F_SORT_KEYS: case SPH_F_SORT_PERM:
             want = (size_t)n * 8; break;
-        case SPH_F_TYPE: case SPH_F_NFLAG: want = (size_t)n * 4; break;
+        case SPH_F_TYPE: case SPH_F_NFLAG: case SPH_F_FALLBACK: want = (size_t)n * 4; break;
+        case SPH_F_STENCIL: want = (size_t)n * 64 * 8; break;
+        case SPH_F_CLOSURE: want = (size_t)n * 4 * 8; break;
         case SPH_F_DT: case SPH_F_TIME: case SPH_F_NACTIVE: want = (size_t)ns * 8; break;
         case SPH_F_FLAGS: want = 4; break;
         default: return fail(c, SPH_EINVAL, "unknown field");
@@ -532,6 +584,45 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
             HIP_OK(fetch(m->flags, 4, tmp));
             memcpy(host, tmp.data(), 4);
             break;
+        case SPH_F_STENCIL: case SPH_F_CLOSURE: case SPH_F_FALLBACK: {
+            memset(host, 0, bytes);
+            if (!m->closure) break;
+            uint32_t cnt = 0;
+            HIP_OK(hipMemcpyAsync(&cnt, m->cl.count, 4, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (cnt > m->cl.capacity) cnt = m->cl.capacity;
+            if (field == SPH_F_FALLBACK) {
+                HIP_OK(fetch(m->cl.fallback, n * 4, tmp));
+                const uint32_t* f = reinterpret_cast<const uint32_t*>(tmp.data());
+                std::vector<uint32_t> lst(cnt);
+                if (cnt) HIP_OK(hipMemcpyAsync(lst.data(), m->cl.list, cnt * 4, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                int32_t* o = static_cast<int32_t*>(host);
+                for (uint32_t k = 0; k < cnt; ++k) o[ids[lst[k]]] = (int32_t)f[lst[k]];
+                break;
+            }
+            std::vector<uint32_t> lst(cnt);
+            if (cnt) HIP_OK(hipMemcpyAsync(lst.data(), m->cl.list, cnt * 4, hipMemcpyDeviceToHost, st));
+            if (field == SPH_F_STENCIL) {
+                std::vector<uint16_t> rows((size_t)cnt * 64);
+                if (cnt) HIP_OK(hipMemcpyAsync(rows.data(), m->cl.stencil, rows.size() * 2, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                for (uint32_t k = 0; k < cnt; ++k)
+                    for (int j = 0; j < 64; ++j) {
+                        uint32_t u = (uint32_t)rows[(size_t)k * 64 + j] << 16;
+                        float f;
+                        memcpy(&f, &u, 4);
+                        out[(size_t)ids[lst[k]] * 64 + j] = (double)f;
+                    }
+            } else {
+                std::vector<float> rows((size_t)cnt * 4);
+                if (cnt) HIP_OK(hipMemcpyAsync(rows.data(), m->cl.out, rows.size() * 4, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                for (uint32_t k = 0; k < cnt; ++k)
+                    for (int j = 0; j < 4; ++j) out[(size_t)ids[lst[k]] * 4 + j] = j < 3 ? rows[(size_t)k * 4 + j] : 0.0;
+            }
+            break;
+        }
     }
     uint32_t fl = 0;
     HIP_OK(hipMemcpyAsync(&fl, m->flags, 4, hipMemcpyDeviceToHost, st));
@@ -585,6 +676,17 @@ int nbr_impl(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* tot
         }
         a0 = a1;
     }
+    return SPH_OK;
+}
+
+template <typename T>
+int closure_impl(sph_ctx* c, const float* params) {
+    Impl<T>* m = impl_of<T>(c);
+    if (!m->closure) return fail(c, SPH_ESTATE, "no system of this context uses the closure");
+    HIP_OK(hipMemcpyAsync(m->net.master, params, sizeof(float) * MLP_NPARAMS, hipMemcpyHostToDevice, c->stream));
+    launch_mlp_set(m->net, m->net.master, c->stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
     return SPH_OK;
 }
 
@@ -680,11 +782,13 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     m->L.block_stream = c->opt.block_stream;
     m->L.xcd = c->opt.xcd_remap;
     const uint32_t trash = c->cell_base[c->n_sys];
-    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream);
+    bool with_closure = false;
+    for (int s2 = 0; s2 < c->n_sys; ++s2) with_closure = with_closure || c->params[s2].closure != 0;
+    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream, with_closure);
     if (ws_bytes < need)
         return fail(c, SPH_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws) & 255) return fail(c, SPH_EINVAL, "workspace must be 256-byte aligned");
-    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream);
+    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream, with_closure);
     const int64_t n = c->n;
     hipStream_t st = c->stream;
     // host staging in device format
@@ -731,6 +835,19 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     launch_fill_u64(reinterpret_cast<unsigned long long*>(m->time), c->n_sys, 0ull, st);
     launch_fill_u32(m->flags, 4, 0u, st);
     launch_fill_u32(m->sb.cell, n, 0u, st);
+    if (m->closure) {
+        launch_fill_u32(m->cl.count, 4, 0u, st);
+        launch_fill_u32(m->cl.fallback, n, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->cl.stencil), (size_t)32 * n, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->cl.out), (size_t)4 * n, 0u, st);
+        std::vector<float> zeros(MLP_NPARAMS, 0.f);
+        HIP_OK(hipMemcpyAsync(m->net.master, zeros.data(), sizeof(float) * MLP_NPARAMS, hipMemcpyHostToDevice, st));
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->net.wt3), 16 * 64 / 2, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->net.w3), 64 * 16 / 2, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->net.b3), 16, 0u, st);
+        launch_mlp_set(m->net, m->net.master, st);
+        HIP_OK(hipStreamSynchronize(st));
+    }
     // a first sort so the state is cell-ordered from the start
     m->sort(st, &c->timer);
     HIP_OK(hipGetLastError());
@@ -759,6 +876,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     c->evaluate_fn = evaluate_impl<T>;
     c->read_fn = read_impl<T>;
     c->nbr_fn = nbr_impl<T>;
+    c->closure_fn = closure_impl<T>;
     return SPH_OK;
 }
 
@@ -780,12 +898,14 @@ sph_status sph_workspace_bytes(const sph_options* opt, int32_t n_sys, const sph_
     std::vector<uint32_t> base;
     if (const char* e = plan(o, n_sys, p, offsets, base)) return fail(c, SPH_EINVAL, e);
     int64_t n = offsets[n_sys];
+    bool with_closure = false;
+    for (int s = 0; s < n_sys; ++s) with_closure = with_closure || p[s].closure != 0;
     if (o.dtype_bits == 32) {
         Impl<float> m;
-        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream);
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure);
     } else {
         Impl<double> m;
-        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream);
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure);
     }
     return SPH_OK;
 }
@@ -946,6 +1066,120 @@ sph_status sph_autotune(const sph_options* opt, int32_t n_sys, const sph_params*
     out->n_tried = tried;
     cache[keybuf] = *out;
     return SPH_OK;
+}
+
+sph_status sph_set_closure(sph_ctx* c, const float* params) {
+    if (!c || !params) return fail(c, SPH_EINVAL, "ctx or params is NULL");
+    return (sph_status)c->closure_fn(c, params);
+}
+
+// ------------------------------------------------------------ closure trainer
+
+static size_t mlp_carve(sph_mlp* t, char* base, int64_t max_batch) {
+    Carver cv{base};
+    const int nw = mlp_grad_waves(max_batch, 2) + 1;
+    MlpBufs B{};
+    B.master = cv.take<float>(MLP_NPARAMS);
+    B.adam_m = cv.take<float>(MLP_NPARAMS);
+    B.adam_v = cv.take<float>(MLP_NPARAMS);
+    B.wt1 = cv.take<uint16_t>(64 * 64);
+    B.wt2 = cv.take<uint16_t>(64 * 64);
+    B.wt3 = cv.take<uint16_t>(16 * 64);
+    B.w2 = cv.take<uint16_t>(64 * 64);
+    B.w3 = cv.take<uint16_t>(64 * 16);
+    B.b1 = cv.take<float>(64);
+    B.b2 = cv.take<float>(64);
+    B.b3 = cv.take<float>(16);
+    float* grad = cv.take<float>(MLP_NPARAMS);
+    float* loss = cv.take<float>(4);
+    float* partial = cv.take<float>((size_t)nw * MLP_NPARAMS);
+    float* loss_part = cv.take<float>(nw);
+    float* staging = cv.take<float>(MLP_NPARAMS);
+    if (t) {
+        t->B = B;
+        t->grad = grad;
+        t->loss = loss;
+        t->partial = partial;
+        t->loss_part = loss_part;
+        t->staging = staging;
+    }
+    return cv.off + 256;
+}
+
+sph_status sph_mlp_workspace_bytes(int64_t max_batch, size_t* bytes_out) {
+    sph_ctx* c = nullptr;
+    if (!bytes_out || max_batch < 1) return fail(c, SPH_EINVAL, "bad arguments");
+    *bytes_out = mlp_carve(nullptr, nullptr, max_batch);
+    return SPH_OK;
+}
+
+sph_status sph_mlp_create(const float* params, int64_t max_batch, void* d_workspace, size_t ws_bytes, void* stream,
+                          sph_mlp** out) {
+    sph_ctx* c = nullptr;
+    if (!out || !params || !d_workspace || max_batch < 1) return fail(c, SPH_EINVAL, "bad arguments");
+    *out = nullptr;
+    if (mlp_carve(nullptr, nullptr, max_batch) > ws_bytes) return fail(c, SPH_ENOMEM, "workspace too small");
+    if (((uintptr_t)d_workspace) & 255) return fail(c, SPH_EINVAL, "workspace must be 256-byte aligned");
+    std::unique_ptr<sph_mlp> t(new sph_mlp());
+    t->stream = static_cast<hipStream_t>(stream);
+    t->max_batch = max_batch;
+    mlp_carve(t.get(), static_cast<char*>(d_workspace), max_batch);
+    hipStream_t st = t->stream;
+    launch_fill_u32(reinterpret_cast<uint32_t*>(t->B.adam_m), MLP_NPARAMS, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(t->B.adam_v), MLP_NPARAMS, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(t->B.wt3), 16 * 64 / 2, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(t->B.w3), 64 * 16 / 2, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(t->B.b3), 16, 0u, st);
+    HIP_OK(hipMemcpyAsync(t->staging, params, sizeof(float) * MLP_NPARAMS, hipMemcpyHostToDevice, st));
+    launch_mlp_set(t->B, t->staging, st);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    *out = t.release();
+    return SPH_OK;
+}
+
+sph_status sph_mlp_forward(sph_mlp* t, const uint16_t* d_x, int64_t m, float* d_y) {
+    sph_ctx* c = nullptr;
+    if (!t || !d_x || !d_y || m < 0) return fail(c, SPH_EINVAL, "bad arguments");
+    if (m > 0) launch_mlp_forward(t->B.view(), d_x, m, d_y, 3, t->stream);
+    HIP_OK(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_mlp_gradient(sph_mlp* t, const uint16_t* d_x, const float* d_t, int64_t m, float* d_grad,
+                            float* d_loss) {
+    sph_ctx* c = nullptr;
+    if (!t || !d_x || !d_t || !d_grad || m < 1 || m > t->max_batch) return fail(c, SPH_EINVAL, "bad arguments");
+    launch_mlp_grad(t->B.view(), d_x, d_t, m, t->tiles_per_wave, t->partial, t->loss_part, d_grad, d_loss,
+                    t->stream);
+    HIP_OK(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_mlp_train_step(sph_mlp* t, const uint16_t* d_x, const float* d_t, int64_t m, float lr,
+                              float* d_loss) {
+    sph_ctx* c = nullptr;
+    if (!t || !d_x || !d_t || m < 1 || m > t->max_batch || !(lr > 0)) return fail(c, SPH_EINVAL, "bad arguments");
+    launch_mlp_grad(t->B.view(), d_x, d_t, m, t->tiles_per_wave, t->partial, t->loss_part, t->grad,
+                    d_loss ? d_loss : t->loss, t->stream);
+    t->t += 1;
+    launch_mlp_adam(t->B, t->grad, lr, t->t, t->stream);
+    HIP_OK(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_mlp_params(sph_mlp* t, float* params) {
+    sph_ctx* c = nullptr;
+    if (!t || !params) return fail(c, SPH_EINVAL, "bad arguments");
+    HIP_OK(hipMemcpyAsync(params, t->B.master, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToHost, t->stream));
+    HIP_OK(hipStreamSynchronize(t->stream));
+    return SPH_OK;
+}
+
+void sph_mlp_free(sph_mlp* t) {
+    if (!t) return;
+    (void)hipStreamSynchronize(t->stream);
+    delete t;
 }
 
 void sph_free(sph_ctx* c) {

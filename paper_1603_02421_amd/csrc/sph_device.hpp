@@ -91,48 +91,66 @@ template <typename T> __device__ __forceinline__ T sqrt_(T x);
 template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double sqrt_<double>(double x) { return __builtin_sqrt(x); }
 
+// Constants of a system's smoothing kernel, loaded once per thread.
+template <typename T>
+struct KernelConsts {
+    int kernel;
+    T inv_h, wnorm, gnorm;
+};
+
+template <typename T>
+__device__ __forceinline__ KernelConsts<T> kconsts(const SysDev<T>& S) {
+    return KernelConsts<T>{S.kernel, S.inv_h, S.wnorm, S.gnorm};
+}
+
 // Kernel value and gradient factor at distance r (< 2h): W(r) and F(r) with
 // grad_a W_ab = F(r) r_ab.
 //   Wendland: W = wn (1 - q/2)^4 (1 + 2q),  F = -5 wn / h^2 (1 - q/2)^3
 //   cubic:    W = wn [1 - 1.5 q^2 + 0.75 q^3 | 0.25 (2 - q)^3],
 //             F = wn / h^2 [-3 + 2.25 q | -0.75 (2 - q)^2 / q]
 template <typename T>
-__device__ __forceinline__ void kernel_wf(const SysDev<T>& S, T r, T& W, T& F) {
-    T q = r * S.inv_h;
-    if (S.kernel == 0) {
+__device__ __forceinline__ void kernel_wf(const KernelConsts<T>& K, T r, T& W, T& F) {
+    T q = r * K.inv_h;
+    if (K.kernel == 0) {
         T u = T(1) - T(0.5) * q;
         T u3 = u * u * u;
-        W = S.wnorm * u3 * u * (T(1) + T(2) * q);
-        F = S.gnorm * u3;
+        W = K.wnorm * u3 * u * (T(1) + T(2) * q);
+        F = K.gnorm * u3;
     } else {
         if (q <= T(1)) {
-            W = S.wnorm * (T(1) + q * q * (T(-1.5) + T(0.75) * q));
-            F = S.gnorm * (T(-3) + T(2.25) * q);
+            W = K.wnorm * (T(1) + q * q * (T(-1.5) + T(0.75) * q));
+            F = K.gnorm * (T(-3) + T(2.25) * q);
         } else {
             T u = T(2) - q;
-            W = S.wnorm * T(0.25) * u * u * u;
-            F = S.gnorm * T(-0.75) * u * u * rcp(q);
+            W = K.wnorm * T(0.25) * u * u * u;
+            F = K.gnorm * T(-0.75) * u * u * rcp(q);
         }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ T kernel_w(const SysDev<T>& S, T r) {
-    T W, F;
-    kernel_wf(S, r, W, F);
-    return W;
+__device__ __forceinline__ T kernel_w(const KernelConsts<T>& K, T r) {
+    T q = r * K.inv_h;
+    if (K.kernel == 0) {
+        T u = T(1) - T(0.5) * q;
+        T u2 = u * u;
+        return K.wnorm * u2 * u2 * (T(1) + T(2) * q);
+    }
+    if (q <= T(1)) return K.wnorm * (T(1) + q * q * (T(-1.5) + T(0.75) * q));
+    T u = T(2) - q;
+    return K.wnorm * T(0.25) * u * u * u;
 }
 
 template <typename T>
-__device__ __forceinline__ T kernel_f(const SysDev<T>& S, T r) {
-    T q = r * S.inv_h;
-    if (S.kernel == 0) {
+__device__ __forceinline__ T kernel_f(const KernelConsts<T>& K, T r) {
+    T q = r * K.inv_h;
+    if (K.kernel == 0) {
         T u = T(1) - T(0.5) * q;
-        return S.gnorm * u * u * u;
+        return K.gnorm * u * u * u;
     }
-    if (q <= T(1)) return S.gnorm * (T(-3) + T(2.25) * q);
+    if (q <= T(1)) return K.gnorm * (T(-3) + T(2.25) * q);
     T u = T(2) - q;
-    return S.gnorm * T(-0.75) * u * u * rcp(q);
+    return K.gnorm * T(-0.75) * u * u * rcp(q);
 }
 
 // Tait equation: P / rho^2 and the sound speed from the stored deviation

@@ -73,6 +73,61 @@ struct EvalView {
     const V4<T>* eos;           // (P / rho^2, c, rho, m)
     unsigned long long* nmask0;  // n: neighbour mask, candidates 0..63
     unsigned long long* nmask1;  // n: candidates 64..126 (+ overflow bit)
+    uint32_t* cl_count;          // closure list (null when no system uses the closure)
+    uint32_t* cl_list;
+    uint32_t cl_capacity;
+    uint32_t pad2_;
+};
+
+// Learned closure network: parameter count and offsets of the flat FP32
+// parameter vector (W1 in x out row-major, b1, W2, b2, W3 64 x 3, b3).
+constexpr int MLP_OFF_W1 = 0;
+constexpr int MLP_OFF_B1 = 64 * 64;
+constexpr int MLP_OFF_W2 = MLP_OFF_B1 + 64;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + 64 * 64;
+constexpr int MLP_OFF_W3 = MLP_OFF_B2 + 64;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + 64 * 3;
+constexpr int MLP_NPARAMS = MLP_OFF_B3 + 3;
+
+// BF16 working copies read by the network kernels: wt* transposed (out x in),
+// w2 and w3 as stored (in x out, w3 padded to 16 outputs); FP32 biases (b3
+// padded to 16).
+struct MlpView {
+    const uint16_t* wt1;
+    const uint16_t* wt2;
+    const uint16_t* wt3;
+    const uint16_t* w2;
+    const uint16_t* w3;
+    const float* b1;
+    const float* b2;
+    const float* b3;
+};
+
+// Everything the trainer owns on the device.
+struct MlpBufs {
+    float* master;   // MLP_NPARAMS FP32 masters
+    float* adam_m;
+    float* adam_v;
+    uint16_t* wt1;   // 64 x 64
+    uint16_t* wt2;   // 64 x 64
+    uint16_t* wt3;   // 16 x 64 (rows 3..15 zero)
+    uint16_t* w2;    // 64 x 64
+    uint16_t* w3;    // 64 x 16 (columns 3..15 zero)
+    float* b1;       // 64
+    float* b2;       // 64
+    float* b3;       // 16 (3..15 zero)
+    MlpView view() const { return MlpView{wt1, wt2, wt3, w2, w3, b1, b2, b3}; }
+};
+
+// The closure's per-evaluation buffers.
+struct ClosureView {
+    uint32_t* count;     // surface particles listed this evaluation
+    uint32_t* list;      // their slots
+    uint16_t* stencil;   // 64 BF16 per listed particle
+    float* out;          // 4 per listed particle: n_x, n_y, kappa h, unused
+    uint32_t* fallback;  // per slot: 1 where the plain curvature was used
+    uint32_t capacity;
+    uint32_t pad_;
 };
 
 // What the predictor and corrector read and write.
@@ -153,5 +208,15 @@ void launch_nbr_fill(const EvalView<T>& v, int a0, int a1, const int64_t* start,
                      hipStream_t st);
 template <typename T>
 void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* dens, T* out, hipStream_t st);
+
+void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y, int ystride, hipStream_t st);
+int mlp_grad_waves(int64_t m, int tiles_per_wave);
+void launch_mlp_grad(const MlpView& W, const uint16_t* X, const float* T, int64_t m, int tiles_per_wave,
+                     float* partial, float* loss_part, float* grad, float* loss, hipStream_t st);
+void launch_mlp_set(const MlpBufs& B, const float* params, hipStream_t st);
+void launch_mlp_adam(const MlpBufs& B, const float* grad, float lr, int t, hipStream_t st);
+template <typename T>
+void launch_closure(const EvalView<T>& v, const ClosureView& C, const MlpView& W, int64_t capacity, hipStream_t st,
+                    KernelTimer* kt);
 
 }  // namespace sphjet

@@ -429,19 +429,35 @@ __global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
     if (!wave_assign(v, sys, a)) return;
     const SysDev<T>& S = v.sys[sys];
     if (a >= v.sys_hi[sys]) return;
+    const KernelConsts<T> K = kconsts(S);
     const double2 pa = v.pos[a];
     T sum = v.vol[a] * S.W0;
     unsigned long long m0 = 0, m1 = 0;
     bool overflow = false;
-    scan_cells_ord<T>(S, v.cstart, v.cell[a], a, pa, v.pos,
-        [&](uint32_t b) { return v.vol[b]; },
-        [&](uint32_t, uint32_t ord, T dx, T dy, T vol_b) {
-            T r = sqrt_(dx * dx + dy * dy);
-            sum += vol_b * kernel_w(S, r);
-            if (ord < 64u) m0 |= 1ull << ord;
-            else if (ord < MASK_BITS) m1 |= 1ull << (ord - 64u);
-            else overflow = true;
-        });
+    auto mark = [&](uint32_t ord) {
+        if (ord < 64u) m0 |= 1ull << ord;
+        else if (ord < MASK_BITS) m1 |= 1ull << (ord - 64u);
+        else overflow = true;
+    };
+    auto load = [&](uint32_t b) { return v.vol[b]; };
+    auto acc = [&](uint32_t, T dx, T dy, T vol_b) { sum += vol_b * kernel_w(K, sqrt_(dx * dx + dy * dy)); };
+    if (S.reach == 1) {
+        // 3 x 3 blocks (about 3.5 candidates per neighbour): first the pair
+        // predicate alone, recorded as the mask, then the kernel sum over the
+        // accepted neighbours only, so lanes do not pay for each other's
+        // accepted candidates
+        scan_cells_ord<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
+                          [&](uint32_t, uint32_t ord, T, T, int) { mark(ord); });
+        if (!overflow) mask_neighbours<T>(v, S, a, pa, m0, m1, load, acc);
+        else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc);
+    } else {
+        // 5 x 5 blocks (about 2.2 candidates per neighbour): one pass
+        scan_cells_ord<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
+                          [&](uint32_t b, uint32_t ord, T dx, T dy, T vol_b) {
+                              acc(b, dx, dy, vol_b);
+                              mark(ord);
+                          });
+    }
     v.colour[a] = sum;
     v.nmask0[a] = m0;
     v.nmask1[a] = overflow ? (m1 | MASK_OVERFLOW) : m1;
@@ -468,6 +484,7 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
         const T pr_a = ea.x, c_a = ea.y, rho_a = ea.z;
         const T Ca = v.colour[a];
         const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
+        const KernelConsts<T> K = kconsts(S);
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, vsig = 0;
         neighbours<T>(v, S, a, pa,
             [&](uint32_t b) {
@@ -482,7 +499,7 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
                 if (!fluid && tag_type(p.tag) != T_FLUID) return;
                 const T pr_b = p.eos.x, c_b = p.eos.y, rho_b = p.eos.z, m_b = p.eos.w;
                 T r2 = dx * dx + dy * dy;
-                T F = kernel_f(S, sqrt_(r2));
+                T F = kernel_f(K, sqrt_(r2));
                 T ux = va.x - p.vel.x, uy = va.y - p.vel.y;
                 T vr = ux * dx + uy * dy;
                 drho += m_b * F * vr;
@@ -531,13 +548,18 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
     const SysDev<T>& S = v.sys[sys];
     const bool valid = a < v.sys_hi[sys] && tag_type(v.tag[a]) == T_FLUID;
     double dtf = __builtin_inf();
+    bool listed = false;
     if (valid) {
         const T eps = S.eps;
+        const KernelConsts<T> K = kconsts(S);
         const V2<T> n_a = v.nrm[a];
         const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
         V2<T> acc = v.acc[a];
         T kappa = 0;
         const T rho_a = v.eos[a].z;
+        // with the learned closure the surface force of a filtered particle is
+        // added later, from the network's curvature or the plain fallback
+        listed = v.cl_count != nullptr && S.closure != 0 && mag > eps;
         if (mag > eps) {
             const T im = rcp(mag);
             const T hx = n_a.x * im, hy = n_a.y * im;
@@ -552,7 +574,7 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
                         T ib = rcp(mb);
                         T r = sqrt_(dx * dx + dy * dy);
                         T W, F;
-                        kernel_wf(S, r, W, F);
+                        kernel_wf(K, r, W, F);
                         num += p.vol * F * ((p.nrm.x * ib - hx) * dx + (p.nrm.y * ib - hy) * dy);
                         den += p.vol * W;
                     }
@@ -560,15 +582,29 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
             kappa = num / den;
         }
         v.kappa_plain[a] = kappa;
-        T f = -S.sigma * rcp(rho_a) * kappa;
+        T f = listed ? T(0) : -S.sigma * rcp(rho_a) * kappa;
         acc.x += f * n_a.x + S.gx;
         acc.y += f * n_a.y + S.gy;
         v.acc[a] = acc;
         v.kappa[a] = kappa;
         T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
-        if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
+        if (am > T(0) && !listed) dtf = sqrt((double)S.h / (double)am);
     }
     if (v.do_dt) wave_atomic_min(v.dtmin + 2 * sys + 1, dtf, valid);
+    if (v.cl_count) {
+        // append the listed slots, one atomic per wave
+        const unsigned long long bal = __ballot(listed);
+        if (bal) {
+            const int first = __ffsll((long long)bal) - 1;
+            uint32_t base = 0;
+            if (__lane_id() == first) base = atomicAdd(v.cl_count, (uint32_t)__popcll(bal));
+            base = __shfl(base, first, 64);
+            if (listed) {
+                const uint32_t idx = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
+                if (idx < v.cl_capacity) v.cl_list[idx] = a;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ time step

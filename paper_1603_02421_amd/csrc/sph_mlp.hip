@@ -1,0 +1,547 @@
+// Learned curvature closure: stencil construction, a 64 -> 64 -> 64 -> 3 MLP
+// (tanh hidden layers, linear output: n_x, n_y, kappa h) on BF16 MFMA with
+// FP32 accumulation, its training (forward, backward, Adam), and the closure
+// step that puts the network's curvature into the surface-tension term of
+// eq. 24 with the plain estimate of eq. 23 as fallback.
+//
+// Matrix tiles use v_mfma_f32_16x16x16_bf16: for a 16x16 A (rows x k), a
+// 16x16 B (k x cols) and the 16x16 FP32 result, lane l holds
+//   A[l % 16][4 (l / 16) + i],  B[4 (l / 16) + i][l % 16],  D[4 (l / 16) + i][l % 16],  i = 0..3.
+// Weights are kept in BF16 twice: transposed (out x in, row-major) so that the
+// forward B fragments are 8 contiguous bytes per lane, and as stored (in x
+// out, row-major) for the backward products with W^T. Every kernel here runs
+// one wavefront per workgroup, so __syncthreads() is a wave barrier.
+#include "sph_internal.hpp"
+
+namespace sphjet {
+
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ bf4 pack4(float a, float b, float c, float d) {
+    bf4 r;
+    r.x = (short)f2bf(a);
+    r.y = (short)f2bf(b);
+    r.z = (short)f2bf(c);
+    r.w = (short)f2bf(d);
+    return r;
+}
+__device__ __forceinline__ bf4 load4(const uint16_t* p) { return *reinterpret_cast<const bf4*>(p); }
+__device__ __forceinline__ f4 mfma(bf4 a, bf4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 zero4() { f4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
+
+// Sum over the 64 lanes that share l % 16 (a column of a D tile), all four
+// entries: result valid in every lane.
+__device__ __forceinline__ float colsum(f4 v) {
+    float s = v.x + v.y + v.z + v.w;
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    return s;
+}
+
+// ----------------------------------------------------------------- forward
+
+// One 16-row tile through the network. X: 16 x 64 BF16 in LDS (row-major).
+// h1, h2: LDS scratch 16 x 64 BF16. Returns the layer outputs in D layout:
+// H1[nb], H2[nb] (FP32, 4 column blocks) and Y (columns 0..2 valid).
+__device__ __forceinline__ void mlp_tile_forward(const MlpView& W, const uint16_t* xs, uint16_t* h1s, uint16_t* h2s,
+                                                 f4 H1[4], f4 H2[4], f4& Y) {
+    const int l = __lane_id(), r = l & 15, g = l >> 4;
+    bf4 xa[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) xa[kb] = load4(xs + r * 64 + 16 * kb + 4 * g);
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        f4 acc = zero4();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = mfma(xa[kb], load4(W.wt1 + (16 * nb + r) * 64 + 16 * kb + 4 * g), acc);
+        const float bias = W.b1[16 * nb + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float h = tanhf(acc[i] + bias);
+            acc[i] = h;
+            h1s[(4 * g + i) * 64 + 16 * nb + r] = f2bf(h);
+        }
+        H1[nb] = acc;
+    }
+    __syncthreads();
+    bf4 ha[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) ha[kb] = load4(h1s + r * 64 + 16 * kb + 4 * g);
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        f4 acc = zero4();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = mfma(ha[kb], load4(W.wt2 + (16 * nb + r) * 64 + 16 * kb + 4 * g), acc);
+        const float bias = W.b2[16 * nb + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float h = tanhf(acc[i] + bias);
+            acc[i] = h;
+            h2s[(4 * g + i) * 64 + 16 * nb + r] = f2bf(h);
+        }
+        H2[nb] = acc;
+    }
+    __syncthreads();
+    f4 acc = zero4();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+        acc = mfma(load4(h2s + r * 64 + 16 * kb + 4 * g), load4(W.wt3 + r * 64 + 16 * kb + 4 * g), acc);
+    const float bias = W.b3[r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += bias;
+    Y = acc;
+}
+
+// Copy rows [row0, row0 + 16) of X (m x 64 BF16) into LDS, zero past m.
+__device__ __forceinline__ void load_tile(const uint16_t* X, int64_t m, int64_t row0, uint16_t* xs) {
+    const int l = __lane_id();
+    // 16 rows x 64 = 1024 BF16 = 256 x 8 bytes: four 8-byte chunks per lane
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int chunk = c * 64 + l;
+        int rr = chunk >> 4, cc = (chunk & 15) * 4;
+        bf4 v = {0, 0, 0, 0};
+        if (row0 + rr < m) v = load4(X + (row0 + rr) * 64 + cc);
+        *reinterpret_cast<bf4*>(xs + rr * 64 + cc) = v;
+    }
+    __syncthreads();
+}
+
+// Y (m x 3, row stride ystride) = network(X) for every row; one wave walks
+// the tiles. The row count is m, or *mdev when mdev is given (device-side
+// count of the closure list).
+__global__ void __launch_bounds__(64) k_mlp_forward(MlpView W, const uint16_t* X, int64_t m_host,
+                                                    const uint32_t* mdev, float* Y, int ystride) {
+    __shared__ uint16_t xs[16 * 64], h1s[16 * 64], h2s[16 * 64];
+    const int l = __lane_id(), r = l & 15, g = l >> 4;
+    const int64_t m = mdev ? (int64_t)*mdev : m_host;
+    const int64_t ntiles = (m + 15) / 16;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        load_tile(X, m, t * 16, xs);
+        f4 H1[4], H2[4], y;
+        mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
+        if (r < 3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int64_t row = t * 16 + 4 * g + i;
+                if (row < m) Y[row * ystride + r] = y[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- training
+
+// Forward and backward of the mean squared error over m rows (targets T, m x 3);
+// each wave accumulates the weight and bias gradients of its tiles in
+// registers and writes them, in the flat parameter order (W1 in x out, b1, W2,
+// b2, W3 in x 3, b3), to partial[wave]; loss_part[wave] gets its sum of
+// squared errors.
+__global__ void __launch_bounds__(64) k_mlp_grad(MlpView W, const uint16_t* X, const float* T, int64_t m,
+                                                 int tiles_per_wave, float* partial, float* loss_part) {
+    __shared__ uint16_t xs[16 * 64], h1s[16 * 64], h2s[16 * 64], ts[16 * 64];
+    const int l = __lane_id(), r = l & 15, g = l >> 4;
+    const float gscale = 2.0f / (float)(m * 3);
+    f4 dW1[4][4], dW2[4][4], dW3[4];
+    float db1[4] = {0, 0, 0, 0}, db2[4] = {0, 0, 0, 0}, db3 = 0.f, lsum = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        dW3[a] = zero4();
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { dW1[a][b] = zero4(); dW2[a][b] = zero4(); }
+    }
+    const int64_t ntiles = (m + 15) / 16;
+    for (int k = 0; k < tiles_per_wave; ++k) {
+        const int64_t t = (int64_t)blockIdx.x * tiles_per_wave + k;
+        if (t >= ntiles) break;
+        const int64_t row0 = t * 16;
+        load_tile(X, m, row0, xs);
+        f4 H1[4], H2[4], y;
+        mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
+        // output error: dY = 2 (Y - T) / (3 m) on valid rows and columns
+        f4 dY;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int64_t row = row0 + 4 * g + i;
+            float d = 0.f;
+            if (row < m && r < 3) {
+                d = y[i] - T[row * 3 + r];
+                lsum += d * d;
+            }
+            dY[i] = d * gscale;
+        }
+        // dW3 = H2^T dY, db3 = colsum(dY)
+        bf4 dyb = pack4(dY[0], dY[1], dY[2], dY[3]);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) dW3[mb] = mfma(pack4(H2[mb][0], H2[mb][1], H2[mb][2], H2[mb][3]), dyb, dW3[mb]);
+        db3 += colsum(dY);
+        // dH2 = dY W3^T: dY to A layout through LDS (16 x 16 in the first columns of ts)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ts[(4 * g + i) * 64 + r] = f2bf(dY[i]);
+        __syncthreads();
+        bf4 dya = load4(ts + r * 64 + 4 * g);
+        f4 dZ2[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            f4 acc = mfma(dya, load4(W.w3 + (16 * nb + r) * 16 + 4 * g), zero4());
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] *= 1.f - H2[nb][i] * H2[nb][i];
+            dZ2[nb] = acc;
+            db2[nb] += colsum(acc);
+        }
+        __syncthreads();
+        // dW2 = H1^T dZ2
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            bf4 a = pack4(H1[mb][0], H1[mb][1], H1[mb][2], H1[mb][3]);
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                dW2[mb][nb] = mfma(a, pack4(dZ2[nb][0], dZ2[nb][1], dZ2[nb][2], dZ2[nb][3]), dW2[mb][nb]);
+        }
+        // dH1 = dZ2 W2^T: dZ2 to A layout through LDS
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ts[(4 * g + i) * 64 + 16 * nb + r] = f2bf(dZ2[nb][i]);
+        __syncthreads();
+        bf4 dza[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) dza[kb] = load4(ts + r * 64 + 16 * kb + 4 * g);
+        f4 dZ1[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            f4 acc = zero4();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc = mfma(dza[kb], load4(W.w2 + (16 * nb + r) * 64 + 16 * kb + 4 * g), acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] *= 1.f - H1[nb][i] * H1[nb][i];
+            dZ1[nb] = acc;
+            db1[nb] += colsum(acc);
+        }
+        // dW1 = X^T dZ1: the A fragment of X^T is X in D layout, read from LDS
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            bf4 a;
+            a.x = (short)xs[(4 * g + 0) * 64 + 16 * mb + r];
+            a.y = (short)xs[(4 * g + 1) * 64 + 16 * mb + r];
+            a.z = (short)xs[(4 * g + 2) * 64 + 16 * mb + r];
+            a.w = (short)xs[(4 * g + 3) * 64 + 16 * mb + r];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                dW1[mb][nb] = mfma(a, pack4(dZ1[nb][0], dZ1[nb][1], dZ1[nb][2], dZ1[nb][3]), dW1[mb][nb]);
+        }
+        __syncthreads();
+    }
+    // write this wave's partial sums in the flat parameter order
+    float* P = partial + (size_t)blockIdx.x * MLP_NPARAMS;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int in = 16 * mb + 4 * g + i, out = 16 * nb + r;
+                P[MLP_OFF_W1 + in * 64 + out] = dW1[mb][nb][i];
+                P[MLP_OFF_W2 + in * 64 + out] = dW2[mb][nb][i];
+            }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (r < 3) P[MLP_OFF_W3 + (16 * mb + 4 * g + i) * 3 + r] = dW3[mb][i];
+    if (g == 0) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            P[MLP_OFF_B1 + 16 * nb + r] = db1[nb];
+            P[MLP_OFF_B2 + 16 * nb + r] = db2[nb];
+        }
+        if (r < 3) P[MLP_OFF_B3 + r] = db3;
+    }
+    // the wave's sum of squared errors
+    float s = lsum;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (l == 0) loss_part[blockIdx.x] = s;
+}
+
+// grad[p] = sum over waves of partial[w][p], in wave order (deterministic).
+__global__ void k_mlp_reduce(const float* partial, int nwaves, float* grad, const float* loss_part, float* loss,
+                             float loss_scale) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < MLP_NPARAMS) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += partial[(size_t)w * MLP_NPARAMS + p];
+        grad[p] = s;
+    }
+    if (p == 0 && loss) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += loss_part[w];
+        *loss = s * loss_scale;
+    }
+}
+
+// Write the BF16 copies of parameter p (FP32 master value w) in both layouts.
+__device__ __forceinline__ void write_bf16(MlpBufs B, int p, float w) {
+    uint16_t b = f2bf(w);
+    if (p < MLP_OFF_B1) {
+        int in = p / 64, out = p % 64;
+        B.wt1[out * 64 + in] = b;
+    } else if (p < MLP_OFF_W2) {
+        B.b1[p - MLP_OFF_B1] = w;
+    } else if (p < MLP_OFF_B2) {
+        int q = p - MLP_OFF_W2, in = q / 64, out = q % 64;
+        B.wt2[out * 64 + in] = b;
+        B.w2[in * 64 + out] = b;
+    } else if (p < MLP_OFF_W3) {
+        B.b2[p - MLP_OFF_B2] = w;
+    } else if (p < MLP_OFF_B3) {
+        int q = p - MLP_OFF_W3, in = q / 3, out = q % 3;
+        B.wt3[out * 64 + in] = b;
+        B.w3[in * 16 + out] = b;
+    } else {
+        B.b3[p - MLP_OFF_B3] = w;
+    }
+}
+
+// Load FP32 parameters and write their BF16 working copies.
+__global__ void k_mlp_set(MlpBufs B, const float* params) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAMS) return;
+    float w = params[p];
+    B.master[p] = w;
+    write_bf16(B, p, w);
+}
+
+// Adam on the FP32 masters (step t >= 1), then the BF16 copies.
+__global__ void k_mlp_adam(MlpBufs B, const float* grad, float lr, float b1, float b2, float eps, float c1,
+                           float c2) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAMS) return;
+    float gr = grad[p];
+    float m = b1 * B.adam_m[p] + (1.f - b1) * gr;
+    float v = b2 * B.adam_v[p] + (1.f - b2) * gr * gr;
+    B.adam_m[p] = m;
+    B.adam_v[p] = v;
+    float w = B.master[p] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    B.master[p] = w;
+    write_bf16(B, p, w);
+}
+
+// ----------------------------------------------------------------- closure
+
+// Stencil of each listed surface particle (one wave per particle): the
+// relative positions (r_b - r_a)/h of its fluid neighbours, the 32 nearest
+// kept (ties by particle id), ordered by angle in (-pi, pi] (ties: nearer,
+// then lower id), zero-padded; written as 64 BF16 values per row.
+template <typename T>
+__global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
+    const int l = __lane_id();
+    const uint32_t count = *C.count;
+    for (uint32_t row = blockIdx.x; row < count; row += gridDim.x) {
+        const uint32_t a = C.list[row];
+        const SysDev<T>& S = v.sys[tag_sys(v.tag[a])];
+        const double2 pa = v.pos[a];
+        const uint32_t ny = (uint32_t)S.ny;
+        const uint32_t local = v.cell[a] - S.cell_base;
+        const int cx = (int)(local / ny), cy = (int)(local - (uint32_t)cx * ny);
+        const int R = S.reach;
+        const int ylo = cy - R < 0 ? 0 : cy - R, yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
+        const int xlo = cx - R < 0 ? 0 : cx - R, xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
+        const unsigned long long m0 = v.nmask0[a], m1 = v.nmask1[a];
+        const bool overflow = (m1 & MASK_OVERFLOW) != 0;
+        const float ih = 1.0f / (float)S.h;
+        // candidate ordinals lane and lane + 64; slot from the row ranges
+        float dxs[2], dys[2], d2s[2], angs[2];
+        uint32_t ids[2];
+        bool val[2];
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const uint32_t o = (uint32_t)l + 64u * half;
+            val[half] = false;
+            dxs[half] = dys[half] = d2s[half] = angs[half] = 0.f;
+            ids[half] = 0u;
+            bool bit = overflow ? true : (o < 64u ? ((m0 >> o) & 1ull) : (o < MASK_BITS ? ((m1 >> (o - 64u)) & 1ull) : 0ull));
+            if (!bit) continue;
+            uint32_t ord0 = 0, b = 0xFFFFFFFFu;
+            for (int X = xlo; X <= xhi; ++X) {
+                const uint32_t rowc = S.cell_base + (uint32_t)X * ny;
+                const uint32_t b0 = v.cstart[rowc + ylo], b1 = v.cstart[rowc + yhi + 1];
+                if (o < ord0 + (b1 - b0)) { b = b0 + (o - ord0); break; }
+                ord0 += b1 - b0;
+            }
+            if (b == 0xFFFFFFFFu || b == a) continue;
+            double ex, ey;
+            double r2 = pair_r2(pa, v.pos[b], ex, ey);
+            if (overflow && !(r2 < S.R2)) continue;
+            if (tag_type(v.tag[b]) != T_FLUID) continue;
+            // relative position of b as seen from a
+            float x = -(float)ex * ih, y = -(float)ey * ih;
+            float ang = atan2f(y, x);
+            if (ang == -3.14159265358979323846f) ang = 3.14159265358979323846f;
+            val[half] = true;
+            dxs[half] = x;
+            dys[half] = y;
+            d2s[half] = x * x + y * y;
+            angs[half] = ang;
+            ids[half] = v.id[b];
+        }
+        // rank by distance (ties by id) among all items; keep the 32 nearest
+        int drank[2] = {0, 0};
+        for (int src = 0; src < 64; ++src) {
+#pragma unroll
+            for (int hs = 0; hs < 2; ++hs) {
+                const bool ov = __shfl(val[hs] ? 1 : 0, src, 64) != 0;
+                const float od = __shfl(d2s[hs], src, 64);
+                const uint32_t oi = __shfl(ids[hs], src, 64);
+#pragma unroll
+                for (int hm = 0; hm < 2; ++hm)
+                    if (ov && (od < d2s[hm] || (od == d2s[hm] && oi < ids[hm]))) ++drank[hm];
+            }
+        }
+        bool keep[2];
+#pragma unroll
+        for (int hm = 0; hm < 2; ++hm) keep[hm] = val[hm] && drank[hm] < 32;
+        // rank by angle among the kept (ties: nearer, then lower id)
+        int arank[2] = {0, 0};
+        for (int src = 0; src < 64; ++src) {
+#pragma unroll
+            for (int hs = 0; hs < 2; ++hs) {
+                const bool ok = __shfl(keep[hs] ? 1 : 0, src, 64) != 0;
+                const float oa = __shfl(angs[hs], src, 64);
+                const float od = __shfl(d2s[hs], src, 64);
+                const uint32_t oi = __shfl(ids[hs], src, 64);
+#pragma unroll
+                for (int hm = 0; hm < 2; ++hm)
+                    if (ok && (oa < angs[hm] || (oa == angs[hm] && (od < d2s[hm] || (od == d2s[hm] && oi < ids[hm])))))
+                        ++arank[hm];
+            }
+        }
+        const int nkept = __popcll(__ballot(keep[0])) + __popcll(__ballot(keep[1]));
+        uint16_t* out = C.stencil + (size_t)row * 64;
+        // zero the padding, then place every kept item at its angle rank
+        if (l >= 2 * nkept) out[l] = 0;
+#pragma unroll
+        for (int hm = 0; hm < 2; ++hm) {
+            if (keep[hm]) {
+                out[2 * arank[hm]] = f2bf(dxs[hm]);
+                out[2 * arank[hm] + 1] = f2bf(dys[hm]);
+            }
+        }
+    }
+}
+
+// Surface-tension acceleration of the listed particles from the network's
+// curvature and normal, or from the plain estimate where the network's
+// curvature deviates from it by more than the tolerance (eq. 24); completes
+// the total acceleration (eq. 25) and its eq. 30 limit.
+template <typename T>
+__global__ void k_closure_apply(EvalView<T> v, ClosureView C) {
+    const uint32_t count = *C.count;
+    for (uint32_t row = blockIdx.x * blockDim.x + threadIdx.x; row - threadIdx.x < count;
+         row += gridDim.x * blockDim.x) {
+        const bool valid = row < count;
+        uint32_t a = 0;
+        int sys = 0;
+        double dtf = __builtin_inf();
+        if (valid) {
+            a = C.list[row];
+            sys = (int)tag_sys(v.tag[a]);
+            const SysDev<T>& S = v.sys[sys];
+            const float* y = C.out + (size_t)row * 4;
+            const T h = S.h;
+            const T k_mlp = (T)y[2] / h;
+            const T k_plain = v.kappa_plain[a];
+            const V2<T> n_a = v.nrm[a];
+            const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
+            T nx = (T)y[0], ny = (T)y[1];
+            const T nm = sqrt_(nx * nx + ny * ny);
+            const bool fb = fabs(k_mlp - k_plain) > S.closure_tol * fabs(k_plain) || !(nm > T(0)) ||
+                            (v.nmask1[a] & MASK_OVERFLOW) != 0ull;
+            T kappa;
+            if (fb) {
+                kappa = k_plain;
+                nx = n_a.x / mag;
+                ny = n_a.y / mag;
+            } else {
+                kappa = k_mlp;
+                nx /= nm;
+                ny /= nm;
+            }
+            const T f = -S.sigma / v.eos[a].z * kappa * mag;
+            V2<T> acc = v.acc[a];
+            acc.x += f * nx;
+            acc.y += f * ny;
+            v.acc[a] = acc;
+            v.kappa[a] = kappa;
+            C.fallback[a] = fb ? 1u : 0u;
+            T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
+            if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
+        }
+        if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, sys, dtf, valid);
+    }
+}
+
+// ----------------------------------------------------------------- launchers
+
+void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y, int ystride, hipStream_t st) {
+    int64_t ntiles = (m + 15) / 16;
+    unsigned grid = (unsigned)(ntiles < 8192 ? (ntiles > 0 ? ntiles : 1) : 8192);
+    k_mlp_forward<<<grid, 64, 0, st>>>(W, X, m, nullptr, Y, ystride);
+}
+
+int mlp_grad_waves(int64_t m, int tiles_per_wave) {
+    int64_t ntiles = (m + 15) / 16;
+    return (int)((ntiles + tiles_per_wave - 1) / tiles_per_wave);
+}
+
+void launch_mlp_grad(const MlpView& W, const uint16_t* X, const float* T, int64_t m, int tiles_per_wave,
+                     float* partial, float* loss_part, float* grad, float* loss, hipStream_t st) {
+    int nw = mlp_grad_waves(m, tiles_per_wave);
+    if (nw < 1) nw = 1;
+    k_mlp_grad<<<nw, 64, 0, st>>>(W, X, T, m, tiles_per_wave, partial, loss_part);
+    k_mlp_reduce<<<(MLP_NPARAMS + 255) / 256, 256, 0, st>>>(partial, nw, grad, loss_part, loss,
+                                                             1.0f / (float)(m * 3));
+}
+
+void launch_mlp_set(const MlpBufs& B, const float* params, hipStream_t st) {
+    k_mlp_set<<<(MLP_NPARAMS + 255) / 256, 256, 0, st>>>(B, params);
+}
+
+void launch_mlp_adam(const MlpBufs& B, const float* grad, float lr, int t, hipStream_t st) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    k_mlp_adam<<<(MLP_NPARAMS + 255) / 256, 256, 0, st>>>(B, grad, lr, b1, b2, eps, c1, c2);
+}
+
+template <typename T>
+void launch_closure(const EvalView<T>& v, const ClosureView& C, const MlpView& W, int64_t capacity, hipStream_t st,
+                    KernelTimer* kt) {
+    kt->begin("closure_stencil", st);
+    k_stencil<T><<<4096, 64, 0, st>>>(v, C);
+    kt->end(st);
+    kt->begin("closure_mlp", st);
+    k_mlp_forward<<<2048, 64, 0, st>>>(W, C.stencil, 0, C.count, C.out, 4);
+    kt->end(st);
+    kt->begin("closure_apply", st);
+    k_closure_apply<T><<<1024, 256, 0, st>>>(v, C);
+    kt->end(st);
+    (void)capacity;
+}
+
+template void launch_closure<float>(const EvalView<float>&, const ClosureView&, const MlpView&, int64_t,
+                                    hipStream_t, KernelTimer*);
+template void launch_closure<double>(const EvalView<double>&, const ClosureView&, const MlpView&, int64_t,
+                                     hipStream_t, KernelTimer*);
+
+}  // namespace sphjet

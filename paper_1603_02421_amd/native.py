@@ -19,13 +19,17 @@ STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVIC
 FIELDS = {
     "pos": 0, "vel": 1, "rho": 2, "pressure": 3, "mass": 4, "type": 5, "drhodt": 6, "accel": 7,
     "colour": 8, "normal": 9, "curv": 10, "nflag": 11, "dt": 12, "time": 13, "nactive": 14,
-    "sort_keys": 15, "sort_perm": 16, "flags": 17, "curv_plain": 18,
+    "sort_keys": 15, "sort_perm": 16, "flags": 17, "curv_plain": 18, "stencil": 19, "closure": 20,
+    "fallback": 21,
 }
+MLP_NPARAMS = 8515
 
 # Exported entry points, as declared in include/sph.h.
 EXPORTS = [
     "sph_workspace_bytes", "sph_init", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
     "sph_sync", "sph_profile", "sph_autotune", "sph_free", "sph_last_error", "sph_abi_version",
+    "sph_set_closure", "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
+    "sph_mlp_train_step", "sph_mlp_params", "sph_mlp_free",
 ]
 
 
@@ -86,11 +90,22 @@ def load():
     L.sph_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, i32, vp]
     L.sph_free.argtypes = [vp]
     L.sph_free.restype = None
+    L.sph_set_closure.argtypes = [vp, vp]
+    L.sph_mlp_workspace_bytes.argtypes = [i64, C.POINTER(sz)]
+    L.sph_mlp_create.argtypes = [vp, i64, vp, sz, vp, C.POINTER(vp)]
+    L.sph_mlp_forward.argtypes = [vp, vp, i64, vp]
+    L.sph_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.sph_mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, vp]
+    L.sph_mlp_params.argtypes = [vp, vp]
+    L.sph_mlp_free.argtypes = [vp]
+    L.sph_mlp_free.restype = None
     L.sph_last_error.argtypes = [vp]
     L.sph_last_error.restype = C.c_char_p
     L.sph_abi_version.restype = i32
     for name in ("sph_workspace_bytes", "sph_init", "sph_step", "sph_evaluate", "sph_read",
-                 "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune"):
+                 "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune", "sph_set_closure",
+                 "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
+                 "sph_mlp_train_step", "sph_mlp_params"):
         getattr(L, name).restype = i32
     _lib = L
     return L

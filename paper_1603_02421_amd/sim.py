@@ -13,7 +13,8 @@ import numpy as np
 from . import native
 
 _VEC = {"pos", "vel", "accel", "normal"}
-_I32 = {"type", "nflag", "flags"}
+_WIDE = {"stencil": 64, "closure": 4}
+_I32 = {"type", "nflag", "flags", "fallback"}
 _I64 = {"nactive", "sort_perm"}
 _U64 = {"sort_keys"}
 _PER_SYS = {"dt", "time", "nactive"}
@@ -113,6 +114,8 @@ class Simulation:
             count = self.n
         if field in _VEC:
             out = np.zeros((count, 2), dtype=np.float64)
+        elif field in _WIDE:
+            out = np.zeros((count, _WIDE[field]), dtype=np.float64)
         elif field in _I32:
             out = np.zeros(count, dtype=np.int32)
         elif field in _I64:
@@ -140,6 +143,13 @@ class Simulation:
         native.check(self._L.sph_neighbors(self._ctx, _ptr(start), _ptr(nbr), nbr.size, C.byref(total)),
                      self._ctx)
         return start, nbr[: int(total.value)]
+
+    def set_closure(self, params: np.ndarray) -> "Simulation":
+        """Install closure network parameters (flat FP32, SPH_MLP_NPARAMS)."""
+        w = np.ascontiguousarray(params, dtype=np.float32)
+        assert w.size == native.MLP_NPARAMS
+        native.check(self._L.sph_set_closure(self._ctx, _ptr(w)), self._ctx)
+        return self
 
     def profile(self, n_steps: int) -> Dict[str, Dict[str, float]]:
         """Per-kernel average time (ms) over n_steps eager steps (advances the state)."""

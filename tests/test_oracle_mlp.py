@@ -1,0 +1,121 @@
+"""Pins of the FP64 closure reference (stencil definition and MLP)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.Generator(np.random.PCG64(1))
+    p = mlp.init_params(3)
+    for k in p:
+        p[k] = p[k] + rng.normal(0, 0.1, size=p[k].shape)
+    X = rng.normal(0, 1, size=(7, 64))
+    T = rng.normal(0, 1, size=(7, 3))
+    Y, cache = mlp.forward(p, X)
+    g = mlp.backward(p, cache, Y, T)
+    e = 1e-6
+    for k in p:
+        flat = p[k].ravel()
+        idx = rng.choice(flat.size, size=min(12, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + e
+            lp = mlp.loss(mlp.forward(p, X)[0], T)
+            flat[i] = old - e
+            lm = mlp.loss(mlp.forward(p, X)[0], T)
+            flat[i] = old
+            fd = (lp - lm) / (2 * e)
+            an = g[k].ravel()[i]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (k, i, fd, an)
+
+
+def test_zero_network_outputs_bias():
+    p = mlp.init_params(0)
+    for k in ("W1", "W2", "W3"):
+        p[k][:] = 0.0
+    p["b3"][:] = [0.5, -1.0, 2.0]
+    Y, _ = mlp.forward(p, np.ones((4, 64)))
+    assert np.all(Y == [[0.5, -1.0, 2.0]])
+
+
+def test_adam_first_step_moves_by_lr_sign():
+    p = {"w": np.array([1.0, -2.0])}
+    g = {"w": np.array([0.3, -5.0])}
+    m = {"w": np.zeros(2)}
+    v = {"w": np.zeros(2)}
+    mlp.adam_step(p, g, m, v, 1, lr=1e-2)
+    # m_hat = g, v_hat = g^2 after one step: the move is lr * g / (|g| + eps)
+    assert np.allclose(p["w"], [1.0 - 1e-2, -2.0 + 1e-2], atol=1e-9)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(2))
+    x = np.concatenate([rng.normal(0, 3, 5000), [1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -0.0, 1e-30, 65504.0]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+
+
+def test_flat_params_round_trip():
+    p = mlp.init_params(5)
+    w = mlp.flat_params(p)
+    assert w.size == mlp.N_PARAMS == 64 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+    q = mlp.unflat_params(w)
+    for k in p:
+        assert np.array_equal(p[k], q[k])
+
+
+def _lattice_stencil(angle=0.0, shift=(0.0, 0.0)):
+    s = wl.lattice_block(11, 11, dx=1.0)
+    c, sn = math.cos(angle), math.sin(angle)
+    pos = s.pos @ np.array([[c, sn], [-sn, c]]) + np.array(shift)
+    s.pos = pos
+    import oracle
+    start, nbr = oracle.neighbors(s)
+    a = 5 * 11 + 5  # the centre of the block
+    return mlp.stencil_of(a, s.pos, nbr[start[a]:start[a + 1]], s.type, s.params["h"]), s.params["h"]
+
+
+def test_lattice_stencil_geometry(orc):
+    st, h = _lattice_stencil()
+    xy = st.reshape(-1, 2) * h
+    nz = np.any(xy != 0, axis=1)
+    # within 2h = 2.6 dx of a lattice site: rings at 1, sqrt 2, 2, sqrt 5 -> 4 + 4 + 4 + 8
+    assert nz.sum() == 20
+    assert np.all(~nz[20:])
+    pts = np.rint(xy[:20]).astype(int)
+    assert np.allclose(xy[:20], pts, atol=1e-12)
+    assert sorted(map(tuple, pts)) == sorted((i, j) for i in range(-2, 3) for j in range(-2, 3)
+                                             if 0 < i * i + j * j <= 5)
+    ang = np.arctan2(pts[:, 1], pts[:, 0])
+    ang[ang == -np.pi] = np.pi
+    assert np.all(np.diff(ang) >= 0)
+    same = np.diff(ang) == 0
+    r2 = (pts ** 2).sum(1)
+    assert np.all(np.diff(r2)[same] > 0)    # collinear neighbours: nearer first
+
+
+def test_stencil_translation_invariance_and_rotation(orc):
+    base, _ = _lattice_stencil()
+    moved, _ = _lattice_stencil(shift=(123.25, -7.5))
+    assert np.allclose(base, moved, atol=1e-9)
+    rot, _ = _lattice_stencil(angle=math.pi / 2 + 1e-3)
+    # rotating the particles rotates every relative position; the angle order is
+    # the same cyclic sequence
+    a = base.reshape(-1, 2)[:20]
+    b = rot.reshape(-1, 2)[:20]
+    c, s = math.cos(math.pi / 2 + 1e-3), math.sin(math.pi / 2 + 1e-3)
+    ra = a @ np.array([[c, s], [-s, c]])
+    match = [int(np.argmin(np.linalg.norm(b - x, axis=1))) for x in ra]
+    assert sorted(match) == list(range(20))
+    assert all(np.linalg.norm(b[m] - x) < 1e-9 for m, x in zip(match, ra))
+
+
+def test_fallback_rule():
+    km = np.array([1.0, 1.3, -2.0, 0.1, 0.0])
+    kp = np.array([1.1, 1.0, -2.3, 0.0, 0.0])
+    assert list(mlp.fallback(km, kp, 0.2)) == [False, True, False, True, False]
