@@ -154,7 +154,8 @@ enum {
     SPH_F_CURV_PLAIN = 18,/* n, curvature of eq. 23 (equals CURV unless the closure is on) */
     SPH_F_STENCIL = 19,   /* n x 64, closure input of every particle the closure saw at the last
                              evaluation (BF16 values as FP64), zeros elsewhere */
-    SPH_F_CLOSURE = 20,   /* n x 4, network output (n_x, n_y, kappa h, 0) of those particles */
+    SPH_F_CLOSURE = 20,   /* n x 4, network output (n_x, n_y, kappa h, 1) of those particles,
+                             zeros elsewhere (the last entry marks the listed particles) */
     SPH_F_FALLBACK = 21,  /* n, int32, 1 where the plain curvature replaced the network's */
     SPH_F_COUNT = 22
 };

@@ -158,3 +158,75 @@ def fallback(kappa_mlp: np.ndarray, kappa_plain: np.ndarray, tol: float = 0.2) -
     """True where the plain estimate replaces the network's: a relative
     deviation above tol."""
     return np.abs(kappa_mlp - kappa_plain) > tol * np.abs(kappa_plain)
+
+
+def closure_evaluate(obj, params, tol=None) -> Dict[str, np.ndarray]:
+    """Right-hand sides with the learned closure in the surface-tension term.
+
+    Every fluid particle of a closure system (params["closure"] = 1) that
+    passes the normal filter of eq. 20 gets a stencil; the network, with its
+    weights and the stencil rounded to BF16 and everything else in FP64, gives
+    (n_x, n_y, kappa h). Its curvature and unit normal enter eq. 24 as
+    a_s = -(sigma / rho_a) kappa |n_a| n_hat, unless the network's curvature
+    differs from the plain one (eq. 23) by more than tol |kappa_plain| (default:
+    the system's closure_tol, else 0.2) or its normal is zero; then the plain
+    term stays. Returns the plain evaluation's dict with acc, kappa, asurf,
+    dt_f and dt replaced, plus: kappa_plain (eq. 23), listed (bool), X (stencils of the listed
+    particles, in id order), Y (network outputs), fallback (bool per particle).
+    """
+    import oracle
+    res = oracle.evaluate(obj)
+    start, nbr = oracle.neighbors(obj)
+    systems = obj.systems if hasattr(obj, "systems") else [obj]
+    off = np.zeros(len(systems) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([s.n for s in systems])
+    pos = np.concatenate([s.pos for s in systems])
+    rho = np.concatenate([s.rho for s in systems])
+    typ = np.concatenate([s.type for s in systems])
+    pb = {k: (bf16_round(v) if k.startswith("W") else np.asarray(v, dtype=np.float32).astype(np.float64))
+          for k, v in unflat_params(params).items()}
+    n = len(typ)
+    listed = np.zeros(n, dtype=bool)
+    fb = np.zeros(n, dtype=bool)
+    Xs, Ys = [], []
+    acc = res["acc"].copy()
+    asurf = res["asurf"].copy()
+    kappa = res["kappa"].copy()
+    for s, sysm in enumerate(systems):
+        p = sysm.params
+        if not p.get("closure", 0):
+            continue
+        lo, hi = int(off[s]), int(off[s + 1])
+        ids = np.nonzero((typ[lo:hi] == 0) & (res["nflag"][lo:hi] == 1))[0] + lo
+        if len(ids) == 0:
+            continue
+        h = float(p["h"])
+        X = bf16_round(stencils(pos, start, nbr, typ, h, ids))
+        Y, _ = forward(pb, X)
+        nh, k_mlp = closure_curvature(Y, h)
+        t = tol if tol is not None else (p.get("closure_tol", 0.0) or 0.2)
+        k_plain = res["kappa"][ids]
+        bad = fallback(k_mlp, k_plain, t) | ~np.any(nh != 0, axis=1)
+        nv = res["nrm"][ids]
+        mag = np.linalg.norm(nv, axis=1)
+        use_k = np.where(bad, k_plain, k_mlp)
+        use_n = np.where(bad[:, None], nv / mag[:, None], nh)
+        a_s = (-float(p["sigma"]) / rho[ids] * use_k * mag)[:, None] * use_n
+        acc[ids] = res["apv"][ids] + a_s + np.asarray(p["gravity"], dtype=np.float64)
+        asurf[ids] = a_s
+        kappa[ids] = use_k
+        listed[ids] = True
+        fb[ids] = bad
+        Xs.append(X)
+        Ys.append(Y)
+        # the acceleration limit of eq. 30 over the system's fluid particles
+        fl = np.nonzero(typ[lo:hi] == 0)[0] + lo
+        am = np.linalg.norm(acc[fl], axis=1)
+        am = am[am > 0]
+        dtf = float(np.min(np.sqrt(h / am))) if am.size else math.inf
+        res["dt_f"][s] = dtf
+        d = p["dt_fixed"] if p.get("dt_fixed", 0.0) > 0 else p["courant"] * min(dtf, res["dt_cv"][s])
+        res["dt"][s] = d if math.isfinite(d) else 0.0
+    res.update(kappa_plain=res["kappa"], acc=acc, asurf=asurf, kappa=kappa, listed=listed, fallback=fb,
+               X=np.concatenate(Xs) if Xs else np.zeros((0, 64)), Y=np.concatenate(Ys) if Ys else np.zeros((0, 3)))
+    return res

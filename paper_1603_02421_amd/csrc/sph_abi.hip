@@ -619,7 +619,7 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
                 if (cnt) HIP_OK(hipMemcpyAsync(rows.data(), m->cl.out, rows.size() * 4, hipMemcpyDeviceToHost, st));
                 HIP_OK(hipStreamSynchronize(st));
                 for (uint32_t k = 0; k < cnt; ++k)
-                    for (int j = 0; j < 4; ++j) out[(size_t)ids[lst[k]] * 4 + j] = j < 3 ? rows[(size_t)k * 4 + j] : 0.0;
+                    for (int j = 0; j < 4; ++j) out[(size_t)ids[lst[k]] * 4 + j] = j < 3 ? rows[(size_t)k * 4 + j] : 1.0;
             }
             break;
         }

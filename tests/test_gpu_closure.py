@@ -1,0 +1,315 @@
+"""Parity of the learned-closure kernels (through the C-ABI) with the FP64 reference.
+
+Network kernels: the reference evaluates the same BF16-rounded weights and
+inputs in FP64. The kernels also round the hidden activations to BF16 before
+each product (unit roundoff u = 2^-9); to first order, with |tanh'| <= 1, the
+output error is bounded by propagating u |H| through |W| layer by layer. The
+forward test takes twice that bound. Gradients: within 1e-2 of each parameter
+block's norm. Closure evaluation: stencils equal to one BF16 unit, listing and
+fallback decisions identical away from their thresholds, accelerations within
+1e-5 of the absolute-sum scale plus the network's bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp
+from parity_util import near_threshold_mask
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -8  # twice the BF16 unit roundoff
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _params(seed, scale=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = mlp.init_params(seed)
+    for k in p:
+        p[k] = p[k] * scale + (rng.normal(0, 0.05, size=p[k].shape) if k.startswith("b") else 0.0)
+    return mlp.flat_params(p).astype(np.float32)
+
+
+def _bf16_params(w):
+    return {k: (mlp.bf16_round(v) if k.startswith("W") else np.asarray(v, np.float32).astype(np.float64))
+            for k, v in mlp.unflat_params(w).items()}
+
+
+def _inputs(m, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return mlp.bf16_round(np.clip(rng.normal(0, 0.8, size=(m, 64)), -2, 2))
+
+
+def net_bound(pb, X, dX=None):
+    """First-order bound on |Y_kernel - Y_reference| from BF16 rounding of the
+    hidden activations (and of the inputs, when dX is given)."""
+    Y, (_, H1, H2) = mlp.forward(pb, X)
+    dZ1 = np.zeros_like(H1) if dX is None else dX @ np.abs(pb["W1"])
+    dH1 = dZ1 + U * np.abs(H1)
+    dH2 = dH1 @ np.abs(pb["W2"]) + U * np.abs(H2)
+    B = dH2 @ np.abs(pb["W3"])
+    # FP32 accumulation and tanhf: a few ulps of the absolute sums
+    B += 1e-6 * (np.abs(H2) @ np.abs(pb["W3"]) + np.abs(pb["b3"]) + 1.0)
+    return Y, B
+
+
+def _to_dev(torch, X):
+    return torch.tensor(X.astype(np.float32), device="cuda:0").to(torch.bfloat16).contiguous()
+
+
+@pytest.mark.parametrize("m", [1, 16, 37, 1000, 20_011])
+def test_forward_matches_reference(gpu, m):
+    import torch
+    from paper_1603_02421_amd.closure import Trainer
+    w = _params(3)
+    X = _inputs(m, 11 + m)
+    say(f"[mlp forward] m={m}")
+    tr = Trainer(w, m)
+    Yg = tr.forward(_to_dev(torch, X)).cpu().numpy().astype(np.float64)
+    tr.close()
+    Yo, B = net_bound(_bf16_params(w), X)
+    err = np.abs(Yg - Yo)
+    r = err / B
+    say(f"   worst err/bound {r.max():.3f}, max |err| {err.max():.3e}")
+    assert np.all(err <= B), (np.unravel_index(np.argmax(r), r.shape), err.max())
+
+
+@pytest.mark.parametrize("m", [16, 45, 4096, 30_000])
+def test_gradient_matches_reference(gpu, m):
+    import torch
+    from paper_1603_02421_amd.closure import Trainer
+    w = _params(5)
+    X = _inputs(m, 21 + m)
+    rng = np.random.Generator(np.random.PCG64(m))
+    T = rng.normal(0, 0.7, size=(m, 3))
+    say(f"[mlp gradient] m={m}")
+    tr = Trainer(w, m)
+    g, loss = tr.gradient(_to_dev(torch, X), torch.tensor(T.astype(np.float32), device="cuda:0"))
+    g = g.cpu().numpy().astype(np.float64)
+    loss = float(loss)
+    tr.close()
+    pb = _bf16_params(w)
+    Y, cache = mlp.forward(pb, X)
+    go = mlp.flat_params(mlp.backward(pb, cache, Y, np.asarray(T, np.float32).astype(np.float64)))
+    lo = mlp.loss(Y, np.asarray(T, np.float32).astype(np.float64))
+    o = 0
+    for k, size in (("W1", 4096), ("b1", 64), ("W2", 4096), ("b2", 64), ("W3", 192), ("b3", 3)):
+        a, b = g[o:o + size], go[o:o + size]
+        o += size
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        say(f"   {k}: rel-to-norm {rel:.2e}")
+        assert rel <= 1e-2, (k, rel)
+    assert abs(loss - lo) <= 1e-2 * lo
+
+
+def test_adam_steps_match_reference(gpu):
+    import torch
+    from paper_1603_02421_amd.closure import Trainer
+    m, lr = 2048, 1e-3
+    w = _params(7)
+    X = _inputs(m, 5)
+    rng = np.random.Generator(np.random.PCG64(9))
+    T = np.asarray(rng.normal(0, 0.7, size=(m, 3)), np.float32).astype(np.float64)
+    tr = Trainer(w, m)
+    Xd, Td = _to_dev(torch, X), torch.tensor(T.astype(np.float32), device="cuda:0")
+    p = {k: v.copy() for k, v in mlp.unflat_params(w).items()}
+    mo = {k: np.zeros_like(v) for k, v in p.items()}
+    vo = {k: np.zeros_like(v) for k, v in p.items()}
+    gs = []
+    for t in (1, 2, 3):
+        say(f"[adam] step {t}")
+        tr.step(Xd, Td, lr)
+        pb = {k: (mlp.bf16_round(v) if k.startswith("W") else np.asarray(v, np.float32).astype(np.float64))
+              for k, v in p.items()}
+        Y, cache = mlp.forward(pb, X)
+        g = mlp.backward(pb, cache, Y, T)
+        gs.append(np.abs(mlp.flat_params(g)))
+        mlp.adam_step(p, g, mo, vo, t, lr=lr)
+    wg = tr.params().astype(np.float64)
+    tr.close()
+    wo = mlp.flat_params(p)
+    moved_o = wo - w.astype(np.float64)
+    moved_g = wg - w.astype(np.float64)
+    # the Adam move is about lr per step in the sign of the gradient; a
+    # parameter whose gradient came near zero in some step may move either way
+    o = 0
+    for k, size in (("W1", 4096), ("b1", 64), ("W2", 4096), ("b2", 64), ("W3", 192), ("b3", 3)):
+        sl = slice(o, o + size)
+        o += size
+        clear = np.all([gt[sl] > 0.1 * np.sqrt(np.mean(gt[sl] ** 2)) for gt in gs], axis=0)
+        d = np.abs(moved_g[sl] - moved_o[sl])[clear]
+        say(f"   {k}: {clear.sum()}/{size} clear, max |move diff| {d.max():.2e} (3 lr = {3 * lr:.0e})")
+        assert np.all(d <= 0.05 * 3 * lr), k
+        # no parameter moves further than the reference's largest move
+        assert np.all(np.abs(moved_g[sl]) <= 1.01 * np.abs(moved_o[sl]).max() + 1e-7)
+
+
+# ----------------------------------------------------------------- closure evaluation
+
+def _closure_cases():
+    jet = wl.jet(n_target=20_000, nD=16, Re=500, We=20, seed=3, free_length=12.0, prefill=6.0)
+    jet.params["closure"] = 1
+    disc = wl.circle(15.0, dx=1.0, jitter=0.1, seed=2)
+    disc.params["closure"] = 1
+    plain = wl.jet(n_target=8_000, nD=12, Re=300, We=10, seed=4, free_length=8.0, prefill=4.0)
+    mixed = wl.Batch([plain, disc.copy()])   # one plain system beside a closure system
+    return dict(jet=jet, disc=disc, mixed=mixed)
+
+
+CL_CASES = _closure_cases()
+
+
+def _stencil_rows_match(g_row, o_row):
+    """Stencils agree when they hold the same points to one BF16 unit in the
+    same angular order; points whose reference angles differ by less than 1e-5
+    may swap. Returns (same points, reordered by such a tie)."""
+    gp, op = g_row.reshape(32, 2), o_row.reshape(32, 2)
+    if np.count_nonzero(np.any(gp != 0, 1)) != np.count_nonzero(np.any(op != 0, 1)):
+        return False, False
+    tol = U * np.abs(op) + 1e-30
+    if np.all(np.abs(gp - op) <= tol):
+        return True, False
+    # same set, different order?
+    k = np.count_nonzero(np.any(op != 0, 1))
+    used = np.zeros(k, bool)
+    for i in range(k):
+        d = np.all(np.abs(op[:k] - gp[i]) <= U * np.abs(op[:k]) + 1e-30, axis=1) & ~used
+        if not d.any():
+            return False, False
+        used[np.argmax(d)] = True
+    ang = np.arctan2(op[:k, 1], op[:k, 0])
+    return True, bool(np.min(np.diff(np.sort(ang))) < 1e-5)
+
+
+@pytest.mark.parametrize("name", list(CL_CASES))
+@pytest.mark.parametrize("tol", [0.2, math.inf])
+def test_closure_evaluation_fp32(gpu, orc, name, tol):
+    obj = CL_CASES[name]
+    obj = wl.Batch([wl.round_for_dtype(s, 32) for s in obj.systems]) if hasattr(obj, "systems") \
+        else wl.round_for_dtype(obj, 32)
+    systems = obj.systems if hasattr(obj, "systems") else [obj]
+    for s in systems:
+        if s.params.get("closure"):
+            s.params["closure_tol"] = 1e30 if math.isinf(tol) else tol
+    w = _params(13, scale=0.3)
+    say(f"[closure eval] case={name} tol={tol} n={obj.n}")
+    with gpu.Simulation(obj, dtype_bits=32) as sim:
+        sim.set_closure(w)
+        sim.evaluate()
+        G = dict(st=sim.read("stencil"), out=sim.read("closure"), fb=sim.read("fallback"),
+                 acc=sim.read("accel"), kappa=sim.read("curv"), kplain=sim.read("curv_plain"),
+                 nflag=sim.read("nflag"), dt=sim.read("dt"))
+    o = mlp.closure_evaluate(obj, w, tol=None)
+    start, nbr = orc.neighbors(obj)
+    typ = np.concatenate([s.type for s in systems])
+    eps = np.concatenate([np.full(s.n, s.params["eps_h"] / s.params["h"]) for s in systems])
+    hpp = np.concatenate([np.full(s.n, s.params["h"]) for s in systems])
+    excl = near_threshold_mask(o, eps, start, nbr)
+    listed_g = G["out"][:, 3] == 1.0
+    L = o["listed"]
+    say(f"   listed {L.sum()}, near-threshold excluded {excl.sum()}")
+    assert L.sum() > 0
+    assert np.array_equal(listed_g[~excl], L[~excl])
+    # stencils
+    ids = np.nonzero(L)[0]
+    row_of = {int(a): i for i, a in enumerate(ids)}
+    swapped = []
+    for a in ids:
+        if excl[a] or not listed_g[a]:
+            continue
+        same, reordered = _stencil_rows_match(G["st"][a], o["X"][row_of[int(a)]])
+        assert same, f"stencil of particle {a} differs"
+        if not reordered and not np.all(np.abs(G["st"][a] - o["X"][row_of[int(a)]])
+                                        <= U * np.abs(o["X"][row_of[int(a)]]) + 1e-30):
+            raise AssertionError(f"stencil of particle {a}: order differs away from angle ties")
+        if reordered:
+            swapped.append(int(a))
+    # network outputs, with the stencils' one-unit input differences in the bound
+    pb = _bf16_params(w)
+    Yo, B = net_bound(pb, o["X"], dX=U * np.abs(o["X"]))
+    cmp_rows = np.array([i for i, a in enumerate(ids) if not excl[a] and listed_g[a] and int(a) not in swapped],
+                        dtype=np.int64)
+    gy = G["out"][ids[cmp_rows], :3]
+    err = np.abs(gy - Yo[cmp_rows])
+    say(f"   network rows {len(cmp_rows)}, swapped {len(swapped)}, worst err/bound "
+        f"{(err / B[cmp_rows]).max() if len(cmp_rows) else 0:.3f}")
+    assert np.all(err <= B[cmp_rows])
+    # fallback decisions away from the threshold (network bound on kappa)
+    kpl = o["kappa_plain"]
+    km = Yo[:, 2] / hpp[ids]
+    dk = B[:, 2] / hpp[ids] + 1e-5 * (np.abs(kpl[ids]) + np.abs(km))
+    ctol = np.array([(s.params.get("closure_tol", 0.2)) for s in systems])
+    sys_of = np.searchsorted(np.cumsum([s.n for s in systems]), ids, side="right")
+    margin = np.abs(np.abs(km - kpl[ids]) - ctol[sys_of] * np.abs(kpl[ids]))
+    decided = (margin > dk + ctol[sys_of] * 1e-5 * np.abs(kpl[ids])) & ~excl[ids] & listed_g[ids]
+    decided &= ~np.isin(ids, swapped)
+    fb_g = G["fb"][ids] == 1
+    assert np.array_equal(fb_g[decided], o["fallback"][ids][decided])
+    say(f"   fallback {o['fallback'].sum()} of {L.sum()}, decided compared {decided.sum()}")
+    # accelerations: plain terms to 1e-5 of their scale, the surface term to
+    # the network's bound on kappa and on the unit normal
+    fl = (typ == wl.FLUID) & ~excl
+    sig = np.concatenate([np.full(s.n, s.params["sigma"]) for s in systems])
+    rho = np.concatenate([s.rho for s in systems])
+    mag = np.linalg.norm(o["nrm"], axis=1)
+    extra = np.zeros(obj.n)
+    nm = np.linalg.norm(Yo[:, :2], axis=1)
+    knet = np.abs(Yo[:, 2]) / hpp[ids]
+    extra[ids] = sig[ids] / rho[ids] * mag[ids] * (B[:, 2] / hpp[ids] + knet * 2 * np.linalg.norm(B[:, :2], axis=1)
+                                                   / np.maximum(nm, 1e-30) + 1e-5 * knet)
+    ok = fl.copy()
+    ok[ids] &= (o["fallback"][ids] == fb_g) & ~np.isin(ids, swapped)
+    err = np.linalg.norm(G["acc"] - o["acc"], axis=1)
+    lim = 1e-5 * o["s_acc"] + extra
+    r = np.where(ok, err / np.maximum(lim, 1e-300), 0.0)
+    say(f"   accel compared {ok.sum()}, worst err/limit {r.max():.3f}")
+    assert np.all(err[ok] <= lim[ok]), int(np.argmax(r))
+    # time step (eq. 30-32) of every system whose fluid particles were all compared
+    off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
+    am = np.linalg.norm(o["acc"], axis=1)
+    for k, s in enumerate(systems):
+        sl = slice(off[k], off[k + 1])
+        f = typ[sl] == wl.FLUID
+        if not np.all(ok[sl][f]):
+            say(f"   dt of system {k} not checked (excluded particles)")
+            continue
+        h, cr = s.params["h"], s.params["courant"]
+        a_hi = am[sl][f] + lim[sl][f]
+        a_lo = np.maximum(am[sl][f] - lim[sl][f], 0.0)
+        lo = cr * min(np.min(np.sqrt(h / a_hi[a_hi > 0])), o["dt_cv"][k])
+        hi = cr * min(np.min(np.sqrt(h / np.maximum(a_lo, 1e-300))), o["dt_cv"][k])
+        assert lo * (1 - 1e-5) <= G["dt"][k] <= hi * (1 + 1e-5), (k, G["dt"][k], lo, hi)
+
+
+def test_closure_in_the_time_loop_with_fallback_everywhere(gpu, orc):
+    """A zero network makes every listed particle fall back to eq. 23-24, so a
+    closure run must follow the plain run (same kernels otherwise) to rounding."""
+    base = wl.round_for_dtype(wl.jet(n_target=12_000, nD=12, Re=400, We=15, seed=6, free_length=8.0,
+                                     prefill=4.0), 32)
+    cl = base.copy()
+    cl.params = dict(base.params, closure=1)
+    say("[closure loop] 30 steps plain vs zero-network closure")
+    with gpu.Simulation(base, dtype_bits=32) as a, gpu.Simulation(cl, dtype_bits=32) as b:
+        b.set_closure(np.zeros(gpu.native.MLP_NPARAMS, np.float32))
+        a.step(30)
+        b.step(30)
+        pa, pb_ = a.read("pos"), b.read("pos")
+        ra, rb = a.read("rho"), b.read("rho")
+        fb = b.read("fallback")
+        out = b.read("closure")
+    dx = base.meta["dx"]
+    assert (out[:, 3] == 1).sum() > 0 and np.all(fb[out[:, 3] == 1] == 1)
+    assert np.abs(pa - pb_).max() <= 1e-4 * dx
+    assert np.abs(ra - rb).max() <= 1e-4
+
+
+def test_closure_requires_closure_system(gpu):
+    s = wl.round_for_dtype(wl.lattice_block(8, 8), 32)
+    with gpu.Simulation(s, dtype_bits=32) as sim:
+        with pytest.raises(gpu.native.SphError):
+            sim.set_closure(np.zeros(gpu.native.MLP_NPARAMS, np.float32))

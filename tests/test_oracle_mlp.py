@@ -119,3 +119,55 @@ def test_fallback_rule():
     km = np.array([1.0, 1.3, -2.0, 0.1, 0.0])
     kp = np.array([1.1, 1.0, -2.3, 0.0, 0.0])
     assert list(mlp.fallback(km, kp, 0.2)) == [False, True, False, True, False]
+
+
+def _closure_disc():
+    d = wl.circle(10.0, dx=1.0, layout="rings")
+    d.params["closure"] = 1
+    return d
+
+
+def test_closure_with_zero_network_falls_back_to_plain(orc):
+    d = _closure_disc()
+    r = mlp.closure_evaluate(d, np.zeros(mlp.N_PARAMS))
+    o = orc.evaluate(d)
+    listed = (d.type == wl.FLUID) & (o["nflag"] == 1)
+    assert listed.sum() > 50 and np.array_equal(r["listed"], listed)
+    # kappa_mlp = 0 and a zero normal: every listed particle keeps eq. 23-24
+    assert np.all(r["fallback"][listed])
+    scale = np.abs(o["acc"]).max()
+    assert np.allclose(r["acc"], o["acc"], rtol=0, atol=1e-12 * scale)
+    assert np.array_equal(r["kappa"], o["kappa"])
+
+
+def test_closure_replaces_the_surface_term(orc):
+    # a network that always answers "flat" (kappa = 0) with no fallback removes
+    # the surface-tension term of the listed particles and nothing else
+    d = _closure_disc()
+    w = np.zeros(mlp.N_PARAMS)
+    w[-3:] = [1.0, 0.0, 0.0]
+    r = mlp.closure_evaluate(d, w, tol=np.inf)
+    o = orc.evaluate(d)
+    L = r["listed"]
+    assert not r["fallback"].any()
+    assert np.allclose(r["acc"][L], o["apv"][L] + np.asarray(d.params["gravity"]), rtol=0, atol=1e-15)
+    assert np.array_equal(r["acc"][~L], o["acc"][~L])
+    assert np.all(r["kappa"][L] == 0.0)
+    # the plain surface force on the disc rim points to the centre
+    rim = L & (np.hypot(d.pos[:, 0], d.pos[:, 1]) > 9.0)
+    assert np.all(np.einsum("ij,ij->i", o["asurf"][rim], d.pos[rim]) < 0)
+
+
+def test_rim_stencils_lean_inward(orc):
+    d = _closure_disc()
+    r = mlp.closure_evaluate(d, np.zeros(mlp.N_PARAMS))
+    ids = np.nonzero(r["listed"])[0]
+    rim = np.hypot(d.pos[ids, 0], d.pos[ids, 1]) > 9.0
+    X = r["X"].reshape(len(ids), 32, 2)
+    mean = X.sum(1)
+    assert rim.sum() > 30
+    assert np.all(np.einsum("ij,ij->i", mean[rim], d.pos[ids][rim]) < 0)
+    # every stencil entry is a fluid neighbour inside the support, in BF16
+    rr = np.linalg.norm(X, axis=2)
+    assert np.all(rr <= 2.0 + 2 ** -7)
+    assert np.array_equal(mlp.bf16_round(r["X"]), r["X"])
