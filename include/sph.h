@@ -154,7 +154,7 @@ enum {
     SPH_F_CURV_PLAIN = 18,/* n, curvature of eq. 23 (equals CURV unless the closure is on) */
     SPH_F_STENCIL = 19,   /* n x 64, closure input of every particle the closure saw at the last
                              evaluation (BF16 values as FP64), zeros elsewhere */
-    SPH_F_CLOSURE = 20,   /* n x 4, network output (n_x, n_y, kappa h, 1) of those particles,
+    SPH_F_CLOSURE = 20,   /* n x 4, network output (n_1, n_2, kappa h, 1) of those particles,
                              zeros elsewhere (the last entry marks the listed particles) */
     SPH_F_FALLBACK = 21,  /* n, int32, 1 where the plain curvature replaced the network's */
     SPH_F_COUNT = 22
@@ -228,10 +228,13 @@ sph_status sph_autotune(const sph_options* opt, int32_t n_sys, const sph_params*
  *
  * For every fluid particle that passes the normal filter (eq. 20), the
  * closure builds a stencil -- the relative positions (r_b - r_a)/h of its
- * fluid neighbours within 2h, the 32 nearest (ties by particle id), ordered by
- * angle in (-pi, pi] (ties: nearer, then lower id), zero-padded to 32 pairs --
- * and feeds it to a 64 -> 64 -> 64 -> 3 network (tanh hidden layers, linear
- * output (n_x, n_y, kappa h)) evaluated on BF16 matrix cores with FP32
+ * fluid neighbours within 2h, the 32 nearest (ties by particle id), written in
+ * the particle's own frame e1 = n_a/|n_a| (the colour gradient of eq. 18,
+ * pointing into the liquid), e2 = e1 turned by +90 degrees, ordered by their
+ * angle in that frame in (-pi, pi] (ties: nearer, then lower id), zero-padded
+ * to 32 pairs -- and feeds it to a 64 -> 64 -> 64 -> 3 network (tanh hidden
+ * layers, linear output (n_1, n_2, kappa h): the interface normal in the
+ * frame (e1, e2) and the curvature) evaluated on BF16 matrix cores with FP32
  * accumulation. The network's curvature and unit normal replace those of
  * eq. 21-23 in the surface-tension acceleration of eq. 24,
  * a_s = -(sigma / rho_a) kappa |n_a| n_hat, except where the network's

@@ -2,14 +2,18 @@
 
 Stencil of a surface particle a: the relative positions (r_b - r_a)/h of its
 fluid neighbours (r_ab < 2h, b != a); at most the 32 nearest are kept (ties by
-particle id), then ordered by angle atan2(y, x) in (-pi, pi] (ties: nearer
-first, then lower id), and zero-padded to 32 entries; the network input is
+particle id). Each is written in the particle's frame: e1 = n_a/|n_a|, the
+unit colour gradient of eq. 18 (pointing into the liquid), and e2 = e1 turned
+by +90 degrees, so the entry is (d.e1, d.e2) for d = (r_b - r_a)/h. Entries are
+ordered by their angle atan2(d.e2, d.e1) in (-pi, pi] (ties: nearer first,
+then lower id) and zero-padded to 32; the network input is
 (x0, y0, x1, y1, ...), 64 numbers.
 
 Network: 64 -> 64 -> 64 -> 3, tanh on both hidden layers, linear output
-(n_x, n_y, kappa h). Loss: mean squared error over the batch and the three
-outputs, equal weights. Training: Adam on FP32 master weights whose BF16
-copies feed the forward pass.
+(n_1, n_2, kappa h): the interface normal in the frame (e1, e2) and the
+curvature. Loss: mean squared error over the batch and the three outputs,
+equal weights. Training: Adam on FP32 master weights whose BF16 copies feed
+the forward pass.
 
 Everything here is plain numpy in float64: definitions written out, no
 blocking, so it can be read against the description above.
@@ -27,21 +31,30 @@ N_IN, N_H, N_OUT = 64, 64, 3
 
 # ----------------------------------------------------------------- stencils
 
-def stencil_of(a: int, pos: np.ndarray, nbrs, types: np.ndarray, h: float) -> np.ndarray:
+def frame(n_a) -> Tuple[np.ndarray, np.ndarray]:
+    """(e1, e2): the unit colour gradient and its +90 degree turn."""
+    e1 = np.asarray(n_a, dtype=np.float64) / math.hypot(float(n_a[0]), float(n_a[1]))
+    return e1, np.array([-e1[1], e1[0]])
+
+
+def stencil_of(a: int, pos: np.ndarray, nbrs, types: np.ndarray, h: float, n_a) -> np.ndarray:
     """64-vector stencil of particle a from its neighbour list (ids b != a with
-    r_ab < 2h). Only fluid neighbours enter."""
+    r_ab < 2h) and its colour gradient n_a. Only fluid neighbours enter."""
+    e1, e2 = frame(n_a)
     cand = [b for b in nbrs if types[b] == 0]
     d = [(float((pos[b, 0] - pos[a, 0]) ** 2 + (pos[b, 1] - pos[a, 1]) ** 2), int(b)) for b in cand]
     d.sort()
     keep = [b for _, b in d[:K_STENCIL]]
     items = []
     for b in keep:
-        x = (pos[b, 0] - pos[a, 0]) / h
-        y = (pos[b, 1] - pos[a, 1]) / h
+        dx = (pos[b, 0] - pos[a, 0]) / h
+        dy = (pos[b, 1] - pos[a, 1]) / h
+        x = dx * e1[0] + dy * e1[1]
+        y = dx * e2[0] + dy * e2[1]
         ang = math.atan2(y, x)
         if ang == -math.pi:
             ang = math.pi
-        items.append((ang, x * x + y * y, b, x, y))
+        items.append((ang, dx * dx + dy * dy, b, x, y))
     items.sort(key=lambda t: (t[0], t[1], t[2]))
     out = np.zeros(2 * K_STENCIL)
     for i, (_, _, _, x, y) in enumerate(items):
@@ -50,9 +63,10 @@ def stencil_of(a: int, pos: np.ndarray, nbrs, types: np.ndarray, h: float) -> np
     return out
 
 
-def stencils(pos, start, nbr, types, h, which) -> np.ndarray:
-    """Stencils of the particles `which` (ids) from CSR neighbour lists."""
-    return np.stack([stencil_of(int(a), pos, nbr[start[a]:start[a + 1]], types, h) for a in which]) \
+def stencils(pos, start, nbr, types, h, which, nrm) -> np.ndarray:
+    """Stencils of the particles `which` (ids) from CSR neighbour lists and
+    colour gradients nrm (n x 2)."""
+    return np.stack([stencil_of(int(a), pos, nbr[start[a]:start[a + 1]], types, h, nrm[a]) for a in which]) \
         if len(which) else np.zeros((0, 2 * K_STENCIL))
 
 
@@ -146,9 +160,12 @@ N_PARAMS = N_IN * N_H + N_H + N_H * N_H + N_H + N_H * N_OUT + N_OUT
 
 # ----------------------------------------------------------------- closure
 
-def closure_curvature(Y: np.ndarray, h: np.ndarray):
-    """Network output -> (unit normal, kappa)."""
-    nrm = Y[:, :2]
+def closure_curvature(Y: np.ndarray, h, n_a: np.ndarray):
+    """Network output and the particles' colour gradients -> (unit normal in
+    x, y, kappa)."""
+    e1 = n_a / np.linalg.norm(n_a, axis=1, keepdims=True)
+    e2 = np.stack([-e1[:, 1], e1[:, 0]], axis=1)
+    nrm = Y[:, :1] * e1 + Y[:, 1:2] * e2
     m = np.linalg.norm(nrm, axis=1, keepdims=True)
     nh = np.where(m > 0, nrm / np.where(m > 0, m, 1.0), 0.0)
     return nh, Y[:, 2] / h
@@ -166,7 +183,8 @@ def closure_evaluate(obj, params, tol=None) -> Dict[str, np.ndarray]:
     Every fluid particle of a closure system (params["closure"] = 1) that
     passes the normal filter of eq. 20 gets a stencil; the network, with its
     weights and the stencil rounded to BF16 and everything else in FP64, gives
-    (n_x, n_y, kappa h). Its curvature and unit normal enter eq. 24 as
+    (n_1, n_2, kappa h) in the frame of the colour gradient. Its curvature and
+    unit normal enter eq. 24 as
     a_s = -(sigma / rho_a) kappa |n_a| n_hat, unless the network's curvature
     differs from the plain one (eq. 23) by more than tol |kappa_plain| (default:
     the system's closure_tol, else 0.2) or its normal is zero; then the plain
@@ -201,9 +219,9 @@ def closure_evaluate(obj, params, tol=None) -> Dict[str, np.ndarray]:
         if len(ids) == 0:
             continue
         h = float(p["h"])
-        X = bf16_round(stencils(pos, start, nbr, typ, h, ids))
+        X = bf16_round(stencils(pos, start, nbr, typ, h, ids, res["nrm"]))
         Y, _ = forward(pb, X)
-        nh, k_mlp = closure_curvature(Y, h)
+        nh, k_mlp = closure_curvature(Y, h, res["nrm"][ids])
         t = tol if tol is not None else (p.get("closure_tol", 0.0) or 0.2)
         k_plain = res["kappa"][ids]
         bad = fallback(k_mlp, k_plain, t) | ~np.any(nh != 0, axis=1)

@@ -1,25 +1,35 @@
 """Learned curvature closure: training data, training loop and accuracy.
 
 The network and its kernels live in the library (sph_mlp_* and the closure
-path of the particle update, include/sph.h); this module marshals data:
+path of the particle update, include/sph.h); this module marshals data.
 
-* training stencils come from the library's own stencil kernel, run on
-  particle sets whose interface is known: discs (radius 3-50 dx) and
-  sinusoidal interfaces (amplitude 0.5-5 dx, wavelength 10-60 dx), on a
-  jittered lattice and randomly rotated, labelled with the exact unit normal
-  and curvature; and jet snapshots subsampled from a run at 4x resolution,
-  labelled with that run's plain estimate (eq. 18-23) at the kept particles;
-* targets are (n_x, n_y, kappa h) with the normal pointing into the liquid
-  (the direction of grad C) and kappa = div n_hat (negative on a convex
-  liquid surface);
-* training runs sph_mlp_train_step (forward, backward and Adam on the GPU).
+Training neighbourhoods come from the library's own stencil kernel, run on
+two kinds of particle sets whose interface geometry is known:
+
+* discs (radius 3-50 dx) and sinusoidal interfaces (amplitude 0.5-5 dx,
+  wavelength 10-60 dx) on a jittered lattice, randomly rotated, labelled with
+  the exact unit normal and curvature of the interface at the particle's
+  nearest interface point (particles within 2h of the interface);
+* jets: a jet run at 4x the target resolution is Poisson-disk subsampled to
+  the target spacing; the coarse set is labelled by the fine run's plain
+  estimate (eq. 18-23), averaged with Wendland weights of the coarse h over
+  the fine interface particles around each coarse particle.
+
+Only interface particles (see INTERFACE_NH) enter the training sets and the
+accuracy figures.
+
+Targets are (n_1, n_2, kappa h): the unit normal pointing into the liquid (the
+direction of grad C) written in the particle's frame (e1 = its unit colour
+gradient, e2 = e1 turned by +90 degrees), and kappa = div n_hat (negative on a
+convex liquid surface), as in eq. 23. Training runs sph_mlp_train_step (forward, backward
+and Adam on the GPU).
 """
 from __future__ import annotations
 
 import ctypes as C
 import math
 import os
-from typing import Dict, List, Tuple
+from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 
@@ -27,6 +37,12 @@ from . import native
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "closure_weights.npz")
+
+# Interface particles for labels and accuracy figures: |n| h >= INTERFACE_NH.
+# The colour gradient (eq. 18) is about 0.1-0.15/h in the two outer particle
+# layers of a free surface and at most a few hundredths of 1/h deeper, where the filter of eq. 20
+# (|n| > 0.01/h) still passes particles whose stencil does not see the surface.
+INTERFACE_NH = 0.05
 
 
 def _ptr(t):
@@ -48,6 +64,7 @@ class Trainer:
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         w = np.ascontiguousarray(params, dtype=np.float32)
+        assert w.size == native.MLP_NPARAMS
         h = C.c_void_p()
         native.check(L.sph_mlp_create(w.ctypes.data_as(C.c_void_p), self.max_batch, _ptr(self.ws),
                                       int(nbytes.value), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -55,14 +72,12 @@ class Trainer:
         self.loss_dev = torch.zeros(4, dtype=torch.float32, device=self.device)
 
     def forward(self, X):
-        torch = self.torch
-        Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device=self.device)
+        Y = self.torch.empty((X.shape[0], 3), dtype=self.torch.float32, device=self.device)
         native.check(self._L.sph_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(Y)))
         return Y
 
     def gradient(self, X, T):
-        torch = self.torch
-        g = torch.empty(native.MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        g = self.torch.empty(native.MLP_NPARAMS, dtype=self.torch.float32, device=self.device)
         native.check(self._L.sph_mlp_gradient(self._h, _ptr(X), _ptr(T), X.shape[0], _ptr(g), _ptr(self.loss_dev)))
         return g, self.loss_dev[0]
 
@@ -100,12 +115,11 @@ def xavier_params(seed: int = 0) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-# ----------------------------------------------------------------- data
+# ----------------------------------------------------------------- shapes
 
-def _rotate(xy, th, c=(0.0, 0.0)):
+def _rotate(xy, th):
     cs, sn = math.cos(th), math.sin(th)
-    R = np.array([[cs, -sn], [sn, cs]])
-    return (xy - c) @ R.T
+    return xy @ np.array([[cs, sn], [-sn, cs]])
 
 
 def _jittered_lattice(x0, y0, nx, ny, dx, jitter, rng):
@@ -116,167 +130,278 @@ def _jittered_lattice(x0, y0, nx, ny, dx, jitter, rng):
     return p
 
 
-def shape_systems(n_shapes: int, seed: int, dx: float = 1.0):
-    """Discs and sinusoidal slabs with their exact interface geometry.
+def _disc_label(q, R, dx):
+    r = np.hypot(q[:, 0], q[:, 1])
+    nh = -q / np.maximum(r, 1e-12)[:, None]
+    return nh, np.full(len(q), -1.0 / R), r > R - 2.6 * dx
 
-    Returns (systems, label functions): label(pos) -> (n_hat (k, 2), kappa (k,),
-    keep mask (k,)) in the system's own coordinates."""
+
+def _sine_label(q, A, kk, lam, dx):
+    """Normal and curvature of y = A sin(kk x) at the interface point nearest
+    to each particle (Newton on the squared distance), liquid below."""
+    x = q[:, 0].copy()
+    for _ in range(20):
+        f = A * np.sin(kk * x)
+        f1 = A * kk * np.cos(kk * x)
+        f2 = -A * kk * kk * np.sin(kk * x)
+        g = (x - q[:, 0]) + (f - q[:, 1]) * f1
+        g1 = 1.0 + f1 * f1 + (f - q[:, 1]) * f2
+        x = x - g / g1
+    f1 = A * kk * np.cos(kk * x)
+    den = np.sqrt(1 + f1 * f1)
+    nh = np.stack([f1 / den, -1.0 / den], axis=1)
+    kap = -A * kk * kk * np.sin(kk * x) / den ** 3
+    dist = np.hypot(x - q[:, 0], A * np.sin(kk * x) - q[:, 1])
+    keep = (q[:, 0] > lam) & (q[:, 0] < 3 * lam) & (dist < 2.6 * dx)
+    return nh, kap, keep
+
+
+def shape_systems(n_shapes: int, seed: int, dx: float = 1.0):
+    """Discs and sinusoidal slabs with their exact interface geometry, each
+    randomly rotated and jittered. meta["label"](unrotated positions) returns
+    (unit normal, kappa, keep mask)."""
     import workloads as wl
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
+    h = 1.3 * dx
     for k in range(n_shapes):
-        jitter = float(rng.choice([0.0, 0.05, 0.1, 0.2]))
+        jitter = float(rng.choice([0.0, 0.02, 0.05, 0.1]))
         th = float(rng.uniform(0, 2 * math.pi))
         if k % 2 == 0:
-            R = float(rng.uniform(3.0, 50.0))
+            R = float(math.exp(rng.uniform(math.log(3.0), math.log(50.0)))) * dx
             n = int(math.ceil(R / dx)) + 1
             p = _jittered_lattice(-n * dx, -n * dx, 2 * n, 2 * n, dx, jitter, rng)
             p = p[np.hypot(p[:, 0], p[:, 1]) < R]
-
-            def label(q, R=R):
-                r = np.hypot(q[:, 0], q[:, 1])
-                nh = -q / np.maximum(r, 1e-12)[:, None]
-                return nh, np.full(len(q), -1.0 / R), r > R - 3.0 * dx
+            label = (lambda q, R=R: _disc_label(q, R, dx))
         else:
             A = float(rng.uniform(0.5, 5.0)) * dx
             lam = float(rng.uniform(10.0, 60.0)) * dx
             kk = 2 * math.pi / lam
-            L = 4 * lam
-            depth = 10.0 * dx
-            base = _jittered_lattice(0.0, -depth - A, int(L / dx), int((depth + 2 * A) / dx) + 2, dx, jitter, rng)
+            depth = 8.0 * dx
+            base = _jittered_lattice(0.0, -depth - A, int(4 * lam / dx), int((depth + 2 * A) / dx) + 2, dx,
+                                     jitter, rng)
             p = base[base[:, 1] < A * np.sin(kk * base[:, 0])]
-
-            def label(q, A=A, kk=kk, lam=lam, dx=dx):
-                x = q[:, 0]
-                s = A * kk * np.cos(kk * x)
-                den = np.sqrt(1 + s * s)
-                nh = np.stack([s / den, -1.0 / den], axis=1)
-                kap = -A * kk * kk * np.sin(kk * x) / den ** 3
-                keep = (x > lam) & (x < 3 * lam) & (np.abs(q[:, 1] - A * np.sin(kk * x)) < 3.0 * dx)
-                return nh, kap, keep
-        # rotate the particle set; labels are evaluated in the unrotated frame
-        sysm = wl.scenarios._assemble(wl.scenarios.default_params(1.3 * dx, 1.0, 10.0, sigma=1.0, alpha=0.05,
-                                                                   closure=1),
-                                      [(_rotate(p, th), (0.0, 0.0), 1.0, wl.FLUID)])
-        lo = sysm.pos.min(0) - 4 * dx
-        hi = sysm.pos.max(0) + 4 * dx
-        sysm.params.update(box_lo=tuple(lo), box_hi=tuple(hi), cell_size=2.2 * 1.3 * dx)
-        sysm.meta = dict(theta=th, label=label)
-        out.append(sysm)
+            label = (lambda q, A=A, kk=kk, lam=lam: _sine_label(q, A, kk, lam, dx))
+        pr = _rotate(p, th)
+        lo, hi = pr.min(0) - 4 * dx, pr.max(0) + 4 * dx
+        par = wl.scenarios.default_params(h, 1.0, 10.0, sigma=1.0, alpha=0.05, closure=1, box_lo=tuple(lo),
+                                          box_hi=tuple(hi))
+        s = wl.scenarios._assemble(par, [(pr, (0.0, 0.0), 1.0, wl.FLUID)], name="shape")
+        s.meta = dict(theta=th, label=label)
+        out.append(s)
     return out
 
 
-def harvest(systems, device="cuda:0", chunk_particles: int = 1_500_000):
-    """Run the closure's stencil kernel on the systems (GPU) and return, for
-    every listed particle, (stencil, target (n_x, n_y, kappa h), plain kappa h)."""
-    from .sim import Simulation
-    X, T, P = [], [], []
+def _chunks(systems, max_particles):
     i = 0
     while i < len(systems):
         grp, n = [], 0
-        while i < len(systems) and (n + systems[i].n <= chunk_particles or not grp):
+        while i < len(systems) and (n + systems[i].n <= max_particles or not grp):
             grp.append(systems[i])
             n += systems[i].n
             i += 1
+        yield grp
+
+
+def _listed_rows(sim, hpp):
+    """Stencils, plain curvature, the listed interface particles
+    (|n| h >= INTERFACE_NH) and the unit colour gradients e1 of a closure
+    evaluation; hpp: h per particle."""
+    sim.evaluate()
+    st = sim.read("stencil")
+    listed = sim.read("closure")[:, 3] == 1.0
+    n = sim.read("normal")
+    mag = np.linalg.norm(n, axis=1)
+    e1 = n / np.maximum(mag, 1e-300)[:, None]
+    return st, sim.read("curv_plain"), listed & (mag * hpp >= INTERFACE_NH), e1
+
+
+def to_frame(v: np.ndarray, e1: np.ndarray) -> np.ndarray:
+    """Vectors v (k x 2) in the frames (e1, e2 = e1 turned by +90 degrees)."""
+    return np.stack([v[:, 0] * e1[:, 0] + v[:, 1] * e1[:, 1], v[:, 1] * e1[:, 0] - v[:, 0] * e1[:, 1]], axis=1)
+
+
+def _hpp(grp):
+    return np.concatenate([np.full(s.n, s.params["h"]) for s in grp])
+
+
+def harvest_shapes(systems, device="cuda:0", chunk_particles: int = 2_000_000):
+    """(stencils, targets (n_1, n_2, kappa h), plain kappa h) of every listed
+    particle near the interface of the shapes."""
+    from .sim import Simulation
+    X, T, P = [], [], []
+    for grp in _chunks(systems, chunk_particles):
         with Simulation(grp, dtype_bits=32, device=device) as sim:
-            sim.evaluate()
-            st = sim.read("stencil")
-            listed = np.any(st != 0, axis=1)
-            kplain = sim.read("curv_plain")
-            pos = sim.read("pos")
+            st, kplain, listed, e1 = _listed_rows(sim, _hpp(grp))
         o = 0
         for s in grp:
             sl = slice(o, o + s.n)
             o += s.n
             h = s.params["h"]
             th = s.meta["theta"]
-            q = _rotate(pos[sl], -th)
-            nh, kap, keep = s.meta["label"](q)
+            nh, kap, keep = s.meta["label"](_rotate(s.pos, -th))
             m = listed[sl] & keep
-            nh_rot = _rotate(nh, th)
             X.append(st[sl][m])
-            T.append(np.concatenate([nh_rot[m], (kap[m] * h)[:, None]], axis=1))
+            T.append(np.concatenate([to_frame(_rotate(nh, th)[m], e1[sl][m]), (kap[m] * h)[:, None]], axis=1))
             P.append(kplain[sl][m] * h)
     return np.concatenate(X), np.concatenate(T), np.concatenate(P)
 
 
+# ----------------------------------------------------------------- jets
+
 def poisson_subsample(pos: np.ndarray, rmin: float, seed: int) -> np.ndarray:
-    """Indices of a greedy Poisson-disk subset: visited in seeded random order,
-    a point is kept when no kept point lies closer than rmin."""
+    """Indices of a greedy Poisson-disk subset: points are visited in seeded
+    random order and kept when no kept point lies closer than rmin."""
     rng = np.random.Generator(np.random.PCG64(seed))
     order = rng.permutation(len(pos))
-    cs = rmin / math.sqrt(2.0)
+    cs = rmin / math.sqrt(2.0)   # at most one kept point per grid cell
     lo = pos.min(0)
-    grid: Dict[Tuple[int, int], int] = {}
+    g = np.floor((pos - lo) / cs).astype(np.int64)
+    ny = int(g[:, 1].max()) + 5
+    occ: Dict[int, int] = {}
     kept = []
     r2 = rmin * rmin
+    offs = [(a, b) for a in range(-2, 3) for b in range(-2, 3)]
     for i in order:
-        gx, gy = int((pos[i, 0] - lo[0]) / cs), int((pos[i, 1] - lo[1]) / cs)
+        gx, gy = int(g[i, 0]), int(g[i, 1])
+        px, py = pos[i, 0], pos[i, 1]
         ok = True
-        for ax in range(gx - 2, gx + 3):
-            for ay in range(gy - 2, gy + 3):
-                j = grid.get((ax, ay))
-                if j is not None:
-                    d = pos[j] - pos[i]
-                    if d[0] * d[0] + d[1] * d[1] < r2:
-                        ok = False
-                        break
-            if not ok:
-                break
+        for a, b in offs:
+            j = occ.get((gx + a) * ny + gy + b)
+            if j is not None:
+                dx, dy = pos[j, 0] - px, pos[j, 1] - py
+                if dx * dx + dy * dy < r2:
+                    ok = False
+                    break
         if ok:
-            grid[(gx, gy)] = i
+            occ[gx * ny + gy] = i
             kept.append(i)
     return np.array(sorted(kept), dtype=np.int64)
 
 
-def jet_harvest(nD_coarse: int = 10, seeds=(0,), steps: int = 300, n_fine: int = 300_000, Re: float = 500.0,
-                We: float = 20.0, window: float = 25.0, device="cuda:0"):
-    """Jet neighbourhoods at resolution D/nD_coarse labelled by the plain
-    estimate of a run at 4x resolution (D/(4 nD_coarse)).
+def _wendland(q):
+    return np.where(q < 2.0, (1 - q / 2) ** 4 * (1 + 2 * q), 0.0)
 
-    The fine jet runs `steps` steps; its particles within `window` D of the
-    orifice are Poisson-disk subsampled to the coarse spacing and re-evaluated
-    at the coarse h. Targets: the fine run's unit normal and curvature at the
-    kept particles that the fine run also filtered as interface (N = 1)."""
+
+def fine_jet_snapshots(nD_coarse: int, Re: float, We: float, seed: int, steps: Sequence[int],
+                       n_fine: int = 300_000, free_length: float = 30.0, piston_amp: float = 0.01,
+                       device="cuda:0"):
+    """Run a jet at 4 nD_coarse particles per D (piston velocity amplitude
+    `piston_amp`) and return snapshots (fluid positions, unit normals, plain
+    curvature and filter flags) after each step count in `steps` (ascending)."""
     import workloads as wl
     from .sim import Simulation
-    Xs, Ts, Ps = [], [], []
-    for seed in seeds:
-        fine = wl.round_for_dtype(wl.jet(n_target=n_fine, nD=4 * nD_coarse, Re=Re, We=We, seed=seed,
-                                         free_length=window + 5.0, prefill=window), 32)
-        with Simulation(fine, dtype_bits=32, device=device) as sim:
-            sim.step(steps)
+    fine = wl.round_for_dtype(wl.jet(n_target=n_fine, nD=4 * nD_coarse, Re=Re, We=We, seed=seed,
+                                     free_length=free_length, prefill=free_length / 3), 32)
+    fine.params["piston_amp"] = float(piston_amp)
+    t_plate = 3 * fine.meta["dx"]
+    snaps = []
+    done = 0
+    with Simulation(fine, dtype_bits=32, device=device, graph_steps=50) as sim:
+        for st in steps:
+            if st > done:
+                sim.step(st - done)
+                done = st
             sim.evaluate()
-            pos = sim.read("pos")
             typ = sim.read("type")
+            pos = sim.read("pos")
+            sel = (typ == wl.FLUID) & (pos[:, 0] > t_plate + 0.5)
             nrm = sim.read("normal")
-            kap = sim.read("curv")
-            nfl = sim.read("nflag")
-        dxc = 1.0 / nD_coarse
-        region = (typ != wl.INACTIVE) & (pos[:, 0] > -2.0) & (pos[:, 0] < window)
-        idx = np.nonzero(region)[0]
-        keep = idx[poisson_subsample(pos[idx], 1.05 * dxc, seed)]
-        hc = 1.3 * dxc
-        p = wl.scenarios.jet_params(nD_coarse, Re, We)
-        p.update(closure=1, box_lo=tuple(pos[keep].min(0) - 4 * dxc), box_hi=tuple(pos[keep].max(0) + 4 * dxc),
-                 cell_size=2.2 * hc)
-        coarse = wl.System(p, pos[keep].copy(), np.zeros((len(keep), 2)), np.ones(len(keep)),
-                           np.full(len(keep), dxc * dxc), typ[keep].astype(np.int32).copy(), name="jet_coarse")
-        with Simulation(coarse, dtype_bits=32, device=device) as sim:
-            sim.evaluate()
-            st = sim.read("stencil")
-            kpc = sim.read("curv_plain")
-        listed = np.any(st != 0, axis=1)
-        ok = listed & (nfl[keep] == 1) & (typ[keep] == wl.FLUID)
-        nf = nrm[keep][ok]
-        nh = nf / np.linalg.norm(nf, axis=1, keepdims=True)
-        Xs.append(st[ok])
-        Ts.append(np.concatenate([nh, (kap[keep][ok] * hc)[:, None]], axis=1))
-        Ps.append(kpc[ok] * hc)
-    return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ps)
+            mag = np.linalg.norm(nrm, axis=1)
+            nh = np.where(mag[:, None] > 0, nrm / np.maximum(mag, 1e-300)[:, None], 0.0)
+            iface = (sim.read("nflag") == 1) & (mag * fine.params["h"] >= INTERFACE_NH)
+            snaps.append(dict(pos=pos[sel], nhat=nh[sel], kappa=sim.read("curv")[sel],
+                              iface=iface[sel], step=st, h_fine=fine.params["h"]))
+    return snaps
+
+
+def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int):
+    """Poisson-disk subsample of a fine snapshot at the coarse spacing (number
+    density 1/dx^2) with reference labels; returns a closure System whose
+    meta holds (nhat_ref, kappa_ref, has_ref)."""
+    import workloads as wl
+    from scipy.spatial import cKDTree
+    dxc = 1.0 / nD_coarse
+    # one greedy pass over the fine points (16 per coarse cell) with
+    # rmin = 0.78 dx keeps one point per dx^2 (measured on a jittered lattice)
+    keep = poisson_subsample(snap["pos"], 0.78 * dxc, seed)
+    pc = snap["pos"][keep]
+    hc = 1.3 * dxc
+    surf = snap["iface"]
+    sp = snap["pos"][surf]
+    sn = snap["nhat"][surf]
+    sk = snap["kappa"][surf]
+    tree = cKDTree(sp)
+    nbrs = tree.query_ball_point(pc, r=hc)
+    nref = np.zeros((len(pc), 2))
+    kref = np.zeros(len(pc))
+    has = np.zeros(len(pc), dtype=bool)
+    for i, lst in enumerate(nbrs):
+        if len(lst) < 3:
+            continue
+        idx = np.asarray(lst)
+        w = _wendland(np.linalg.norm(sp[idx] - pc[i], axis=1) / hc)
+        v = (w[:, None] * sn[idx]).sum(0)
+        if np.linalg.norm(v) <= 0.5 * w.sum():   # normals disagree: no clean label
+            continue
+        nref[i] = v / np.linalg.norm(v)
+        kref[i] = (w * sk[idx]).sum() / w.sum()
+        has[i] = True
+    p = wl.scenarios.jet_params(nD_coarse, Re, We)
+    p.update(closure=1, box_lo=tuple(pc.min(0) - 4 * dxc), box_hi=tuple(pc.max(0) + 4 * dxc))
+    n = len(pc)
+    return wl.System(p, pc.copy(), np.zeros((n, 2)), np.ones(n), np.full(n, dxc * dxc), np.zeros(n, np.int32),
+                     name="jet_coarse", meta=dict(nhat_ref=nref, kappa_ref=kref, has_ref=has, nD=nD_coarse))
+
+
+def harvest_coarse(systems, device="cuda:0", chunk_particles: int = 2_000_000, params=None):
+    """(stencils, targets, plain kappa h, closure kappa h, fallback flags) of
+    the listed particles of coarse jet sets that carry a reference label; with
+    `params` the closure runs in the same evaluation (else its kappa is 0)."""
+    from .sim import Simulation
+    X, T, P, K, F = [], [], [], [], []
+    for grp in _chunks(systems, chunk_particles):
+        with Simulation(grp, dtype_bits=32, device=device) as sim:
+            if params is not None:
+                sim.set_closure(params)
+            st, kplain, listed, e1 = _listed_rows(sim, _hpp(grp))
+            kfin = sim.read("curv")
+            fb = sim.read("fallback")
+        o = 0
+        for s in grp:
+            sl = slice(o, o + s.n)
+            o += s.n
+            h = s.params["h"]
+            m = listed[sl] & s.meta["has_ref"]
+            X.append(st[sl][m])
+            T.append(np.concatenate([to_frame(s.meta["nhat_ref"][m], e1[sl][m]),
+                                     (s.meta["kappa_ref"][m] * h)[:, None]], axis=1))
+            P.append(kplain[sl][m] * h)
+            K.append(kfin[sl][m] * h)
+            F.append(fb[sl][m])
+    cat = np.concatenate
+    return cat(X), cat(T), cat(P), cat(K), cat(F)
 
 
 # ----------------------------------------------------------------- training
+
+def mirror(X: np.ndarray, T: np.ndarray):
+    """Mirror images of stencils and targets about e1 (e2 -> -e2): entries
+    (x, y) become (x, -y), re-ordered by angle (ties: nearer first), padding
+    kept last; targets (n_1, n_2, kappa h) become (n_1, -n_2, kappa h)."""
+    P = X.reshape(len(X), -1, 2).copy()
+    P[:, :, 1] = -P[:, :, 1]
+    pad = ~np.any(P != 0, axis=2)
+    ang = np.arctan2(P[:, :, 1], P[:, :, 0])
+    ang[ang == -np.pi] = np.pi
+    ang[pad] = np.inf
+    r2 = (P ** 2).sum(2)
+    order = np.lexsort((r2, ang), axis=1)
+    P = np.take_along_axis(P, order[:, :, None], axis=1)
+    Tm = T.copy()
+    Tm[:, 1] = -Tm[:, 1]
+    return P.reshape(len(X), -1), Tm
+
 
 def to_device_bf16(X: np.ndarray, device="cuda:0"):
     import torch
@@ -284,9 +409,10 @@ def to_device_bf16(X: np.ndarray, device="cuda:0"):
 
 
 def train(X: np.ndarray, T: np.ndarray, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
-          params: np.ndarray = None, device="cuda:0", log=print) -> np.ndarray:
-    """Adam on the mean squared error with the library's training kernels; the
-    learning rate decays by 10x over the run (cosine)."""
+          params: np.ndarray = None, device="cuda:0", log=print) -> Tuple[np.ndarray, List[float]]:
+    """Adam on the mean squared error with the library's training kernels, on
+    seeded shuffled mini-batches; the learning rate follows a cosine from lr
+    down to lr / 10. Returns the FP32 parameters and the mean loss per epoch."""
     import torch
     Xd = to_device_bf16(X, device)
     Td = torch.tensor(np.asarray(T, dtype=np.float32), device=device)
@@ -294,26 +420,26 @@ def train(X: np.ndarray, T: np.ndarray, epochs: int = 40, batch: int = 4096, lr:
     tr = Trainer(w0, batch, device)
     g = torch.Generator(device="cpu").manual_seed(seed)
     n = X.shape[0]
-    nb = n // batch
+    nb = max(n // batch, 1)
     total = epochs * nb
     it = 0
+    hist = []
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).to(device)
-        tot = 0.0
+        acc = torch.zeros((), dtype=torch.float32, device=device)
         for b in range(nb):
             rows = perm[b * batch:(b + 1) * batch]
-            xb = Xd.index_select(0, rows).contiguous()
-            tb = Td.index_select(0, rows).contiguous()
+            xb = Xd.index_select(0, rows)
+            tb = Td.index_select(0, rows)
             f = 0.1 + 0.9 * 0.5 * (1 + math.cos(math.pi * it / max(total, 1)))
-            loss = tr.step(xb, tb, lr * f)
+            acc += tr.step(xb, tb, lr * f)
             it += 1
-            if b == nb - 1:
-                tot = float(loss)
+        hist.append(float(acc) / nb)
         if log and (ep % 5 == 0 or ep == epochs - 1):
-            log(f"[closure] epoch {ep} loss {tot:.3e}")
+            log(f"[closure] epoch {ep} loss {hist[-1]:.4e}")
     w = tr.params()
     tr.close()
-    return w
+    return w, hist
 
 
 def predict(params: np.ndarray, X: np.ndarray, device="cuda:0") -> np.ndarray:
@@ -326,6 +452,12 @@ def predict(params: np.ndarray, X: np.ndarray, device="cuda:0") -> np.ndarray:
 
 def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
     return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def apply_fallback(k_mlp: np.ndarray, k_plain: np.ndarray, tol: float = 0.2) -> np.ndarray:
+    """Curvature the closure uses: the network's, or the plain one where the two
+    differ by more than tol times the plain magnitude."""
+    return np.where(np.abs(k_mlp - k_plain) > tol * np.abs(k_plain), k_plain, k_mlp)
 
 
 def save(params: np.ndarray, path: str = WEIGHTS, **meta):

@@ -342,8 +342,10 @@ __global__ void k_mlp_adam(MlpBufs B, const float* grad, float lr, float b1, flo
 
 // Stencil of each listed surface particle (one wave per particle): the
 // relative positions (r_b - r_a)/h of its fluid neighbours, the 32 nearest
-// kept (ties by particle id), ordered by angle in (-pi, pi] (ties: nearer,
-// then lower id), zero-padded; written as 64 BF16 values per row.
+// kept (ties by particle id), expressed in the frame e1 = n_a/|n_a| (eq. 18),
+// e2 = e1 turned by +90 degrees, ordered by their angle in that frame in
+// (-pi, pi] (ties: nearer, then lower id; the cut at angle pi faces away from
+// the liquid), zero-padded; written as 64 BF16 values per row.
 template <typename T>
 __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
     const int l = __lane_id();
@@ -361,6 +363,11 @@ __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
         const unsigned long long m0 = v.nmask0[a], m1 = v.nmask1[a];
         const bool overflow = (m1 & MASK_OVERFLOW) != 0;
         const float ih = 1.0f / (float)S.h;
+        // e1: unit colour gradient (eq. 18, into the liquid); e2: e1 turned by +90 degrees
+        const V2<T> na = v.nrm[a];
+        const float nfx = (float)na.x, nfy = (float)na.y;
+        const float inv_n = 1.0f / sqrtf(nfx * nfx + nfy * nfy);
+        const float e1x = nfx * inv_n, e1y = nfy * inv_n;
         // candidate ordinals lane and lane + 64; slot from the row ranges
         float dxs[2], dys[2], d2s[2], angs[2];
         uint32_t ids[2];
@@ -385,13 +392,15 @@ __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
             double r2 = pair_r2(pa, v.pos[b], ex, ey);
             if (overflow && !(r2 < S.R2)) continue;
             if (tag_type(v.tag[b]) != T_FLUID) continue;
-            // relative position of b as seen from a
-            float x = -(float)ex * ih, y = -(float)ey * ih;
-            float ang = atan2f(y, x);
+            // relative position of b as seen from a, in units of h, then in
+            // the frame (e1, e2) of a's colour-gradient direction
+            const float x = -(float)ex * ih, y = -(float)ey * ih;
+            const float xl = x * e1x + y * e1y, yl = y * e1x - x * e1y;
+            float ang = atan2f(yl, xl);
             if (ang == -3.14159265358979323846f) ang = 3.14159265358979323846f;
             val[half] = true;
-            dxs[half] = x;
-            dys[half] = y;
+            dxs[half] = xl;
+            dys[half] = yl;
             d2s[half] = x * x + y * y;
             angs[half] = ang;
             ids[half] = v.id[b];
@@ -464,7 +473,9 @@ __global__ void k_closure_apply(EvalView<T> v, ClosureView C) {
             const T k_plain = v.kappa_plain[a];
             const V2<T> n_a = v.nrm[a];
             const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
-            T nx = (T)y[0], ny = (T)y[1];
+            // network normal from the frame (e1, e2) of n_a back to x, y
+            const T e1x = n_a.x / mag, e1y = n_a.y / mag;
+            T nx = (T)y[0] * e1x - (T)y[1] * e1y, ny = (T)y[0] * e1y + (T)y[1] * e1x;
             const T nm = sqrt_(nx * nx + ny * ny);
             const bool fb = fabs(k_mlp - k_plain) > S.closure_tol * fabs(k_plain) || !(nm > T(0)) ||
                             (v.nmask1[a] & MASK_OVERFLOW) != 0ull;

@@ -1,0 +1,175 @@
+"""Train the learned curvature closure on the GPU and measure what it gains.
+
+    python -m paper_1603_02421_amd.train_closure --out DIR [--shapes N] [--epochs E] ...
+
+1. Training data: rotated discs and sinusoidal interfaces with exact labels,
+   and jets run at 4x resolution, subsampled to the target spacing and
+   labelled by the fine runs' plain curvature (see closure.py), each stencil
+   also mirrored about its frame's e1 axis.
+2. Training: Adam on the mean squared error with the library's own forward,
+   backward and Adam kernels (sph_mlp_train_step).
+3. Evaluation on held-out shapes and held-out jets (other seeds, Re, We): the
+   relative L2 curvature error against the reference of the plain estimate
+   (eq. 23) at the target resolution, of the network alone, and of the
+   closure with its fallback, the last taken from the particle update itself
+   (sph_evaluate with the closure installed).
+4. Cost: particle-steps/s of the plain and closure updates on the same jet,
+   and the 4x-resolution run that the reference labels come from.
+
+Writes DIR/closure_weights.npz and DIR/closure_report.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+TRAIN_JETS = [  # (nD coarse, Re, We, seed, piston amplitude)
+    (10, 500.0, 20.0, 11, 0.01), (10, 200.0, 10.0, 12, 0.2), (12, 1000.0, 30.0, 13, 0.01),
+    (12, 300.0, 8.0, 14, 0.2), (16, 800.0, 15.0, 15, 0.1), (10, 1500.0, 40.0, 16, 0.2),
+    (14, 400.0, 25.0, 17, 0.1), (16, 2000.0, 50.0, 18, 0.01),
+]
+HELD_OUT_JETS = [(10, 700.0, 12.0, 101, 0.1), (12, 250.0, 35.0, 102, 0.2), (16, 1200.0, 20.0, 103, 0.01)]
+
+
+def jet_sets(spec, snap_steps, n_fine, free_length):
+    from . import closure as cl
+    out = []
+    from .native import SphError
+    for (nD, Re, We, seed, amp) in spec:
+        t0 = time.time()
+        try:
+            snaps = cl.fine_jet_snapshots(nD, Re, We, seed, snap_steps, n_fine=n_fine, free_length=free_length,
+                                          piston_amp=amp)
+        except SphError as e:
+            log(f"[jets] nD={nD} Re={Re} We={We} amp={amp}: skipped ({e})")
+            continue
+        for k, sn in enumerate(snaps):
+            out.append(cl.coarse_from_snapshot(sn, nD, Re, We, seed * 100 + k))
+        log(f"[jets] nD={nD} Re={Re} We={We} amp={amp}: {len(snaps)} snapshots, "
+            f"{sum(s.n for s in out[-len(snaps):])} coarse particles, {time.time() - t0:.1f} s")
+    return out
+
+
+def errors(k_ref, k_plain, k_mlp, k_closure):
+    from .closure import rel_l2
+    curved = np.abs(k_ref) > 0.05
+    r = dict(n=int(len(k_ref)), plain=rel_l2(k_plain, k_ref), mlp=rel_l2(k_mlp, k_ref),
+             closure=rel_l2(k_closure, k_ref), n_curved=int(curved.sum()))
+    if curved.any():
+        r.update(plain_curved=rel_l2(k_plain[curved], k_ref[curved]), mlp_curved=rel_l2(k_mlp[curved], k_ref[curved]),
+                 closure_curved=rel_l2(k_closure[curved], k_ref[curved]))
+    return r
+
+
+def throughput(system, params, steps, closure: bool):
+    import workloads as wl
+    from .sim import Simulation
+    s = wl.round_for_dtype(system, 32)
+    s.params = dict(s.params, closure=1 if closure else 0)
+    with Simulation(s, dtype_bits=32, graph_steps=50) as sim:
+        if closure:
+            sim.set_closure(params)
+        sim.step(100)
+        sim.sync()
+        tau0 = float(sim.read("time")[0])
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        dt = time.perf_counter() - t0
+        tau = float(sim.read("time")[0]) - tau0
+        n = int(sim.read("nactive")[0])
+    return dict(n=n, steps=steps, seconds=dt, particle_steps_per_s=n * steps / dt, sim_time=tau,
+                seconds_per_unit_time=dt / tau)
+
+
+def main(argv=None):
+    from . import closure as cl
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--shapes", type=int, default=4000)
+    ap.add_argument("--held-out-shapes", type=int, default=400)
+    ap.add_argument("--jets", type=int, default=len(TRAIN_JETS))
+    ap.add_argument("--snap-steps", type=str, default="6000,12000,18000,24000,30000")
+    ap.add_argument("--n-fine", type=int, default=400_000)
+    ap.add_argument("--free-length", type=float, default=40.0)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--bench-steps", type=int, default=2000)
+    ap.add_argument("--cost-n", type=int, default=300_000)
+    ap.add_argument("--no-mirror", action="store_true", help="no mirror images of the training stencils")
+    a = ap.parse_args(argv)
+    os.makedirs(a.out, exist_ok=True)
+    snap_steps = [int(x) for x in a.snap_steps.split(",")]
+    rep = dict(args=vars(a))
+
+    t0 = time.time()
+    shapes = cl.shape_systems(a.shapes, seed=a.seed)
+    Xs, Ts, Ps = cl.harvest_shapes(shapes)
+    del shapes
+    log(f"[data] shapes: {len(Xs)} neighbourhoods ({time.time() - t0:.1f} s)")
+    jets = jet_sets(TRAIN_JETS[:a.jets], snap_steps, a.n_fine, a.free_length)
+    Xj, Tj, Pj, _, _ = cl.harvest_coarse(jets)
+    del jets
+    log(f"[data] jets: {len(Xj)} neighbourhoods ({time.time() - t0:.1f} s)")
+    X = np.concatenate([Xs, Xj])
+    T = np.concatenate([Ts, Tj])
+    if not a.no_mirror:
+        Xm, Tm = cl.mirror(X, T)
+        X, T = np.concatenate([X, Xm]), np.concatenate([T, Tm])
+    rep["data"] = dict(shapes=int(len(Xs)), jets=int(len(Xj)), mirrored=not a.no_mirror, samples=int(len(X)),
+                       seconds=time.time() - t0)
+
+    t1 = time.time()
+    w, hist = cl.train(X, T, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=a.seed, log=log)
+    rep["train"] = dict(seconds=time.time() - t1, loss=hist, samples=int(len(X)))
+    cl.save(w, os.path.join(a.out, "closure_weights.npz"))
+    del X, T
+    log(f"[train] done in {time.time() - t1:.1f} s, final loss {hist[-1]:.4e}")
+
+    # held-out shapes (exact labels)
+    ho = cl.shape_systems(a.held_out_shapes, seed=a.seed + 1000)
+    Xh, Th, Ph = cl.harvest_shapes(ho)
+    Yh = cl.predict(w, Xh)
+    rep["held_out_shapes"] = errors(Th[:, 2], Ph, Yh[:, 2], cl.apply_fallback(Yh[:, 2], Ph))
+    log(f"[eval] held-out shapes: {rep['held_out_shapes']}")
+    # held-out jets, with the closure's curvature taken from the particle update
+    hj = jet_sets(HELD_OUT_JETS, snap_steps, a.n_fine, a.free_length)
+    X2, T2, P2, K2, F2 = cl.harvest_coarse(hj, params=w)
+    Y2 = cl.predict(w, X2)
+    ang = np.degrees(np.arccos(np.clip(np.einsum("ij,ij->i", Y2[:, :2] / np.linalg.norm(Y2[:, :2], axis=1,
+                                                                                          keepdims=True), T2[:, :2]),
+                                       -1, 1)))
+    rep["held_out_jets"] = errors(T2[:, 2], P2, Y2[:, 2], K2)
+    rep["held_out_jets"].update(fallback_fraction=float(F2.mean()), normal_angle_deg_median=float(np.median(ang)))
+    log(f"[eval] held-out jets: {rep['held_out_jets']}")
+
+    # cost: plain vs closure on a jet at D = 20 dx, and the same jet at 4x
+    # resolution (D = 80 dx, 16x the particles, plain), per unit simulated time
+    import workloads as wl
+    base = wl.jet(n_target=a.cost_n, nD=20, Re=500.0, We=20.0, seed=7, free_length=60.0, prefill=20.0)
+    rep["cost"] = dict(plain=throughput(base, w, a.bench_steps, False),
+                       closure=throughput(base, w, a.bench_steps, True))
+    log(f"[cost] D=20dx: {rep['cost']}")
+    fine = wl.jet(n_target=16 * a.cost_n, nD=80, Re=500.0, We=20.0, seed=7, free_length=60.0, prefill=20.0)
+    rep["cost"]["fine_plain_4x"] = throughput(fine, w, max(a.bench_steps // 4, 100), False)
+    rep["cost"]["speedup_vs_4x_resolution"] = (rep["cost"]["fine_plain_4x"]["seconds_per_unit_time"]
+                                               / rep["cost"]["closure"]["seconds_per_unit_time"])
+    log(f"[cost] {rep['cost']}")
+    with open(os.path.join(a.out, "closure_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    log("[done]")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,67 @@
+"""Host-side logic of the closure's training data (no GPU)."""
+import math
+
+import numpy as np
+
+import workloads as wl
+from oracle import mlp
+from paper_1603_02421_amd import closure as cl
+
+
+def test_mirror_matches_stencil_of_mirrored_particles(orc):
+    s = wl.lattice_block(11, 11, dx=1.0)
+    rng = np.random.Generator(np.random.PCG64(4))
+    s.pos = s.pos + rng.uniform(-0.1, 0.1, size=s.pos.shape)
+    a = 60
+    n = np.array([0.6, 0.8])
+    start, nbr = orc.neighbors(s)
+    X = mlp.stencil_of(a, s.pos, nbr[start[a]:start[a + 1]], s.type, s.params["h"], n)
+    e1 = n / np.linalg.norm(n)
+    P = s.pos - s.pos[a]
+    m = s.copy()
+    m.pos = 2 * np.outer(P @ e1, e1) - P + s.pos[a]   # reflection about the line along e1
+    start2, nbr2 = orc.neighbors(m)
+    Xm = mlp.stencil_of(a, m.pos, nbr2[start2[a]:start2[a + 1]], m.type, m.params["h"], n)
+    Xa, Ta = cl.mirror(X[None], np.array([[0.9, 0.1, -0.2]]))
+    assert np.abs(Xa[0] - Xm).max() < 1e-12
+    assert np.array_equal(Ta, [[0.9, -0.1, -0.2]])
+
+
+def test_to_frame_is_the_stencil_frame():
+    rng = np.random.Generator(np.random.PCG64(1))
+    v = rng.normal(size=(50, 2))
+    n = rng.normal(size=(50, 2))
+    e1 = n / np.linalg.norm(n, axis=1, keepdims=True)
+    got = cl.to_frame(v, e1)
+    for i in range(50):
+        f1, f2 = mlp.frame(n[i])
+        assert np.allclose(got[i], [v[i] @ f1, v[i] @ f2], atol=1e-14)
+
+
+def test_shape_labels():
+    # disc: inward normal and -1/R; sinusoid: nearest-point geometry
+    nh, k, keep = cl._disc_label(np.array([[3.0, 4.0], [0.0, 1.0]]), 5.0, 1.0)
+    assert np.allclose(nh[0], [-0.6, -0.8]) and np.allclose(k, -0.2)
+    assert list(keep) == [True, False]
+    A, kk, lam = 2.0, 2 * math.pi / 20.0, 20.0
+    x0 = np.array([25.0, 27.0, 33.0])
+    q = np.stack([x0, A * np.sin(kk * x0)], axis=1)          # points on the curve
+    nh, kap, keep = cl._sine_label(q, A, kk, lam, 1.0)
+    s = A * kk * np.cos(kk * x0)
+    assert np.allclose(nh, np.stack([s, -np.ones(3)], 1) / np.sqrt(1 + s * s)[:, None])
+    assert np.allclose(kap, -A * kk * kk * np.sin(kk * x0) / (1 + s * s) ** 1.5)
+    # a point below the crest: its nearest interface point is the crest
+    nh2, kap2, _ = cl._sine_label(np.array([[25.0, 1.0]]), A, kk, lam, 1.0)
+    assert np.allclose(nh2, [[0.0, -1.0]], atol=1e-9) and np.isclose(kap2[0], -A * kk * kk)
+
+
+def test_poisson_subsample_spacing_and_density():
+    rng = np.random.Generator(np.random.PCG64(0))
+    i, j = np.meshgrid(np.arange(160), np.arange(160), indexing="ij")
+    pos = np.stack([(i.ravel() + 0.5) * 0.025, (j.ravel() + 0.5) * 0.025], 1)
+    pos = pos + rng.uniform(-0.0025, 0.0025, size=pos.shape)
+    k = cl.poisson_subsample(pos, 0.078, 3)
+    from scipy.spatial import cKDTree
+    d, _ = cKDTree(pos[k]).query(pos[k], k=2)
+    assert d[:, 1].min() >= 0.078
+    assert 0.9 * 1600 <= len(k) <= 1.1 * 1600   # about one point per 0.1 x 0.1 cell of the 4 x 4 square

@@ -69,15 +69,19 @@ def test_flat_params_round_trip():
         assert np.array_equal(p[k], q[k])
 
 
-def _lattice_stencil(angle=0.0, shift=(0.0, 0.0)):
+def _lattice_stencil(angle=0.0, shift=(0.0, 0.0), jitter=0.0, normal=(1.0, 0.0)):
     s = wl.lattice_block(11, 11, dx=1.0)
+    if jitter:
+        rng = np.random.Generator(np.random.PCG64(4))
+        s.pos = s.pos + rng.uniform(-jitter, jitter, size=s.pos.shape)
     c, sn = math.cos(angle), math.sin(angle)
-    pos = s.pos @ np.array([[c, sn], [-sn, c]]) + np.array(shift)
-    s.pos = pos
+    R = np.array([[c, sn], [-sn, c]])        # row vectors turned by +angle
+    s.pos = s.pos @ R + np.array(shift)
+    n_a = np.asarray(normal) @ R
     import oracle
     start, nbr = oracle.neighbors(s)
     a = 5 * 11 + 5  # the centre of the block
-    return mlp.stencil_of(a, s.pos, nbr[start[a]:start[a + 1]], s.type, s.params["h"]), s.params["h"]
+    return mlp.stencil_of(a, s.pos, nbr[start[a]:start[a + 1]], s.type, s.params["h"], n_a), s.params["h"]
 
 
 def test_lattice_stencil_geometry(orc):
@@ -99,20 +103,24 @@ def test_lattice_stencil_geometry(orc):
     assert np.all(np.diff(r2)[same] > 0)    # collinear neighbours: nearer first
 
 
-def test_stencil_translation_invariance_and_rotation(orc):
+def test_stencil_translation_and_rotation_invariance(orc):
     base, _ = _lattice_stencil()
     moved, _ = _lattice_stencil(shift=(123.25, -7.5))
     assert np.allclose(base, moved, atol=1e-9)
-    rot, _ = _lattice_stencil(angle=math.pi / 2 + 1e-3)
-    # rotating the particles rotates every relative position; the angle order is
-    # the same cyclic sequence
-    a = base.reshape(-1, 2)[:20]
-    b = rot.reshape(-1, 2)[:20]
-    c, s = math.cos(math.pi / 2 + 1e-3), math.sin(math.pi / 2 + 1e-3)
-    ra = a @ np.array([[c, s], [-s, c]])
-    match = [int(np.argmin(np.linalg.norm(b - x, axis=1))) for x in ra]
+    # turning the particles and the colour gradient together leaves the stencil
+    # (written in the gradient's frame) unchanged, order included
+    j0, _ = _lattice_stencil(jitter=0.1, normal=(0.6, 0.8))
+    for ang in (0.3, math.pi / 2 + 1e-3, 2.5, -1.9):
+        jr, _ = _lattice_stencil(angle=ang, jitter=0.1, normal=(0.6, 0.8))
+        assert np.allclose(j0, jr, atol=1e-9), ang
+    # a frame turned against the particles turns every entry the other way
+    c, s = math.cos(0.7), math.sin(0.7)
+    fr, _ = _lattice_stencil(normal=(c, s))
+    want = base.reshape(-1, 2)[:20] @ np.array([[c, -s], [s, c]])
+    got = fr.reshape(-1, 2)[:20]
+    match = [int(np.argmin(np.linalg.norm(got - x, axis=1))) for x in want]
     assert sorted(match) == list(range(20))
-    assert all(np.linalg.norm(b[m] - x) < 1e-9 for m, x in zip(match, ra))
+    assert all(np.linalg.norm(got[m] - x) < 1e-9 for m, x in zip(match, want))
 
 
 def test_fallback_rule():
@@ -141,8 +149,9 @@ def test_closure_with_zero_network_falls_back_to_plain(orc):
 
 
 def test_closure_replaces_the_surface_term(orc):
-    # a network that always answers "flat" (kappa = 0) with no fallback removes
-    # the surface-tension term of the listed particles and nothing else
+    # a network that always answers "flat" (kappa = 0, normal e1) with no
+    # fallback removes the surface-tension term of the listed particles and
+    # nothing else
     d = _closure_disc()
     w = np.zeros(mlp.N_PARAMS)
     w[-3:] = [1.0, 0.0, 0.0]
@@ -166,7 +175,11 @@ def test_rim_stencils_lean_inward(orc):
     X = r["X"].reshape(len(ids), 32, 2)
     mean = X.sum(1)
     assert rim.sum() > 30
-    assert np.all(np.einsum("ij,ij->i", mean[rim], d.pos[ids][rim]) < 0)
+    # in the colour-gradient frame the liquid lies along +e1
+    assert np.all(mean[rim, 0] > 0)
+    # and the stencils of the rim particles, all seen from their own frame, are
+    # nearly mirror-symmetric about e1 on the ring layout
+    assert np.all(np.abs(mean[rim, 1]) < 0.5 * mean[rim, 0])
     # every stencil entry is a fluid neighbour inside the support, in BF16
     rr = np.linalg.norm(X, axis=2)
     assert np.all(rr <= 2.0 + 2 ** -7)
