@@ -7,9 +7,10 @@ Training neighbourhoods come from the library's own stencil kernel, run on
 two kinds of particle sets whose interface geometry is known:
 
 * discs (radius 3-50 dx) and sinusoidal interfaces (amplitude 0.5-5 dx,
-  wavelength 10-60 dx) on a jittered lattice, randomly rotated, labelled with
-  the exact unit normal and curvature of the interface at the particle's
-  nearest interface point (particles within 2h of the interface);
+  wavelength 10-60 dx), with particles in layers that follow the interface
+  or cut from the square lattice, jittered and randomly rotated, labelled
+  with the exact unit normal and curvature of the interface at the
+  particle's nearest interface point (particles within 2h of the interface);
 * jets: a jet run at 4x the target resolution is Poisson-disk subsampled to
   the target spacing; the coarse set is labelled by the fine run's plain
   estimate (eq. 18-23), averaged with Wendland weights of the coarse h over
@@ -156,38 +157,36 @@ def _sine_label(q, A, kk, lam, dx):
     return nh, kap, keep
 
 
-def shape_systems(n_shapes: int, seed: int, dx: float = 1.0):
+def shape_systems(n_shapes: int, seed: int, dx: float = 1.0, conforming: float = 0.8):
     """Discs and sinusoidal slabs with their exact interface geometry, each
-    randomly rotated and jittered. meta["label"](unrotated positions) returns
-    (unit normal, kappa, keep mask)."""
+    randomly rotated and jittered (0-0.1 dx). A fraction `conforming` of them
+    has particles in layers that follow the interface (rings, columns), as a
+    relaxed free surface does; the rest is cut from the square lattice, with
+    its staircase. meta["label"](unrotated positions) returns (unit normal,
+    kappa, keep mask)."""
     import workloads as wl
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
-    h = 1.3 * dx
     for k in range(n_shapes):
         jitter = float(rng.choice([0.0, 0.02, 0.05, 0.1]))
         th = float(rng.uniform(0, 2 * math.pi))
+        layered = bool(rng.uniform() < conforming)
+        sub = int(rng.integers(0, 2**31 - 1))
         if k % 2 == 0:
             R = float(math.exp(rng.uniform(math.log(3.0), math.log(50.0)))) * dx
-            n = int(math.ceil(R / dx)) + 1
-            p = _jittered_lattice(-n * dx, -n * dx, 2 * n, 2 * n, dx, jitter, rng)
-            p = p[np.hypot(p[:, 0], p[:, 1]) < R]
+            s = wl.circle(R, dx=dx, jitter=jitter, seed=sub, layout="rings" if layered else "lattice")
             label = (lambda q, R=R: _disc_label(q, R, dx))
         else:
             A = float(rng.uniform(0.5, 5.0)) * dx
             lam = float(rng.uniform(10.0, 60.0)) * dx
-            kk = 2 * math.pi / lam
-            depth = 8.0 * dx
-            base = _jittered_lattice(0.0, -depth - A, int(4 * lam / dx), int((depth + 2 * A) / dx) + 2, dx,
-                                     jitter, rng)
-            p = base[base[:, 1] < A * np.sin(kk * base[:, 0])]
-            label = (lambda q, A=A, kk=kk, lam=lam: _sine_label(q, A, kk, lam, dx))
-        pr = _rotate(p, th)
-        lo, hi = pr.min(0) - 4 * dx, pr.max(0) + 4 * dx
-        par = wl.scenarios.default_params(h, 1.0, 10.0, sigma=1.0, alpha=0.05, closure=1, box_lo=tuple(lo),
-                                          box_hi=tuple(hi))
-        s = wl.scenarios._assemble(par, [(pr, (0.0, 0.0), 1.0, wl.FLUID)], name="shape")
-        s.meta = dict(theta=th, label=label)
+            s = wl.sinusoid(A, lam, dx=dx, periods=4, depth=12.0 * dx, jitter=jitter, seed=sub,
+                            layout="columns" if layered else "lattice")
+            label = (lambda q, A=A, kk=2 * math.pi / lam, lam=lam: _sine_label(q, A, kk, lam, dx))
+        pr = _rotate(s.pos, th)
+        s.pos = pr
+        s.params.update(closure=1, box_lo=tuple(pr.min(0) - 4 * dx), box_hi=tuple(pr.max(0) + 4 * dx),
+                        cell_size=2.2 * 1.3 * dx)
+        s.meta = dict(theta=th, label=label, layered=layered, jitter=jitter)
         out.append(s)
     return out
 
@@ -226,10 +225,11 @@ def _hpp(grp):
 
 
 def harvest_shapes(systems, device="cuda:0", chunk_particles: int = 2_000_000):
-    """(stencils, targets (n_1, n_2, kappa h), plain kappa h) of every listed
-    particle near the interface of the shapes."""
+    """(stencils, targets (n_1, n_2, kappa h), plain kappa h, index of the
+    shape) of every listed particle near the interface of the shapes."""
     from .sim import Simulation
-    X, T, P = [], [], []
+    X, T, P, I = [], [], [], []
+    k = 0
     for grp in _chunks(systems, chunk_particles):
         with Simulation(grp, dtype_bits=32, device=device) as sim:
             st, kplain, listed, e1 = _listed_rows(sim, _hpp(grp))
@@ -244,7 +244,9 @@ def harvest_shapes(systems, device="cuda:0", chunk_particles: int = 2_000_000):
             X.append(st[sl][m])
             T.append(np.concatenate([to_frame(_rotate(nh, th)[m], e1[sl][m]), (kap[m] * h)[:, None]], axis=1))
             P.append(kplain[sl][m] * h)
-    return np.concatenate(X), np.concatenate(T), np.concatenate(P)
+            I.append(np.full(int(m.sum()), k))
+            k += 1
+    return np.concatenate(X), np.concatenate(T), np.concatenate(P), np.concatenate(I)
 
 
 # ----------------------------------------------------------------- jets

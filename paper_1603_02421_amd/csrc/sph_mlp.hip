@@ -118,13 +118,11 @@ __device__ __forceinline__ void load_tile(const uint16_t* X, int64_t m, int64_t 
 }
 
 // Y (m x 3, row stride ystride) = network(X) for every row; one wave walks
-// the tiles. The row count is m, or *mdev when mdev is given (device-side
-// count of the closure list).
-__global__ void __launch_bounds__(64) k_mlp_forward(MlpView W, const uint16_t* X, int64_t m_host,
-                                                    const uint32_t* mdev, float* Y, int ystride) {
+// the tiles.
+__global__ void __launch_bounds__(64) k_mlp_forward(MlpView W, const uint16_t* X, int64_t m, float* Y,
+                                                    int ystride) {
     __shared__ uint16_t xs[16 * 64], h1s[16 * 64], h2s[16 * 64];
     const int l = __lane_id(), r = l & 15, g = l >> 4;
-    const int64_t m = mdev ? (int64_t)*mdev : m_host;
     const int64_t ntiles = (m + 15) / 16;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         load_tile(X, m, t * 16, xs);
@@ -348,6 +346,8 @@ __global__ void k_mlp_adam(MlpBufs B, const float* grad, float lr, float b1, flo
 // the liquid), zero-padded; written as 64 BF16 values per row.
 template <typename T>
 __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
+    __shared__ float sx[128], sy[128], sd[128], sa[128];
+    __shared__ uint32_t sid[128], skeep[128];
     const int l = __lane_id();
     const uint32_t count = *C.count;
     for (uint32_t row = blockIdx.x; row < count; row += gridDim.x) {
@@ -405,101 +405,139 @@ __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
             angs[half] = ang;
             ids[half] = v.id[b];
         }
-        // rank by distance (ties by id) among all items; keep the 32 nearest
-        int drank[2] = {0, 0};
-        for (int src = 0; src < 64; ++src) {
+        // compact the valid items into LDS slots [0, k), then rank each item
+        // against the k others only (k is about 20 on a free surface)
+        const unsigned long long b0 = __ballot(val[0]), b1 = __ballot(val[1]);
+        const int k0 = __popcll(b0), k = k0 + __popcll(b1);
+        const unsigned long long below = (1ull << l) - 1ull;
 #pragma unroll
-            for (int hs = 0; hs < 2; ++hs) {
-                const bool ov = __shfl(val[hs] ? 1 : 0, src, 64) != 0;
-                const float od = __shfl(d2s[hs], src, 64);
-                const uint32_t oi = __shfl(ids[hs], src, 64);
-#pragma unroll
-                for (int hm = 0; hm < 2; ++hm)
-                    if (ov && (od < d2s[hm] || (od == d2s[hm] && oi < ids[hm]))) ++drank[hm];
+        for (int hm = 0; hm < 2; ++hm) {
+            if (val[hm]) {
+                const int p = hm == 0 ? __popcll(b0 & below) : k0 + __popcll(b1 & below);
+                sx[p] = dxs[hm];
+                sy[p] = dys[hm];
+                sd[p] = d2s[hm];
+                sa[p] = angs[hm];
+                sid[p] = ids[hm];
             }
         }
+        __syncthreads();
+        // the 32 nearest (ties by id) stay
         bool keep[2];
 #pragma unroll
-        for (int hm = 0; hm < 2; ++hm) keep[hm] = val[hm] && drank[hm] < 32;
-        // rank by angle among the kept (ties: nearer, then lower id)
-        int arank[2] = {0, 0};
-        for (int src = 0; src < 64; ++src) {
-#pragma unroll
-            for (int hs = 0; hs < 2; ++hs) {
-                const bool ok = __shfl(keep[hs] ? 1 : 0, src, 64) != 0;
-                const float oa = __shfl(angs[hs], src, 64);
-                const float od = __shfl(d2s[hs], src, 64);
-                const uint32_t oi = __shfl(ids[hs], src, 64);
-#pragma unroll
-                for (int hm = 0; hm < 2; ++hm)
-                    if (ok && (oa < angs[hm] || (oa == angs[hm] && (od < d2s[hm] || (od == d2s[hm] && oi < ids[hm])))))
-                        ++arank[hm];
+        for (int hm = 0; hm < 2; ++hm) {
+            const int j = l + 64 * hm;
+            keep[hm] = false;
+            if (j < k) {
+                int drank = 0;
+                if (k > 32) {
+                    const float d = sd[j];
+                    const uint32_t id = sid[j];
+                    for (int q = 0; q < k; ++q) {
+                        const float od = sd[q];
+                        drank += (od < d || (od == d && sid[q] < id)) ? 1 : 0;
+                    }
+                }
+                keep[hm] = drank < 32;
+                skeep[j] = keep[hm] ? 1u : 0u;
             }
         }
-        const int nkept = __popcll(__ballot(keep[0])) + __popcll(__ballot(keep[1]));
+        __syncthreads();
+        // angle rank among the kept (ties: nearer, then lower id); write out
         uint16_t* out = C.stencil + (size_t)row * 64;
-        // zero the padding, then place every kept item at its angle rank
+        const int nkept = k < 32 ? k : 32;
         if (l >= 2 * nkept) out[l] = 0;
 #pragma unroll
         for (int hm = 0; hm < 2; ++hm) {
-            if (keep[hm]) {
-                out[2 * arank[hm]] = f2bf(dxs[hm]);
-                out[2 * arank[hm] + 1] = f2bf(dys[hm]);
+            const int j = l + 64 * hm;
+            if (j < k && keep[hm]) {
+                const float an = sa[j], d = sd[j];
+                const uint32_t id = sid[j];
+                int arank = 0;
+                for (int q = 0; q < k; ++q) {
+                    const float oa = sa[q], od = sd[q];
+                    const bool before = oa < an || (oa == an && (od < d || (od == d && sid[q] < id)));
+                    arank += (skeep[q] != 0u && before) ? 1 : 0;
+                }
+                out[2 * arank] = f2bf(sx[j]);
+                out[2 * arank + 1] = f2bf(sy[j]);
             }
         }
+        __syncthreads();  // the LDS slots are reused by the next row
     }
 }
 
-// Surface-tension acceleration of the listed particles from the network's
-// curvature and normal, or from the plain estimate where the network's
-// curvature deviates from it by more than the tolerance (eq. 24); completes
-// the total acceleration (eq. 25) and its eq. 30 limit.
+// Surface-tension acceleration of one listed particle from the network's
+// output y = (n_1, n_2, kappa h) (normal in the frame of n_a), or from the plain
+// estimate where the network's curvature deviates from it by more than the
+// tolerance (eq. 24); completes the total acceleration (eq. 25) and returns
+// its eq. 30 limit and the particle's system.
 template <typename T>
-__global__ void k_closure_apply(EvalView<T> v, ClosureView C) {
-    const uint32_t count = *C.count;
-    for (uint32_t row = blockIdx.x * blockDim.x + threadIdx.x; row - threadIdx.x < count;
-         row += gridDim.x * blockDim.x) {
-        const bool valid = row < count;
-        uint32_t a = 0;
+__device__ __forceinline__ double closure_apply_row(const EvalView<T>& v, const ClosureView& C, uint32_t a,
+                                                    float y0, float y1, float y2, int& sys) {
+    sys = (int)tag_sys(v.tag[a]);
+    const SysDev<T>& S = v.sys[sys];
+    const T h = S.h;
+    const T k_mlp = (T)y2 / h;
+    const T k_plain = v.kappa_plain[a];
+    const V2<T> n_a = v.nrm[a];
+    const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
+    // network normal from the frame (e1, e2) of n_a back to x, y
+    const T e1x = n_a.x / mag, e1y = n_a.y / mag;
+    T nx = (T)y0 * e1x - (T)y1 * e1y, ny = (T)y0 * e1y + (T)y1 * e1x;
+    const T nm = sqrt_(nx * nx + ny * ny);
+    const bool fb = fabs(k_mlp - k_plain) > S.closure_tol * fabs(k_plain) || !(nm > T(0)) ||
+                    (v.nmask1[a] & MASK_OVERFLOW) != 0ull;
+    T kappa;
+    if (fb) {
+        kappa = k_plain;
+        nx = e1x;
+        ny = e1y;
+    } else {
+        kappa = k_mlp;
+        nx /= nm;
+        ny /= nm;
+    }
+    const T f = -S.sigma / v.eos[a].z * kappa * mag;
+    V2<T> acc = v.acc[a];
+    acc.x += f * nx;
+    acc.y += f * ny;
+    v.acc[a] = acc;
+    v.kappa[a] = kappa;
+    C.fallback[a] = fb ? 1u : 0u;
+    const T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
+    return am > T(0) ? sqrt((double)S.h / (double)am) : __builtin_inf();
+}
+
+// The network on the listed stencils, 16 rows per wave and tile, followed by
+// the closure step of each row (one wavefront per workgroup).
+template <typename T>
+__global__ void __launch_bounds__(64) k_closure_net(EvalView<T> v, ClosureView C, MlpView W) {
+    __shared__ uint16_t xs[16 * 64], h1s[16 * 64], h2s[16 * 64];
+    __shared__ float ys[16 * 4];
+    const int l = __lane_id(), r = l & 15, g = l >> 4;
+    const int64_t m = (int64_t)*C.count;
+    const int64_t ntiles = (m + 15) / 16;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        load_tile(C.stencil, m, t * 16, xs);
+        f4 H1[4], H2[4], y;
+        mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
+        if (r < 3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t row = t * 16 + 4 * g + i;
+                ys[(4 * g + i) * 4 + r] = y[i];
+                if (row < m) C.out[row * 4 + r] = y[i];
+            }
+        }
+        __syncthreads();
+        const int64_t row = t * 16 + l;
+        const bool valid = l < 16 && row < m;
         int sys = 0;
         double dtf = __builtin_inf();
-        if (valid) {
-            a = C.list[row];
-            sys = (int)tag_sys(v.tag[a]);
-            const SysDev<T>& S = v.sys[sys];
-            const float* y = C.out + (size_t)row * 4;
-            const T h = S.h;
-            const T k_mlp = (T)y[2] / h;
-            const T k_plain = v.kappa_plain[a];
-            const V2<T> n_a = v.nrm[a];
-            const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
-            // network normal from the frame (e1, e2) of n_a back to x, y
-            const T e1x = n_a.x / mag, e1y = n_a.y / mag;
-            T nx = (T)y[0] * e1x - (T)y[1] * e1y, ny = (T)y[0] * e1y + (T)y[1] * e1x;
-            const T nm = sqrt_(nx * nx + ny * ny);
-            const bool fb = fabs(k_mlp - k_plain) > S.closure_tol * fabs(k_plain) || !(nm > T(0)) ||
-                            (v.nmask1[a] & MASK_OVERFLOW) != 0ull;
-            T kappa;
-            if (fb) {
-                kappa = k_plain;
-                nx = n_a.x / mag;
-                ny = n_a.y / mag;
-            } else {
-                kappa = k_mlp;
-                nx /= nm;
-                ny /= nm;
-            }
-            const T f = -S.sigma / v.eos[a].z * kappa * mag;
-            V2<T> acc = v.acc[a];
-            acc.x += f * nx;
-            acc.y += f * ny;
-            v.acc[a] = acc;
-            v.kappa[a] = kappa;
-            C.fallback[a] = fb ? 1u : 0u;
-            T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
-            if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
-        }
+        if (valid) dtf = closure_apply_row<T>(v, C, C.list[row], ys[l * 4], ys[l * 4 + 1], ys[l * 4 + 2], sys);
         if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, sys, dtf, valid);
+        __syncthreads();
     }
 }
 
@@ -508,7 +546,7 @@ __global__ void k_closure_apply(EvalView<T> v, ClosureView C) {
 void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y, int ystride, hipStream_t st) {
     int64_t ntiles = (m + 15) / 16;
     unsigned grid = (unsigned)(ntiles < 8192 ? (ntiles > 0 ? ntiles : 1) : 8192);
-    k_mlp_forward<<<grid, 64, 0, st>>>(W, X, m, nullptr, Y, ystride);
+    k_mlp_forward<<<grid, 64, 0, st>>>(W, X, m, Y, ystride);
 }
 
 int mlp_grad_waves(int64_t m, int tiles_per_wave) {
@@ -541,11 +579,8 @@ void launch_closure(const EvalView<T>& v, const ClosureView& C, const MlpView& W
     kt->begin("closure_stencil", st);
     k_stencil<T><<<4096, 64, 0, st>>>(v, C);
     kt->end(st);
-    kt->begin("closure_mlp", st);
-    k_mlp_forward<<<2048, 64, 0, st>>>(W, C.stencil, 0, C.count, C.out, 4);
-    kt->end(st);
-    kt->begin("closure_apply", st);
-    k_closure_apply<T><<<1024, 256, 0, st>>>(v, C);
+    kt->begin("closure_net", st);
+    k_closure_net<T><<<2048, 64, 0, st>>>(v, C, W);
     kt->end(st);
     (void)capacity;
 }

@@ -101,7 +101,7 @@ def main(argv=None):
     ap.add_argument("--snap-steps", type=str, default="6000,12000,18000,24000,30000")
     ap.add_argument("--n-fine", type=int, default=400_000)
     ap.add_argument("--free-length", type=float, default=40.0)
-    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
@@ -115,7 +115,7 @@ def main(argv=None):
 
     t0 = time.time()
     shapes = cl.shape_systems(a.shapes, seed=a.seed)
-    Xs, Ts, Ps = cl.harvest_shapes(shapes)
+    Xs, Ts, Ps, _ = cl.harvest_shapes(shapes)
     del shapes
     log(f"[data] shapes: {len(Xs)} neighbourhoods ({time.time() - t0:.1f} s)")
     jets = jet_sets(TRAIN_JETS[:a.jets], snap_steps, a.n_fine, a.free_length)
@@ -139,10 +139,17 @@ def main(argv=None):
 
     # held-out shapes (exact labels)
     ho = cl.shape_systems(a.held_out_shapes, seed=a.seed + 1000)
-    Xh, Th, Ph = cl.harvest_shapes(ho)
+    Xh, Th, Ph, Ih = cl.harvest_shapes(ho)
     Yh = cl.predict(w, Xh)
     rep["held_out_shapes"] = errors(Th[:, 2], Ph, Yh[:, 2], cl.apply_fallback(Yh[:, 2], Ph))
     log(f"[eval] held-out shapes: {rep['held_out_shapes']}")
+    for name, sel in (("layered", lambda s: s.meta["layered"]), ("lattice", lambda s: not s.meta["layered"]),
+                      ("layered_discs", lambda s: s.meta["layered"] and s.name == "circle"),
+                      ("layered_no_jitter", lambda s: s.meta["layered"] and s.meta["jitter"] == 0.0)):
+        m = np.array([sel(ho[i]) for i in Ih], dtype=bool)
+        if m.any():
+            rep[f"held_out_shapes_{name}"] = errors(Th[m, 2], Ph[m], Yh[m, 2], cl.apply_fallback(Yh[m, 2], Ph[m]))
+            log(f"[eval]   {name}: {rep[f'held_out_shapes_{name}']}")
     # held-out jets, with the closure's curvature taken from the particle update
     hj = jet_sets(HELD_OUT_JETS, snap_steps, a.n_fine, a.free_length)
     X2, T2, P2, K2, F2 = cl.harvest_coarse(hj, params=w)

@@ -337,3 +337,45 @@ def test_closure_requires_closure_system(gpu):
     with gpu.Simulation(s, dtype_bits=32) as sim:
         with pytest.raises(gpu.native.SphError):
             sim.set_closure(np.zeros(gpu.native.MLP_NPARAMS, np.float32))
+
+
+# ----------------------------------------------------------------- what training gains
+
+def test_trained_network_beats_plain_estimate_on_unseen_shapes(gpu):
+    """The shipped weights (trained on other seeds) against the exact curvature
+    of discs and sinusoidal interfaces they never saw: the network's relative
+    L2 error is well below that of eq. 23."""
+    from paper_1603_02421_amd import closure as cl
+    w = cl.load()
+    shapes = cl.shape_systems(60, seed=777)
+    X, T, P, _ = cl.harvest_shapes(shapes)
+    Y = cl.predict(w, X)
+    e_plain, e_mlp = cl.rel_l2(P, T[:, 2]), cl.rel_l2(Y[:, 2], T[:, 2])
+    say(f"[gain] {len(X)} interface particles: plain {e_plain:.3f}, network {e_mlp:.3f}")
+    assert e_mlp < 0.5 * e_plain
+
+
+def test_trained_closure_inside_the_update_on_a_disc(gpu):
+    """A relaxed-looking disc (concentric rings, jittered) of radius 12 dx: with
+    the fallback off, the curvature the update uses is the network's and lies
+    closer to -1/R than the plain estimate; the surface force points inward."""
+    from paper_1603_02421_amd import closure as cl
+    w = cl.load()
+    d = wl.round_for_dtype(wl.circle(12.0, dx=1.0, jitter=0.03, seed=5, layout="rings"), 32)
+    d.params.update(closure=1, closure_tol=1e30)
+    with gpu.Simulation(d, dtype_bits=32) as sim:
+        sim.set_closure(w)
+        sim.evaluate()
+        kap, kpl = sim.read("curv"), sim.read("curv_plain")
+        out, nrm, acc = sim.read("closure"), sim.read("normal"), sim.read("accel")
+    h = d.params["h"]
+    r = np.hypot(d.pos[:, 0], d.pos[:, 1])
+    sel = (out[:, 3] == 1) & (np.linalg.norm(nrm, axis=1) * h >= cl.INTERFACE_NH) & (r > 12.0 - 2.6)
+    assert sel.sum() > 60
+    assert np.allclose(kap[sel], out[sel, 2] / h, rtol=1e-6)
+    ref = np.full(sel.sum(), -1.0 / 12.0)
+    e_plain, e_net = cl.rel_l2(kpl[sel], ref), cl.rel_l2(kap[sel], ref)
+    say(f"[disc] {sel.sum()} interface particles: plain {e_plain:.3f}, closure {e_net:.3f}")
+    assert e_net < e_plain
+    rim = sel & (r > 11.0)
+    assert np.all(np.einsum("ij,ij->i", acc[rim], d.pos[rim]) < 0)
