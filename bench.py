@@ -13,7 +13,9 @@ timed steps with all inputs resident on the GPU.
 After the timed region the same context runs a few eagerly launched steps with
 a HIP event pair around every kernel on the context's stream; the kernel with
 the largest share of the step gives the roofline object (algorithmic bytes per
-active particle x active particles / mean launch time). The FP64 oracle is
+active particle x active particles / mean launch time). The same workload then
+runs with the learned curvature closure in every system (closure: its
+particle-steps/s, listed particles and fallback fraction). The FP64 oracle is
 timed on the host cores on a bounded sample of the workload (cpu_baseline).
 """
 from __future__ import annotations
@@ -92,6 +94,41 @@ def cpu_baseline(batch, target_s: float = 15.0):
                                        f"step, FP64 C oracle with OpenMP, {el:.1f} s")
 
 
+def closure_leg(sph, batch, bits, block_sweep, cell_factor, args):
+    """The same workload and launch shape with the learned closure in every
+    system (shipped weights, fallback tolerance 0.2), timed the same way."""
+    import torch
+    import workloads as wl
+    from paper_1603_02421_amd import closure as cl
+    systems = []
+    for s in batch.systems:
+        c = s.copy()
+        c.params = dict(s.params, closure=1, closure_tol=0.2)
+        systems.append(c)
+    cb = wl.Batch(systems)
+    sim = sph.Simulation(cb, dtype_bits=bits, block_sweep=block_sweep, xcd_remap=args.xcd, cell_factor=cell_factor)
+    sim.set_closure(cl.load())
+    sim.step(args.warmup)
+    sim.sync()
+    n0 = int(sim.read("nactive", allow_unstable=True).sum())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    sim.step(args.steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    n1 = int(sim.read("nactive", allow_unstable=True).sum())
+    sim.evaluate()
+    listed = sim.read("closure", allow_unstable=True)[:, 3] == 1.0
+    fb = sim.read("fallback", allow_unstable=True)
+    sim.close()
+    value = args.steps * 0.5 * (n0 + n1) / (ms * 1e-3)
+    print(f"[bench] closure: {args.steps} steps in {ms:.1f} ms, {value:.4g} particle-steps/s", flush=True)
+    return dict(value=value, unit="particle-steps/s", ms_per_step=ms / args.steps, tolerance=0.2,
+                listed=int(listed.sum()), fallback_fraction=float(fb[listed].mean()) if listed.any() else 0.0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +137,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--block-sweep", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
     ap.add_argument("--cell-factor", type=float, default=0.0,
@@ -198,10 +236,12 @@ def main():
                        "hbm_frac": step_bytes * value / (HBM_PEAK_GBS * 1e9)},
         "kernels": kernels,
     }
+    sim.close()
+    if not args.no_closure:
+        out["closure"] = closure_leg(sph, batch, bits, block_sweep, cell_factor, args)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(batch)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 

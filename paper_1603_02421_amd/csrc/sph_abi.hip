@@ -179,7 +179,6 @@ struct sph_ctx {
 struct sph_mlp {
     hipStream_t stream = nullptr;
     int64_t max_batch = 0;
-    int tiles_per_wave = 2;
     int t = 0;
     MlpBufs B{};
     float* grad = nullptr;
@@ -1077,7 +1076,7 @@ sph_status sph_set_closure(sph_ctx* c, const float* params) {
 
 static size_t mlp_carve(sph_mlp* t, char* base, int64_t max_batch) {
     Carver cv{base};
-    const int nw = mlp_grad_waves(max_batch, 2) + 1;
+    const int nw = mlp_grad_waves(max_batch);
     MlpBufs B{};
     B.master = cv.take<float>(MLP_NPARAMS);
     B.adam_m = cv.take<float>(MLP_NPARAMS);
@@ -1150,7 +1149,7 @@ sph_status sph_mlp_gradient(sph_mlp* t, const uint16_t* d_x, const float* d_t, i
                             float* d_loss) {
     sph_ctx* c = nullptr;
     if (!t || !d_x || !d_t || !d_grad || m < 1 || m > t->max_batch) return fail(c, SPH_EINVAL, "bad arguments");
-    launch_mlp_grad(t->B.view(), d_x, d_t, m, t->tiles_per_wave, t->partial, t->loss_part, d_grad, d_loss,
+    launch_mlp_grad(t->B.view(), d_x, d_t, m, t->partial, t->loss_part, d_grad, d_loss,
                     t->stream);
     HIP_OK(hipGetLastError());
     return SPH_OK;
@@ -1160,7 +1159,7 @@ sph_status sph_mlp_train_step(sph_mlp* t, const uint16_t* d_x, const float* d_t,
                               float* d_loss) {
     sph_ctx* c = nullptr;
     if (!t || !d_x || !d_t || m < 1 || m > t->max_batch || !(lr > 0)) return fail(c, SPH_EINVAL, "bad arguments");
-    launch_mlp_grad(t->B.view(), d_x, d_t, m, t->tiles_per_wave, t->partial, t->loss_part, t->grad,
+    launch_mlp_grad(t->B.view(), d_x, d_t, m, t->partial, t->loss_part, t->grad,
                     d_loss ? d_loss : t->loss, t->stream);
     t->t += 1;
     launch_mlp_adam(t->B, t->grad, lr, t->t, t->stream);

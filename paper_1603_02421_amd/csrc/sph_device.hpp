@@ -204,6 +204,16 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
+// atomicMin on the bit pattern of a non-negative double, skipped when the
+// stored value is already no larger (values only decrease between the clears,
+// so a stale read can only cost an unneeded atomic): thousands of waves
+// update one minimum per system, and most of them cannot lower it.
+__device__ __forceinline__ void atomic_min_bits(unsigned long long* dst, double m) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+    const unsigned long long cur = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bits < cur) atomicMin(dst, bits);
+}
+
 // Minimum of non-negative values v into dst[sys] (stored as FP64 bits, whose
 // unsigned order equals the numeric order for non-negative numbers). Every lane
 // of the wave must call this; lanes with valid = false contribute nothing.
@@ -213,10 +223,9 @@ __device__ __forceinline__ void atomic_min_per_system(unsigned long long* dst, i
     bool uniform = __all(!valid || sys == s_first);
     if (uniform) {
         double m = wave_min(valid ? v : __builtin_inf());
-        if (__lane_id() == 0 && s_first >= 0 && m < __builtin_inf())
-            atomicMin(dst + (size_t)s_first * stride, (unsigned long long)__double_as_longlong(m));
+        if (__lane_id() == 0 && s_first >= 0 && m < __builtin_inf()) atomic_min_bits(dst + (size_t)s_first * stride, m);
     } else if (valid && v < __builtin_inf()) {
-        atomicMin(dst + (size_t)sys * stride, (unsigned long long)__double_as_longlong(v));
+        atomic_min_bits(dst + (size_t)sys * stride, v);
     }
 }
 

@@ -210,9 +210,10 @@ template <typename T>
 void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* dens, T* out, hipStream_t st);
 
 void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y, int ystride, hipStream_t st);
-int mlp_grad_waves(int64_t m, int tiles_per_wave);
-void launch_mlp_grad(const MlpView& W, const uint16_t* X, const float* T, int64_t m, int tiles_per_wave,
-                     float* partial, float* loss_part, float* grad, float* loss, hipStream_t st);
+constexpr int MLP_GRAD_WAVES = 1024;
+int mlp_grad_waves(int64_t m);
+void launch_mlp_grad(const MlpView& W, const uint16_t* X, const float* T, int64_t m, float* partial,
+                     float* loss_part, float* grad, float* loss, hipStream_t st);
 void launch_mlp_set(const MlpBufs& B, const float* params, hipStream_t st);
 void launch_mlp_adam(const MlpBufs& B, const float* grad, float lr, int t, hipStream_t st);
 template <typename T>

@@ -249,8 +249,7 @@ __device__ __forceinline__ bool wave_assign(const EvalView<T>& v, int& sys, uint
 // Minimum of non-negative values over the wave into dst (one system per wave).
 __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double v, bool valid) {
     double m = wave_min(valid ? v : __builtin_inf());
-    if (__lane_id() == 0 && m < __builtin_inf())
-        atomicMin(dst, (unsigned long long)__double_as_longlong(m));
+    if (__lane_id() == 0 && m < __builtin_inf()) atomic_min_bits(dst, m);
 }
 
 // Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that

@@ -11,6 +11,8 @@
 // forward B fragments are 8 contiguous bytes per lane, and as stored (in x
 // out, row-major) for the backward products with W^T. Every kernel here runs
 // one wavefront per workgroup, so __syncthreads() is a wave barrier.
+#include <algorithm>
+
 #include "sph_internal.hpp"
 
 namespace sphjet {
@@ -338,20 +340,55 @@ __global__ void k_mlp_adam(MlpBufs B, const float* grad, float lr, float b1, flo
 
 // ----------------------------------------------------------------- closure
 
-// Stencil of each listed surface particle (one wave per particle): the
-// relative positions (r_b - r_a)/h of its fluid neighbours, the 32 nearest
-// kept (ties by particle id), expressed in the frame e1 = n_a/|n_a| (eq. 18),
-// e2 = e1 turned by +90 degrees, ordered by their angle in that frame in
-// (-pi, pi] (ties: nearer, then lower id; the cut at angle pi faces away from
-// the liquid), zero-padded; written as 64 BF16 values per row.
+// Position of the i-th set bit of m (0-based); m must have more than i set bits.
+__device__ __forceinline__ int select_bit(unsigned long long m, int i) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const unsigned long long low = (1ull << w) - 1ull;
+        const int c = __popcll(m & low);
+        if (i >= c) {
+            i -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m &= low;
+        }
+    }
+    return pos;
+}
+
+// Candidates of a listed slot: the set bits of its neighbour mask (ordinals
+// into its block of cell rows), or, when the mask overflowed, every ordinal
+// below 128 (then the distance test is redone here).
+__device__ __forceinline__ int stencil_candidates(unsigned long long m0, unsigned long long m1) {
+    if (m1 & MASK_OVERFLOW) return 128;
+    return __popcll(m0) + __popcll(m1 & ~MASK_OVERFLOW);
+}
+
+// One listed slot's stencil, built by a group of `width` lanes (32 or 64) of
+// the wave; `j` is the lane's index in the group and `lds` the group's 128
+// (width 64) or 32 (width 32) LDS slots. Every lane of the wave calls this
+// the same number of times (barriers); inactive groups pass active = false.
 template <typename T>
-__global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
-    __shared__ float sx[128], sy[128], sd[128], sa[128];
-    __shared__ uint32_t sid[128], skeep[128];
+__device__ __forceinline__ void build_stencil(const EvalView<T>& v, const ClosureView& C, uint32_t row, bool active,
+                                              int base, int width, int j, float* sx, float* sy, float* sd,
+                                              float* sa, uint32_t* sid, uint32_t* skeep) {
     const int l = __lane_id();
-    const uint32_t count = *C.count;
-    for (uint32_t row = blockIdx.x; row < count; row += gridDim.x) {
-        const uint32_t a = C.list[row];
+    uint32_t a = 0;
+    unsigned long long m0 = 0, m1 = 0;
+    int total = 0;
+    if (active) {
+        a = C.list[row];
+        m0 = v.nmask0[a];
+        m1 = v.nmask1[a];
+        total = stencil_candidates(m0, m1);
+    }
+    const bool overflow = (m1 & MASK_OVERFLOW) != 0;
+    float ix[2] = {0.f, 0.f}, iy[2] = {0.f, 0.f}, id2[2] = {0.f, 0.f}, ian[2] = {0.f, 0.f};
+    uint32_t iid[2] = {0u, 0u};
+    bool val[2] = {false, false};
+    if (active) {
         const SysDev<T>& S = v.sys[tag_sys(v.tag[a])];
         const double2 pa = v.pos[a];
         const uint32_t ny = (uint32_t)S.ny;
@@ -360,26 +397,19 @@ __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
         const int R = S.reach;
         const int ylo = cy - R < 0 ? 0 : cy - R, yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
         const int xlo = cx - R < 0 ? 0 : cx - R, xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
-        const unsigned long long m0 = v.nmask0[a], m1 = v.nmask1[a];
-        const bool overflow = (m1 & MASK_OVERFLOW) != 0;
         const float ih = 1.0f / (float)S.h;
         // e1: unit colour gradient (eq. 18, into the liquid); e2: e1 turned by +90 degrees
         const V2<T> na = v.nrm[a];
         const float nfx = (float)na.x, nfy = (float)na.y;
         const float inv_n = 1.0f / sqrtf(nfx * nfx + nfy * nfy);
         const float e1x = nfx * inv_n, e1y = nfy * inv_n;
-        // candidate ordinals lane and lane + 64; slot from the row ranges
-        float dxs[2], dys[2], d2s[2], angs[2];
-        uint32_t ids[2];
-        bool val[2];
+        const int c0 = __popcll(m0);
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            const uint32_t o = (uint32_t)l + 64u * half;
-            val[half] = false;
-            dxs[half] = dys[half] = d2s[half] = angs[half] = 0.f;
-            ids[half] = 0u;
-            bool bit = overflow ? true : (o < 64u ? ((m0 >> o) & 1ull) : (o < MASK_BITS ? ((m1 >> (o - 64u)) & 1ull) : 0ull));
-            if (!bit) continue;
+        for (int it = 0; it < 2; ++it) {
+            const int idx = j + width * it;
+            if (idx >= total || (width == 32 && it == 1)) continue;
+            const uint32_t o = overflow ? (uint32_t)idx
+                                        : (uint32_t)(idx < c0 ? select_bit(m0, idx) : 64 + select_bit(m1, idx - c0));
             uint32_t ord0 = 0, b = 0xFFFFFFFFu;
             for (int X = xlo; X <= xhi; ++X) {
                 const uint32_t rowc = S.cell_base + (uint32_t)X * ny;
@@ -389,108 +419,161 @@ __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
             }
             if (b == 0xFFFFFFFFu || b == a) continue;
             double ex, ey;
-            double r2 = pair_r2(pa, v.pos[b], ex, ey);
+            const double r2 = pair_r2(pa, v.pos[b], ex, ey);
             if (overflow && !(r2 < S.R2)) continue;
             if (tag_type(v.tag[b]) != T_FLUID) continue;
-            // relative position of b as seen from a, in units of h, then in
-            // the frame (e1, e2) of a's colour-gradient direction
+            // relative position of b as seen from a, in units of h, then in the frame (e1, e2)
             const float x = -(float)ex * ih, y = -(float)ey * ih;
             const float xl = x * e1x + y * e1y, yl = y * e1x - x * e1y;
             float ang = atan2f(yl, xl);
             if (ang == -3.14159265358979323846f) ang = 3.14159265358979323846f;
-            val[half] = true;
-            dxs[half] = xl;
-            dys[half] = yl;
-            d2s[half] = x * x + y * y;
-            angs[half] = ang;
-            ids[half] = v.id[b];
+            val[it] = true;
+            ix[it] = xl;
+            iy[it] = yl;
+            id2[it] = x * x + y * y;
+            ian[it] = ang;
+            iid[it] = v.id[b];
         }
-        // compact the valid items into LDS slots [0, k), then rank each item
-        // against the k others only (k is about 20 on a free surface)
-        const unsigned long long b0 = __ballot(val[0]), b1 = __ballot(val[1]);
-        const int k0 = __popcll(b0), k = k0 + __popcll(b1);
-        const unsigned long long below = (1ull << l) - 1ull;
+    }
+    // compact the group's valid items into its LDS slots [0, k)
+    const unsigned long long gmask = width == 64 ? ~0ull : (0xFFFFFFFFull << base);
+    const unsigned long long g0 = __ballot(val[0]) & gmask, g1 = __ballot(val[1]) & gmask;
+    const int k0 = __popcll(g0), k = k0 + __popcll(g1);
+    const unsigned long long below = (1ull << l) - 1ull;
 #pragma unroll
-        for (int hm = 0; hm < 2; ++hm) {
-            if (val[hm]) {
-                const int p = hm == 0 ? __popcll(b0 & below) : k0 + __popcll(b1 & below);
-                sx[p] = dxs[hm];
-                sy[p] = dys[hm];
-                sd[p] = d2s[hm];
-                sa[p] = angs[hm];
-                sid[p] = ids[hm];
-            }
+    for (int it = 0; it < 2; ++it) {
+        if (val[it]) {
+            const int p = it == 0 ? __popcll(g0 & below) : k0 + __popcll(g1 & below);
+            sx[p] = ix[it];
+            sy[p] = iy[it];
+            sd[p] = id2[it];
+            sa[p] = ian[it];
+            sid[p] = iid[it];
         }
-        __syncthreads();
-        // the 32 nearest (ties by id) stay
-        bool keep[2];
+    }
+    __syncthreads();
+    // the 32 nearest (ties by id) stay
+    bool keep[2] = {false, false};
 #pragma unroll
-        for (int hm = 0; hm < 2; ++hm) {
-            const int j = l + 64 * hm;
-            keep[hm] = false;
-            if (j < k) {
-                int drank = 0;
-                if (k > 32) {
-                    const float d = sd[j];
-                    const uint32_t id = sid[j];
-                    for (int q = 0; q < k; ++q) {
-                        const float od = sd[q];
-                        drank += (od < d || (od == d && sid[q] < id)) ? 1 : 0;
-                    }
+    for (int it = 0; it < 2; ++it) {
+        const int q0 = j + width * it;
+        if (q0 < k) {
+            int drank = 0;
+            if (k > 32) {
+                const float d = sd[q0];
+                const uint32_t id = sid[q0];
+                for (int q = 0; q < k; ++q) {
+                    const float od = sd[q];
+                    drank += (od < d || (od == d && sid[q] < id)) ? 1 : 0;
                 }
-                keep[hm] = drank < 32;
-                skeep[j] = keep[hm] ? 1u : 0u;
             }
+            keep[it] = drank < 32;
+            skeep[q0] = keep[it] ? 1u : 0u;
         }
-        __syncthreads();
-        // angle rank among the kept (ties: nearer, then lower id); write out
+    }
+    __syncthreads();
+    // angle rank among the kept (ties: nearer, then lower id); write the row
+    if (active) {
         uint16_t* out = C.stencil + (size_t)row * 64;
         const int nkept = k < 32 ? k : 32;
-        if (l >= 2 * nkept) out[l] = 0;
+        for (int e = j; e < 64; e += width)
+            if (e >= 2 * nkept) out[e] = 0;
 #pragma unroll
-        for (int hm = 0; hm < 2; ++hm) {
-            const int j = l + 64 * hm;
-            if (j < k && keep[hm]) {
-                const float an = sa[j], d = sd[j];
-                const uint32_t id = sid[j];
+        for (int it = 0; it < 2; ++it) {
+            const int q0 = j + width * it;
+            if (q0 < k && keep[it]) {
+                const float an = sa[q0], d = sd[q0];
+                const uint32_t id = sid[q0];
                 int arank = 0;
                 for (int q = 0; q < k; ++q) {
                     const float oa = sa[q], od = sd[q];
                     const bool before = oa < an || (oa == an && (od < d || (od == d && sid[q] < id)));
                     arank += (skeep[q] != 0u && before) ? 1 : 0;
                 }
-                out[2 * arank] = f2bf(sx[j]);
-                out[2 * arank + 1] = f2bf(sy[j]);
+                out[2 * arank] = f2bf(sx[q0]);
+                out[2 * arank + 1] = f2bf(sy[q0]);
             }
         }
-        __syncthreads();  // the LDS slots are reused by the next row
     }
+    __syncthreads();  // the LDS slots are reused by the next call
+}
+
+// Stencil of each listed surface particle: the relative positions
+// (r_b - r_a)/h of its fluid neighbours, the 32 nearest kept (ties by particle
+// id), expressed in the frame e1 = n_a/|n_a| (eq. 18), e2 = e1 turned by +90
+// degrees, ordered by their angle in that frame in (-pi, pi] (ties: nearer,
+// then lower id; the cut at angle pi faces away from the liquid), zero-padded;
+// written as 64 BF16 values per row. A wave takes two listed particles, one
+// per half, when both have at most 32 candidates (the usual case on a free
+// surface), and otherwise builds them one after the other with all 64 lanes.
+template <typename T>
+__global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
+    __shared__ float sx[128], sy[128], sd[128], sa[128];
+    __shared__ uint32_t sid[128], skeep[128];
+    const int l = __lane_id();
+    const uint32_t count = *C.count;
+    for (uint32_t pair = blockIdx.x; 2 * pair < count; pair += gridDim.x) {
+        const uint32_t r0 = 2 * pair, r1 = r0 + 1;
+        const uint32_t a0 = C.list[r0], a1 = r1 < count ? C.list[r1] : a0;
+        const int t0 = stencil_candidates(v.nmask0[a0], v.nmask1[a0]);
+        const int t1 = r1 < count ? stencil_candidates(v.nmask0[a1], v.nmask1[a1]) : 0;
+        if (t0 <= 32 && t1 <= 32) {
+            const int g = l >> 5;
+            build_stencil<T>(v, C, g ? r1 : r0, g ? r1 < count : true, 32 * g, 32, l & 31, sx + 64 * g,
+                             sy + 64 * g, sd + 64 * g, sa + 64 * g, sid + 64 * g, skeep + 64 * g);
+        } else {
+            build_stencil<T>(v, C, r0, true, 0, 64, l, sx, sy, sd, sa, sid, skeep);
+            build_stencil<T>(v, C, r1, r1 < count, 0, 64, l, sx, sy, sd, sa, sid, skeep);
+        }
+    }
+}
+
+// What the closure step of one listed particle reads besides the network's
+// output; loaded before the network runs so the loads overlap its products.
+template <typename T>
+struct ApplyIn {
+    uint32_t a;
+    int sys;
+    T h, tol, sigma, k_plain, rho;
+    V2<T> n_a, acc;
+    bool overflow;
+};
+
+template <typename T>
+__device__ __forceinline__ ApplyIn<T> closure_apply_load(const EvalView<T>& v, uint32_t a) {
+    ApplyIn<T> in;
+    in.a = a;
+    in.sys = (int)tag_sys(v.tag[a]);
+    const SysDev<T>& S = v.sys[in.sys];
+    in.h = S.h;
+    in.tol = S.closure_tol;
+    in.sigma = S.sigma;
+    in.k_plain = v.kappa_plain[a];
+    in.rho = v.eos[a].z;
+    in.n_a = v.nrm[a];
+    in.acc = v.acc[a];
+    in.overflow = (v.nmask1[a] & MASK_OVERFLOW) != 0ull;
+    return in;
 }
 
 // Surface-tension acceleration of one listed particle from the network's
 // output y = (n_1, n_2, kappa h) (normal in the frame of n_a), or from the plain
 // estimate where the network's curvature deviates from it by more than the
 // tolerance (eq. 24); completes the total acceleration (eq. 25) and returns
-// its eq. 30 limit and the particle's system.
+// its eq. 30 limit.
 template <typename T>
-__device__ __forceinline__ double closure_apply_row(const EvalView<T>& v, const ClosureView& C, uint32_t a,
-                                                    float y0, float y1, float y2, int& sys) {
-    sys = (int)tag_sys(v.tag[a]);
-    const SysDev<T>& S = v.sys[sys];
-    const T h = S.h;
-    const T k_mlp = (T)y2 / h;
-    const T k_plain = v.kappa_plain[a];
-    const V2<T> n_a = v.nrm[a];
-    const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
+__device__ __forceinline__ double closure_apply_row(const EvalView<T>& v, const ClosureView& C,
+                                                    const ApplyIn<T>& in, float y0, float y1, float y2) {
+    const T k_mlp = (T)y2 / in.h;
+    const T mag = sqrt_(in.n_a.x * in.n_a.x + in.n_a.y * in.n_a.y);
     // network normal from the frame (e1, e2) of n_a back to x, y
-    const T e1x = n_a.x / mag, e1y = n_a.y / mag;
+    const T e1x = in.n_a.x / mag, e1y = in.n_a.y / mag;
     T nx = (T)y0 * e1x - (T)y1 * e1y, ny = (T)y0 * e1y + (T)y1 * e1x;
     const T nm = sqrt_(nx * nx + ny * ny);
-    const bool fb = fabs(k_mlp - k_plain) > S.closure_tol * fabs(k_plain) || !(nm > T(0)) ||
-                    (v.nmask1[a] & MASK_OVERFLOW) != 0ull;
+    const bool fb = fabs(k_mlp - in.k_plain) > in.tol * fabs(in.k_plain) || !(nm > T(0)) || in.overflow;
     T kappa;
     if (fb) {
-        kappa = k_plain;
+        kappa = in.k_plain;
         nx = e1x;
         ny = e1y;
     } else {
@@ -498,15 +581,15 @@ __device__ __forceinline__ double closure_apply_row(const EvalView<T>& v, const 
         nx /= nm;
         ny /= nm;
     }
-    const T f = -S.sigma / v.eos[a].z * kappa * mag;
-    V2<T> acc = v.acc[a];
+    const T f = -in.sigma / in.rho * kappa * mag;
+    V2<T> acc = in.acc;
     acc.x += f * nx;
     acc.y += f * ny;
-    v.acc[a] = acc;
-    v.kappa[a] = kappa;
-    C.fallback[a] = fb ? 1u : 0u;
+    v.acc[in.a] = acc;
+    v.kappa[in.a] = kappa;
+    C.fallback[in.a] = fb ? 1u : 0u;
     const T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
-    return am > T(0) ? sqrt((double)S.h / (double)am) : __builtin_inf();
+    return am > T(0) ? sqrt((double)in.h / (double)am) : __builtin_inf();
 }
 
 // The network on the listed stencils, 16 rows per wave and tile, followed by
@@ -519,24 +602,25 @@ __global__ void __launch_bounds__(64) k_closure_net(EvalView<T> v, ClosureView C
     const int64_t m = (int64_t)*C.count;
     const int64_t ntiles = (m + 15) / 16;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t row = t * 16 + l;
+        const bool valid = l < 16 && row < m;
+        ApplyIn<T> in{};
+        if (valid) in = closure_apply_load<T>(v, C.list[row]);
         load_tile(C.stencil, m, t * 16, xs);
         f4 H1[4], H2[4], y;
         mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
         if (r < 3) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int64_t row = t * 16 + 4 * g + i;
+                const int64_t rr = t * 16 + 4 * g + i;
                 ys[(4 * g + i) * 4 + r] = y[i];
-                if (row < m) C.out[row * 4 + r] = y[i];
+                if (rr < m) C.out[rr * 4 + r] = y[i];
             }
         }
         __syncthreads();
-        const int64_t row = t * 16 + l;
-        const bool valid = l < 16 && row < m;
-        int sys = 0;
         double dtf = __builtin_inf();
-        if (valid) dtf = closure_apply_row<T>(v, C, C.list[row], ys[l * 4], ys[l * 4 + 1], ys[l * 4 + 2], sys);
-        if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, sys, dtf, valid);
+        if (valid) dtf = closure_apply_row<T>(v, C, in, ys[l * 4], ys[l * 4 + 1], ys[l * 4 + 2]);
+        if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, in.sys, dtf, valid);
         __syncthreads();
     }
 }
@@ -549,15 +633,19 @@ void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y
     k_mlp_forward<<<grid, 64, 0, st>>>(W, X, m, Y, ystride);
 }
 
-int mlp_grad_waves(int64_t m, int tiles_per_wave) {
-    int64_t ntiles = (m + 15) / 16;
-    return (int)((ntiles + tiles_per_wave - 1) / tiles_per_wave);
+// Waves of the gradient kernel for m rows: one per 16-row tile, at most
+// MLP_GRAD_WAVES (each then takes a contiguous run of tiles), so the partial
+// sums stay within MLP_GRAD_WAVES x MLP_NPARAMS floats.
+int mlp_grad_waves(int64_t m) {
+    const int64_t ntiles = (m + 15) / 16;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, MLP_GRAD_WAVES));
 }
 
-void launch_mlp_grad(const MlpView& W, const uint16_t* X, const float* T, int64_t m, int tiles_per_wave,
-                     float* partial, float* loss_part, float* grad, float* loss, hipStream_t st) {
-    int nw = mlp_grad_waves(m, tiles_per_wave);
-    if (nw < 1) nw = 1;
+void launch_mlp_grad(const MlpView& W, const uint16_t* X, const float* T, int64_t m, float* partial,
+                     float* loss_part, float* grad, float* loss, hipStream_t st) {
+    const int nw = mlp_grad_waves(m);
+    const int64_t ntiles = (m + 15) / 16;
+    const int tiles_per_wave = (int)((ntiles + nw - 1) / nw);
     k_mlp_grad<<<nw, 64, 0, st>>>(W, X, T, m, tiles_per_wave, partial, loss_part);
     k_mlp_reduce<<<(MLP_NPARAMS + 255) / 256, 256, 0, st>>>(partial, nw, grad, loss_part, loss,
                                                              1.0f / (float)(m * 3));
@@ -577,12 +665,15 @@ template <typename T>
 void launch_closure(const EvalView<T>& v, const ClosureView& C, const MlpView& W, int64_t capacity, hipStream_t st,
                     KernelTimer* kt) {
     kt->begin("closure_stencil", st);
-    k_stencil<T><<<4096, 64, 0, st>>>(v, C);
+    // grids sized for the listed particles a system of this size can have
+    // (a free surface lists a few percent), at least one wave per SIMD
+    const unsigned sgrid = (unsigned)std::min<int64_t>(65536, std::max<int64_t>(1024, capacity / 64));
+    k_stencil<T><<<sgrid, 64, 0, st>>>(v, C);
     kt->end(st);
     kt->begin("closure_net", st);
-    k_closure_net<T><<<2048, 64, 0, st>>>(v, C, W);
+    const unsigned ngrid = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1024, capacity / 512));
+    k_closure_net<T><<<ngrid, 64, 0, st>>>(v, C, W);
     kt->end(st);
-    (void)capacity;
 }
 
 template void launch_closure<float>(const EvalView<float>&, const ClosureView&, const MlpView&, int64_t,
