@@ -108,11 +108,17 @@ def main(argv=None):
     ap.add_argument("--bench-steps", type=int, default=2000)
     ap.add_argument("--cost-n", type=int, default=300_000)
     ap.add_argument("--no-mirror", action="store_true", help="no mirror images of the training stencils")
+    ap.add_argument("--eval-only", action="store_true", help="skip data and training; evaluate the weights")
+    ap.add_argument("--weights", default="", help="weights file for --eval-only (default: the shipped ones)")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     snap_steps = [int(x) for x in a.snap_steps.split(",")]
     rep = dict(args=vars(a))
 
+    if a.eval_only:
+        w = cl.load(a.weights) if a.weights else cl.load()
+        evaluate_and_cost(cl, w, a, snap_steps, rep)
+        return
     t0 = time.time()
     shapes = cl.shape_systems(a.shapes, seed=a.seed)
     Xs, Ts, Ps, _ = cl.harvest_shapes(shapes)
@@ -136,6 +142,10 @@ def main(argv=None):
     cl.save(w, os.path.join(a.out, "closure_weights.npz"))
     del X, T
     log(f"[train] done in {time.time() - t1:.1f} s, final loss {hist[-1]:.4e}")
+    evaluate_and_cost(cl, w, a, snap_steps, rep)
+
+
+def evaluate_and_cost(cl, w, a, snap_steps, rep):
 
     # held-out shapes (exact labels)
     ho = cl.shape_systems(a.held_out_shapes, seed=a.seed + 1000)
