@@ -52,6 +52,82 @@ ALGO_BYTES = {
 }
 
 
+KERNEL_NAMES = {  # device function -> the name the library's profiler gives it
+    "k_colour": "colour", "k_main": "main", "k_surface": "surface", "k_permute": "sort_permute",
+    "k_predict": "predict", "k_correct": "correct", "k_key": "sort_key", "k_scatter": "sort_scatter",
+    "k_cellsort": "sort_cells", "k_stencil": "closure_stencil", "k_closure_net": "closure_net",
+}
+
+
+def sources_digest() -> str:
+    """SHA-256 of the HIP sources: measured traffic applies only to the kernels it was taken on."""
+    import hashlib
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1603_02421_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            d.update(f.encode() + b"\0" + fh.read())
+    return d.hexdigest()
+
+
+def traffic_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def measured_traffic(workload: str, cell_factor: float, block_sweep: int, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, when it was taken on these sources and this launch shape."""
+    try:
+        with open(traffic_path(workload)) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    if abs(t.get("cell_factor", 0) - cell_factor) > 1e-9 or t.get("block_sweep") != block_sweep:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
+def _pmc(path: str, counter: str):
+    import collections
+    import csv
+    out = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").split("::")[-1]
+            out[name].append(float(r["Counter_Value"]))
+    return out
+
+
+def write_traffic(args):
+    """Turn four rocprofv3 --pmc counter files (FETCH_SIZE and WRITE_SIZE of
+    the workload, and of the 1 GiB copy) into profiles/traffic_<workload>.json."""
+    import statistics
+    fetch, write, cfetch, cwrite = args.traffic_from
+    copy_bytes = float(1 << 30)
+    cf = max(v for vals in _pmc(cfetch, "FETCH_SIZE").values() for v in vals) * 1024.0
+    cw = max(v for vals in _pmc(cwrite, "WRITE_SIZE").values() for v in vals) * 1024.0
+    fs, ws = copy_bytes / cf, copy_bytes / cw
+    f, w = _pmc(fetch, "FETCH_SIZE"), _pmc(write, "WRITE_SIZE")
+    kernels = {}
+    for dev, name in KERNEL_NAMES.items():
+        if dev in f and dev in w:
+            kernels[name] = dict(fetch_bytes=statistics.median(f[dev]) * 1024.0 * fs,
+                                 write_bytes=statistics.median(w[dev]) * 1024.0 * ws, dispatches=len(f[dev]))
+    out = dict(workload=args.workload, cell_factor=args.cell_factor, block_sweep=args.block_sweep,
+               sources_sha256=sources_digest(), fetch_scale=fs, write_scale=ws,
+               note="median HBM bytes per dispatch, rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB) scaled by the "
+                    "factors a plain 1 GiB device copy gives (bench.py --copy-calibration)",
+               kernels=kernels)
+    with open(traffic_path(args.workload), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def make_workload(name: str):
     import workloads as wl
     if name == "c3":
@@ -145,7 +221,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (keep the scenario cell size)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_<workload>.json from rocprofv3 --pmc counter files "
+                         "(needs --cell-factor and --block-sweep of the profiled run)")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -230,7 +312,8 @@ def main():
                    "n_active": n_act, "closure": "plain", "graph": True, "instability_flags": flags,
                    "autotune": tune},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, cell_factor, block_sweep, dom),
                      "algo_bytes_per_particle": ALGO_BYTES[dom], "avg_launch_ms": avg},
         "step_model": {"algo_bytes_per_particle_step": step_bytes,
                        "hbm_frac": step_bytes * value / (HBM_PEAK_GBS * 1e9)},
