@@ -38,10 +38,10 @@ HBM_PEAK_GBS = 8000.0
 # (neighbour re-reads are the reuse the cell order provides and are not
 # counted). Layout: pos 16 (FP64 pair), vel 8, dens 4, mass 4, tag 4, id 4,
 # cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, c,
-# rho, m), neighbour mask 16.
+# rho, m/rho), neighbour mask 20 (one word per cell row).
 ALGO_BYTES = {
-    "colour": 16 + 4 + 4 + 4 + 16,                        # pos vol cell -> colour mask
-    "main": 4 + 16 + 8 + 16 + 4 + 16 + 4 + 4 + 8 + 8,     # tag pos vel eos colour mask cell -> drho acc nrm
+    "colour": 16 + 4 + 4 + 4 + 20,                        # pos vol cell -> colour mask
+    "main": 4 + 16 + 8 + 16 + 4 + 20 + 4 + 4 + 8 + 8,     # tag pos vel eos colour mask cell -> drho acc nrm
     "surface": 4 + 8 + 8 + 4 + 8 + 4 + 4,                 # tag nrm acc rho -> acc kappa kappa_plain (bulk)
     "predict": 4 + 16 + 8 + 4 + 4 + 8 + 4 + 16 + 8 + 4 + 4 + 16,  # tag pos vel dens drho acc mass -> half state, vol, eos
     "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,       # tag pos vel dens drho acc -> pos vel dens

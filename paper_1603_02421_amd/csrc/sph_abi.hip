@@ -215,8 +215,8 @@ struct Impl : sph_ctx_base {
     T *colour = nullptr, *drho = nullptr, *kappa = nullptr, *kappa_plain = nullptr, *aux = nullptr;
     T* vol = nullptr;
     V4<T>* eos = nullptr;
-    unsigned long long* nmask0 = nullptr;
-    unsigned long long* nmask1 = nullptr;
+    uint4* nmask = nullptr;
+    uint32_t* nmask4 = nullptr;
     // learned closure (only when some system uses it)
     bool closure = false;
     ClosureView cl{};
@@ -288,8 +288,8 @@ struct Impl : sph_ctx_base {
         aux = cv.take<T>(n_ < 2 ? 2 : n_);
         vol = cv.take<T>(n_);
         eos = cv.take<V4<T>>(n_);
-        nmask0 = cv.take<unsigned long long>(n_);
-        nmask1 = cv.take<unsigned long long>(n_);
+        nmask = cv.take<uint4>(n_);
+        nmask4 = cv.take<uint32_t>(n_);
         int64_t nb = (n_ + block_stream - 1) / block_stream;
         sb.trash = trash;
         sb.cstart = cv.take<uint32_t>((size_t)trash + 2);
@@ -341,8 +341,8 @@ struct Impl : sph_ctx_base {
         v.dtmin = dtmin;
         v.vol = vol;
         v.eos = eos;
-        v.nmask0 = nmask0;
-        v.nmask1 = nmask1;
+        v.nmask = nmask;
+        v.nmask4 = nmask4;
         if (closure) {
             v.cl_count = cl.count;
             v.cl_list = cl.list;

@@ -30,12 +30,18 @@ template <> struct V4t<float> { using type = float4; };
 template <> struct V4t<double> { using type = double4; };
 template <typename T> using V4 = typename V4t<T>::type;
 
-// The colour sweep records which of a particle's candidates (the slots of its
-// neighbouring cells, numbered row by row) passed the pair predicate, as a
-// 128-bit mask. Bit 127 marks a particle with more than 127 candidates; the
-// later sweeps then scan its cells again instead of reading the mask.
-constexpr uint32_t MASK_BITS = 127;
-constexpr unsigned long long MASK_OVERFLOW = 1ull << 63;
+// The colour sweep records which of a particle's candidates passed the pair
+// predicate as one 32-bit word per cell row of its block (at most 5 rows): bit
+// k of word r is the k-th slot of row r's slot range. Row 4 keeps bits 0..30;
+// bit 31 of word 4 marks a particle with a row of more candidates than its
+// word holds, whose later sweeps scan its cells again instead.
+constexpr uint32_t MASK_ROW_BITS = 32;
+constexpr uint32_t MASK_OVERFLOW = 1u << 31;
+
+// The mask words of one particle.
+struct RowMask {
+    uint32_t w[5];
+};
 
 // Per-system constants, precomputed on the host.
 template <typename T>
@@ -177,7 +183,7 @@ __device__ __forceinline__ void tait(const SysDev<T>& S, T dens, T& rho, T& p_ov
 }
 
 // Per-particle quantities every neighbour sum needs, computed once per
-// evaluation: vol = m / rho and eos = (P / rho^2, c, rho, m).
+// evaluation: vol = m / rho and eos = (P / rho^2, c, rho, m / rho).
 template <typename T>
 __device__ __forceinline__ void particle_props(const SysDev<T>& S, T dens, T mass, T& vol, V4<T>& eos) {
     T rho, pr, c;
@@ -186,7 +192,7 @@ __device__ __forceinline__ void particle_props(const SysDev<T>& S, T dens, T mas
     eos.x = pr;
     eos.y = c;
     eos.z = rho;
-    eos.w = mass;
+    eos.w = vol;
 }
 
 template <typename T>

@@ -70,9 +70,9 @@ struct EvalView {
     T* kappa_plain;
     unsigned long long* dtmin;  // 2 per system: [h/(c+sig) min, sqrt(h/|a|) min]
     const T* vol;               // m / rho of every slot (this evaluation's state)
-    const V4<T>* eos;           // (P / rho^2, c, rho, m)
-    unsigned long long* nmask0;  // n: neighbour mask, candidates 0..63
-    unsigned long long* nmask1;  // n: candidates 64..126 (+ overflow bit)
+    const V4<T>* eos;           // (P / rho^2, c, rho, m / rho)
+    uint4* nmask;                // n: neighbour mask words of cell rows 0..3
+    uint32_t* nmask4;            // n: word of row 4 (+ overflow bit 31)
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
     uint32_t* cl_list;
     uint32_t cl_capacity;

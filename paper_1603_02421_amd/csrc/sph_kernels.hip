@@ -258,10 +258,10 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 // the accepted ones (load(b)), then compute(b, dx, dy, payload) with
 // r_ab = r_a - r_b in the working precision. Slot ranges come straight from
 // the cell starts: with the y index fastest, each cell row is one range.
-template <typename T, typename LoadFn, typename ComputeFn>
-__device__ __forceinline__ void scan_cells_ord(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
-                                               uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
-                                               ComputeFn&& compute) {
+template <typename T, int NB = 4, typename LoadFn, typename ComputeFn, typename RowEndFn>
+__device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
+                                                uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
+                                                ComputeFn&& compute, RowEndFn&& row_end) {
     using P = typename std::decay<decltype(load(0u))>::type;
     const uint32_t ny = (uint32_t)S.ny;
     const uint32_t local = cell - S.cell_base;
@@ -273,42 +273,42 @@ __device__ __forceinline__ void scan_cells_ord(const SysDev<T>& S, const uint32_
     const int xlo = cx - R < 0 ? 0 : cx - R;
     const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
     const double R2 = S.R2;
-    uint32_t ord0 = 0;   // ordinal of the first candidate of the row
-    for (int X = xlo; X <= xhi; ++X) {
+    int r = 0;   // row of the block, 0 at x = xlo
+    for (int X = xlo; X <= xhi; ++X, ++r) {
         const uint32_t row = S.cell_base + (uint32_t)X * ny;
         const uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
-        for (uint32_t b = b0; b < b1; b += 4) {
-            double2 q[4];
+        for (uint32_t b = b0; b < b1; b += NB) {
+            double2 q[NB];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) q[k] = pos[b + k < b1 ? b + k : b1 - 1];
-            bool ok[4];
-            T dx[4], dy[4];
+            for (int k = 0; k < NB; ++k) q[k] = pos[b + k < b1 ? b + k : b1 - 1];
+            bool ok[NB];
+            T dx[NB], dy[NB];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < NB; ++k) {
                 double ex, ey;
                 double r2 = pair_r2(pa, q[k], ex, ey);
                 ok[k] = (b + k < b1) && (b + k != a) && (r2 < R2);
                 dx[k] = (T)ex;
                 dy[k] = (T)ey;
             }
-            P pl[4] = {};
+            P pl[NB] = {};
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < NB; ++k)
                 if (ok[k]) pl[k] = load(b + k);
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (ok[k]) compute(b + k, ord0 + (b + k - b0), dx[k], dy[k], pl[k]);
+            for (int k = 0; k < NB; ++k)
+                if (ok[k]) compute(b + k, b + k - b0, dx[k], dy[k], pl[k]);
         }
-        ord0 += b1 - b0;
+        row_end(r);
     }
 }
 
-template <typename T, typename LoadFn, typename ComputeFn>
+template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
                                            uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
                                            ComputeFn&& compute) {
-    scan_cells_ord<T>(S, cstart, cell, a, pa, pos, load,
-                      [&](uint32_t b, uint32_t, T dx, T dy, const auto& p) { compute(b, dx, dy, p); });
+    scan_cells_rows<T, NB>(S, cstart, cell, a, pa, pos, load,
+                       [&](uint32_t b, uint32_t, T dx, T dy, const auto& p) { compute(b, dx, dy, p); }, [](int) {});
 }
 
 // Reference-style visitor, one candidate at a time (debug neighbour lists).
@@ -335,14 +335,13 @@ __device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_
     }
 }
 
-// Visit the neighbours recorded in slot a's candidate mask, four at a time
-// (positions and payloads, then compute). A mask bit is a candidate ordinal;
-// the row ranges of the cell block turn it back into a slot. r_ab = r_a - r_b
-// is formed in FP64 exactly as in the scan.
-template <typename T, typename LoadFn, typename ComputeFn>
+// Visit the neighbours recorded in slot a's mask words, four at a time
+// (positions and payloads, then compute). Bit k of word r is the k-th slot of
+// cell row r of the block; r_ab = r_a - r_b is formed in FP64 exactly as in
+// the scan.
+template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
-                                                unsigned long long m0, unsigned long long m1, LoadFn&& load,
-                                                ComputeFn&& compute) {
+                                                const RowMask& M, LoadFn&& load, ComputeFn&& compute) {
     using P = typename std::decay<decltype(load(0u))>::type;
     const uint32_t ny = (uint32_t)S.ny;
     const uint32_t local = v.cell[a] - S.cell_base;
@@ -350,52 +349,65 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
     const int cy = (int)(local - (uint32_t)cx * ny);
     const int R = S.reach;
     const int ylo = cy - R < 0 ? 0 : cy - R;
-    const int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
     const int xlo = cx - R < 0 ? 0 : cx - R;
     const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
-    // slot = ordinal + shift[row], rows ending at ordinal end[row]
-    uint32_t shift[5], end[4];
-    uint32_t ord0 = 0;
+    // first slot of every row of the block (rows past the grid edge have no bits)
+    uint32_t st[5];
 #pragma unroll
     for (int r = 0; r < 5; ++r) {
         const int X = xlo + r;
-        uint32_t b0 = 0, len = 0;
-        if (X <= xhi) {
-            const uint32_t row = S.cell_base + (uint32_t)X * ny;
-            b0 = v.cstart[row + ylo];
-            len = v.cstart[row + yhi + 1] - b0;
-        }
-        shift[r] = b0 - ord0;
-        ord0 += len;
-        if (r < 4) end[r] = X <= xhi ? ord0 : 0xFFFFFFFFu;
+        st[r] = X <= xhi ? v.cstart[S.cell_base + (uint32_t)X * ny + ylo] : 0u;
     }
-    while (m0 | m1) {
-        uint32_t bb[4];
-        bool ok[4];
+    // queue of (word, first slot) of the non-empty rows, front in (m, base);
+    // built once, so taking the next bit never has to skip an empty row
+    uint32_t qm[5] = {0u, 0u, 0u, 0u, 0u}, qb[5] = {0u, 0u, 0u, 0u, 0u};
+    int nq = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            uint32_t o = 0;
-            ok[j] = (m0 | m1) != 0ull;
-            if (m0) {
-                o = (uint32_t)__ffsll((long long)m0) - 1u;
-                m0 &= m0 - 1ull;
-            } else if (m1) {
-                o = 64u + (uint32_t)__ffsll((long long)m1) - 1u;
-                m1 &= m1 - 1ull;
-            }
-            uint32_t sh = o < end[0] ? shift[0] : o < end[1] ? shift[1] : o < end[2] ? shift[2]
-                        : o < end[3] ? shift[3] : shift[4];
-            bb[j] = ok[j] ? o + sh : a;
+    for (int r = 0; r < 5; ++r) {
+        // append row r when its word is non-empty (selects, no indexing)
+        const bool put = M.w[r] != 0u;
+#pragma unroll
+        for (int i = 0; i <= r; ++i) {
+            const bool here = put && nq == i;
+            qm[i] = here ? M.w[r] : qm[i];
+            qb[i] = here ? st[r] : qb[i];
         }
-        double2 q[4];
+        nq += put ? 1 : 0;
+    }
+    uint32_t m = qm[0], base = qb[0];
+    uint32_t m1 = qm[1], b1 = qb[1], m2 = qm[2], b2 = qb[2], m3 = qm[3], b3 = qb[3], m4 = qm[4], b4 = qb[4];
+    // next recorded neighbour; false once every word is spent
+    auto next = [&](uint32_t& b) -> bool {
+        const bool ok = m != 0u;
+        b = ok ? base + (uint32_t)__builtin_ctz(m) : a;
+        m &= m - 1u;
+        const bool adv = m == 0u;
+        m = adv ? m1 : m;
+        base = adv ? b1 : base;
+        m1 = adv ? m2 : m1;
+        b1 = adv ? b2 : b1;
+        m2 = adv ? m3 : m2;
+        b2 = adv ? b3 : b2;
+        m3 = adv ? m4 : m3;
+        b3 = adv ? b4 : b3;
+        m4 = adv ? 0u : m4;
+        return ok;
+    };
+    while (true) {
+        uint32_t bb[NB];
+        bool ok[NB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) q[j] = v.pos[bb[j]];
-        P pl[4] = {};
+        for (int j = 0; j < NB; ++j) ok[j] = next(bb[j]);
+        if (!ok[0]) break;
+        double2 q[NB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NB; ++j) q[j] = v.pos[bb[j]];
+        P pl[NB] = {};
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
             if (ok[j]) pl[j] = load(bb[j]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NB; ++j) {
             if (ok[j]) {
                 double ex, ey;
                 pair_r2(pa, q[j], ex, ey);
@@ -405,14 +417,25 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
     }
 }
 
+__device__ __forceinline__ RowMask load_mask(const uint4* nmask, const uint32_t* nmask4, uint32_t a) {
+    const uint4 w = nmask[a];
+    RowMask M;
+    M.w[0] = w.x;
+    M.w[1] = w.y;
+    M.w[2] = w.z;
+    M.w[3] = w.w;
+    M.w[4] = nmask4[a];
+    return M;
+}
+
 // The neighbours of slot a: from its mask, or by scanning its cells when it
 // had more candidates than the mask holds.
-template <typename T, typename LoadFn, typename ComputeFn>
+template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
                                            LoadFn&& load, ComputeFn&& compute) {
-    const unsigned long long m0 = v.nmask0[a], m1 = v.nmask1[a];
-    if (!(m1 & MASK_OVERFLOW)) mask_neighbours<T>(v, S, a, pa, m0, m1, load, compute);
-    else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute);
+    const RowMask M = load_mask(v.nmask, v.nmask4, a);
+    if (!(M.w[4] & MASK_OVERFLOW)) mask_neighbours<T, NB>(v, S, a, pa, M, load, compute);
+    else scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute);  // rare: keep it lean
 }
 
 template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; T col; uint32_t tag; };
@@ -421,8 +444,10 @@ template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 // Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included
 // (eq. 14). The cell scan of this sweep also records which candidates passed
 // the pair predicate, for the two sweeps that follow.
+// Eight waves per SIMD (at most 64 VGPRs): the candidate scan is issue-bound
+// and hides its gathers best with the most waves (measured 5% faster than 7).
 template <typename T>
-__global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_colour(EvalView<T> v) {
     int sys;
     uint32_t a;
     if (!wave_assign(v, sys, a)) return;
@@ -431,12 +456,21 @@ __global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
     const KernelConsts<T> K = kconsts(S);
     const double2 pa = v.pos[a];
     T sum = v.vol[a] * S.W0;
-    unsigned long long m0 = 0, m1 = 0;
+    // mask words: `cur` collects the row being scanned, row_end files it
+    RowMask M = {{0u, 0u, 0u, 0u, 0u}};
+    uint32_t cur = 0;
     bool overflow = false;
-    auto mark = [&](uint32_t ord) {
-        if (ord < 64u) m0 |= 1ull << ord;
-        else if (ord < MASK_BITS) m1 |= 1ull << (ord - 64u);
+    auto mark = [&](uint32_t k) {
+        if (k < MASK_ROW_BITS) cur |= 1u << k;
         else overflow = true;
+    };
+    auto row_end = [&](int r) {
+        M.w[0] = r == 0 ? cur : M.w[0];
+        M.w[1] = r == 1 ? cur : M.w[1];
+        M.w[2] = r == 2 ? cur : M.w[2];
+        M.w[3] = r == 3 ? cur : M.w[3];
+        M.w[4] = r == 4 ? cur : M.w[4];
+        cur = 0;
     };
     auto load = [&](uint32_t b) { return v.vol[b]; };
     auto acc = [&](uint32_t, T dx, T dy, T vol_b) { sum += vol_b * kernel_w(K, sqrt_(dx * dx + dy * dy)); };
@@ -445,21 +479,24 @@ __global__ void __launch_bounds__(256) k_colour(EvalView<T> v) {
         // predicate alone, recorded as the mask, then the kernel sum over the
         // accepted neighbours only, so lanes do not pay for each other's
         // accepted candidates
-        scan_cells_ord<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
-                          [&](uint32_t, uint32_t ord, T, T, int) { mark(ord); });
-        if (!overflow) mask_neighbours<T>(v, S, a, pa, m0, m1, load, acc);
+        scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
+                           [&](uint32_t, uint32_t k, T, T, int) { mark(k); }, row_end);
+        if (!overflow) mask_neighbours<T>(v, S, a, pa, M, load, acc);
         else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc);
     } else {
         // 5 x 5 blocks (about 2.2 candidates per neighbour): one pass
-        scan_cells_ord<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
-                          [&](uint32_t b, uint32_t ord, T dx, T dy, T vol_b) {
-                              acc(b, dx, dy, vol_b);
-                              mark(ord);
-                          });
+        scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
+                           [&](uint32_t b, uint32_t k, T dx, T dy, T vol_b) {
+                               acc(b, dx, dy, vol_b);
+                               mark(k);
+                           },
+                           row_end);
     }
+    // bit 31 of the last word is the overflow flag, so that row holds 31 bits
+    if (M.w[4] & MASK_OVERFLOW) overflow = true;
     v.colour[a] = sum;
-    v.nmask0[a] = m0;
-    v.nmask1[a] = overflow ? (m1 | MASK_OVERFLOW) : m1;
+    v.nmask[a] = make_uint4(M.w[0], M.w[1], M.w[2], M.w[3]);
+    v.nmask4[a] = overflow ? (M.w[4] | MASK_OVERFLOW) : M.w[4];
 }
 
 // Sweep 2: continuity (eq. 7) for every active particle (a boundary particle
@@ -484,7 +521,7 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
         const T Ca = v.colour[a];
         const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
         const KernelConsts<T> K = kconsts(S);
-        T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, vsig = 0;
+        T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, sig_vr = 0, sig_r2 = 1;
         neighbours<T>(v, S, a, pa,
             [&](uint32_t b) {
                 Pay2<T> p;
@@ -496,15 +533,19 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
             },
             [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
                 if (!fluid && tag_type(p.tag) != T_FLUID) return;
-                const T pr_b = p.eos.x, c_b = p.eos.y, rho_b = p.eos.z, m_b = p.eos.w;
+                const T pr_b = p.eos.x, c_b = p.eos.y, rho_b = p.eos.z, vol_b = p.eos.w;
+                const T m_b = vol_b * rho_b;
                 T r2 = dx * dx + dy * dy;
                 T F = kernel_f(K, sqrt_(r2));
                 T ux = va.x - p.vel.x, uy = va.y - p.vel.y;
                 T vr = ux * dx + uy * dy;
-                drho += m_b * F * vr;
-                T ir2 = rcp(r2);
-                T sg = fabs(h * vr * ir2);
-                vsig = sg > vsig ? sg : vsig;
+                const T mF = m_b * F;
+                drho += mF * vr;
+                // signal term max_b |v_ab . r_ab| / r_ab^2, kept as a fraction
+                const T avr = fabs(vr);
+                const bool up = avr * sig_r2 > sig_vr * r2;
+                sig_vr = up ? avr : sig_vr;
+                sig_r2 = up ? r2 : sig_r2;
                 if (fluid) {
                     T pi = 0;
                     if (vr < T(0)) {
@@ -512,14 +553,15 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
                         T rbar = T(0.5) * (rho_a + rho_b);
                         pi = -alpha_h * cbar * vr * rcp(rbar * (r2 + eta2));
                     }
-                    T coef = m_b * (pr_a + pr_b + pi) * F;
+                    T coef = mF * (pr_a + pr_b + pi);
                     ax -= coef * dx;
                     ay -= coef * dy;
-                    T cn = m_b * rcp(rho_b) * (p.col - Ca) * F;
+                    T cn = vol_b * (p.col - Ca) * F;
                     nx += cn * dx;
                     ny += cn * dy;
                 }
             });
+        const T vsig = h * sig_vr / sig_r2;
         v.drho[a] = drho;
         V2<T> acc, nrm;
         acc.x = ax;

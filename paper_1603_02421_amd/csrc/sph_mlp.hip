@@ -340,13 +340,14 @@ __global__ void k_mlp_adam(MlpBufs B, const float* grad, float lr, float b1, flo
 
 // ----------------------------------------------------------------- closure
 
-// Position of the i-th set bit of m (0-based); m must have more than i set bits.
-__device__ __forceinline__ int select_bit(unsigned long long m, int i) {
+// Position of the i-th set bit of the 32-bit word m (0-based); m must have
+// more than i set bits.
+__device__ __forceinline__ int select_bit(uint32_t m, int i) {
     int pos = 0;
 #pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) {
-        const unsigned long long low = (1ull << w) - 1ull;
-        const int c = __popcll(m & low);
+    for (int w = 16; w >= 1; w >>= 1) {
+        const uint32_t low = (1u << w) - 1u;
+        const int c = __popc(m & low);
         if (i >= c) {
             i -= c;
             m >>= w;
@@ -358,12 +359,23 @@ __device__ __forceinline__ int select_bit(unsigned long long m, int i) {
     return pos;
 }
 
-// Candidates of a listed slot: the set bits of its neighbour mask (ordinals
-// into its block of cell rows), or, when the mask overflowed, every ordinal
-// below 128 (then the distance test is redone here).
-__device__ __forceinline__ int stencil_candidates(unsigned long long m0, unsigned long long m1) {
-    if (m1 & MASK_OVERFLOW) return 128;
-    return __popcll(m0) + __popcll(m1 & ~MASK_OVERFLOW);
+// Candidates of a listed slot: the set bits of its mask words, or, when the
+// mask overflowed, every slot of its block up to the 128th (then the distance
+// test is redone here).
+__device__ __forceinline__ int stencil_candidates(const RowMask& M) {
+    if (M.w[4] & MASK_OVERFLOW) return 128;
+    return __popc(M.w[0]) + __popc(M.w[1]) + __popc(M.w[2]) + __popc(M.w[3]) + __popc(M.w[4]);
+}
+
+__device__ __forceinline__ RowMask closure_mask(const uint4* nmask, const uint32_t* nmask4, uint32_t a) {
+    const uint4 w = nmask[a];
+    RowMask M;
+    M.w[0] = w.x;
+    M.w[1] = w.y;
+    M.w[2] = w.z;
+    M.w[3] = w.w;
+    M.w[4] = nmask4[a];
+    return M;
 }
 
 // One listed slot's stencil, built by a group of `width` lanes (32 or 64) of
@@ -376,15 +388,14 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
                                               float* sa, uint32_t* sid, uint32_t* skeep) {
     const int l = __lane_id();
     uint32_t a = 0;
-    unsigned long long m0 = 0, m1 = 0;
+    RowMask M = {{0u, 0u, 0u, 0u, 0u}};
     int total = 0;
     if (active) {
         a = C.list[row];
-        m0 = v.nmask0[a];
-        m1 = v.nmask1[a];
-        total = stencil_candidates(m0, m1);
+        M = closure_mask(v.nmask, v.nmask4, a);
+        total = stencil_candidates(M);
     }
-    const bool overflow = (m1 & MASK_OVERFLOW) != 0;
+    const bool overflow = (M.w[4] & MASK_OVERFLOW) != 0;
     float ix[2] = {0.f, 0.f}, iy[2] = {0.f, 0.f}, id2[2] = {0.f, 0.f}, ian[2] = {0.f, 0.f};
     uint32_t iid[2] = {0u, 0u};
     bool val[2] = {false, false};
@@ -403,19 +414,25 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
         const float nfx = (float)na.x, nfy = (float)na.y;
         const float inv_n = 1.0f / sqrtf(nfx * nfx + nfy * nfy);
         const float e1x = nfx * inv_n, e1y = nfy * inv_n;
-        const int c0 = __popcll(m0);
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             const int idx = j + width * it;
             if (idx >= total || (width == 32 && it == 1)) continue;
-            const uint32_t o = overflow ? (uint32_t)idx
-                                        : (uint32_t)(idx < c0 ? select_bit(m0, idx) : 64 + select_bit(m1, idx - c0));
+            // the idx-th candidate: the idx-th set bit over the rows' words, or,
+            // after an overflow, the idx-th slot of the block
             uint32_t ord0 = 0, b = 0xFFFFFFFFu;
-            for (int X = xlo; X <= xhi; ++X) {
+            int r = 0;
+            for (int X = xlo; X <= xhi; ++X, ++r) {
                 const uint32_t rowc = S.cell_base + (uint32_t)X * ny;
-                const uint32_t b0 = v.cstart[rowc + ylo], b1 = v.cstart[rowc + yhi + 1];
-                if (o < ord0 + (b1 - b0)) { b = b0 + (o - ord0); break; }
-                ord0 += b1 - b0;
+                const uint32_t b0 = v.cstart[rowc + ylo];
+                const uint32_t wr = r == 0 ? M.w[0] : r == 1 ? M.w[1] : r == 2 ? M.w[2] : r == 3 ? M.w[3] : M.w[4];
+                const uint32_t cnt = overflow ? v.cstart[rowc + yhi + 1] - b0 : (uint32_t)__popc(wr);
+                if ((uint32_t)idx < ord0 + cnt) {
+                    const uint32_t k = (uint32_t)idx - ord0;
+                    b = b0 + (overflow ? k : (uint32_t)select_bit(wr, (int)k));
+                    break;
+                }
+                ord0 += cnt;
             }
             if (b == 0xFFFFFFFFu || b == a) continue;
             double ex, ey;
@@ -515,8 +532,8 @@ __global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
     for (uint32_t pair = blockIdx.x; 2 * pair < count; pair += gridDim.x) {
         const uint32_t r0 = 2 * pair, r1 = r0 + 1;
         const uint32_t a0 = C.list[r0], a1 = r1 < count ? C.list[r1] : a0;
-        const int t0 = stencil_candidates(v.nmask0[a0], v.nmask1[a0]);
-        const int t1 = r1 < count ? stencil_candidates(v.nmask0[a1], v.nmask1[a1]) : 0;
+        const int t0 = stencil_candidates(closure_mask(v.nmask, v.nmask4, a0));
+        const int t1 = r1 < count ? stencil_candidates(closure_mask(v.nmask, v.nmask4, a1)) : 0;
         if (t0 <= 32 && t1 <= 32) {
             const int g = l >> 5;
             build_stencil<T>(v, C, g ? r1 : r0, g ? r1 < count : true, 32 * g, 32, l & 31, sx + 64 * g,
@@ -552,7 +569,7 @@ __device__ __forceinline__ ApplyIn<T> closure_apply_load(const EvalView<T>& v, u
     in.rho = v.eos[a].z;
     in.n_a = v.nrm[a];
     in.acc = v.acc[a];
-    in.overflow = (v.nmask1[a] & MASK_OVERFLOW) != 0ull;
+    in.overflow = (v.nmask4[a] & MASK_OVERFLOW) != 0u;
     return in;
 }
 
