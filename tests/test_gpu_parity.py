@@ -163,6 +163,33 @@ def test_short_trajectory_fp32_jet(gpu, orc, use_graph):
         assert np.array_equal(sim.read("type"), st.type)
 
 
+def test_fast_particles_within_the_cell_skin(gpu, orc):
+    """Particles moving 0.04-0.08h in the half step, close to the 0.1h the
+    cell skin allows (cells of 2.2h, one ring): the half-step evaluation,
+    which reuses the cells sorted at step start, still finds every pair
+    within 2h and the step matches the oracle."""
+    cloud = wl.random_cloud(1500, extent=25.0, seed=11, vel_scale=0.0, gravity=(0.0, 0.0))
+    rng = np.random.Generator(np.random.PCG64(12))
+    ang = rng.uniform(0.0, 2 * np.pi, cloud.n)
+    mag = rng.uniform(0.5, 1.0, cloud.n) * 10.0
+    cloud.vel = np.stack([np.cos(ang), np.sin(ang)], axis=1) * mag[:, None]
+    cloud.vel[cloud.type == wl.WALL] = 0.0
+    h = cloud.params["h"]
+    cloud.params["dt_fixed"] = 0.16 * h / 10.0
+    obj = wl.round_for_dtype(cloud, 32)
+    fl = obj.type == wl.FLUID
+    half = np.linalg.norm(obj.vel[fl], axis=1) * cloud.params["dt_fixed"] / 2
+    assert half.max() > 0.05 * h and half.max() < 0.1 * h   # close to the cell skin, inside it
+    say(f"[trajectory fp32] fast cloud n={obj.n}, half-step displacement up to {half.max() / h:.3f} h")
+    st = orc.State(obj)
+    with _sim(gpu, obj) as sim:
+        sim.step(1)
+        st.step(1)
+        ep, er, ev = _traj_errors(sim, st, 1.0, 1.0)
+        say(f"   1 step: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
+        assert ep <= 1e-4 and er <= 1e-4 and ev <= 1e-4
+
+
 def test_trajectory_fp64_dam_break(gpu, orc):
     obj = wl.dam_break()
     say(f"[trajectory fp64] dam_break n={obj.n}")
