@@ -211,7 +211,9 @@ sph_status sph_profile(sph_ctx* ctx, int32_t n_steps, int32_t max_stats, const c
  * cell sizes 1.05, 1.1, 1.2 h (5 x 5 cell blocks) and 2.05, 2.2 h (3 x 3) and
  * block_sweep 128 and 256, a throwaway context is built from the given initial
  * state inside d_workspace (the caller's arrays are not modified), run for two
- * warm-up steps and trial_steps timed steps, and freed. Configurations whose
+ * warm-up steps and two windows of trial_steps timed steps (the faster window
+ * counts), and freed. A configuration later in that order replaces the best so
+ * far only when it is more than 2% faster. Configurations whose
  * workspace exceeds ws_bytes are skipped; size the workspace with
  * sph_workspace_bytes() at cell_size = 1.05 h to allow all of them. The winner
  * is cached per process by (dtype, number of systems, log2 of the particle
