@@ -88,3 +88,25 @@ def test_init_rejects_null_workspace_without_touching_the_gpu():
     st = L.sph_init(None, 1, P, vp(off), vp(s.pos), vp(s.vel), vp(s.rho), vp(s.mass), vp(s.type),
                     None, 0, None, C.byref(ctx))
     assert st == -1 and ctx.value is None
+
+
+def test_trainer_workspace_and_argument_checks_without_the_gpu():
+    from paper_1603_02421_amd import native
+    L = native.load()
+    out = C.c_size_t(0)
+    assert L.sph_mlp_workspace_bytes(0, C.byref(out)) == -1
+    sizes = []
+    for m in (16, 4096, 16 * 1024, 16 * 1024 * 8):
+        assert L.sph_mlp_workspace_bytes(m, C.byref(out)) == 0
+        sizes.append(out.value)
+    # the per-wave gradient partials grow with the batch up to 1024 waves, then stop
+    assert sizes[0] < sizes[1] < sizes[2] == sizes[3]
+    assert sizes[2] >= 1024 * native.MLP_NPARAMS * 4
+    h = C.c_void_p()
+    w = np.zeros(native.MLP_NPARAMS, dtype=np.float32)
+    assert L.sph_mlp_create(None, 16, None, 0, None, C.byref(h)) == -1 and h.value is None
+    assert L.sph_mlp_create(w.ctypes.data_as(C.c_void_p), 0, None, 0, None, C.byref(h)) == -1
+    assert L.sph_mlp_gradient(None, None, None, 16, None, None) == -1
+    assert L.sph_mlp_train_step(None, None, None, 16, C.c_float(1e-3), None) == -1
+    assert L.sph_mlp_forward(None, None, 16, None) == -1
+    assert "bad arguments" in L.sph_last_error(None).decode()

@@ -206,19 +206,19 @@ def _stencil_rows_match(g_row, o_row, frame_err):
     return True, bool(tie or wrap)
 
 
-@pytest.mark.parametrize("name", list(CL_CASES))
+@pytest.mark.parametrize("name,bits", [(n, 32) for n in CL_CASES] + [("jet", 64)])
 @pytest.mark.parametrize("tol", [0.2, math.inf])
-def test_closure_evaluation_fp32(gpu, orc, name, tol):
+def test_closure_evaluation(gpu, orc, name, bits, tol):
     obj = CL_CASES[name]
-    obj = wl.Batch([wl.round_for_dtype(s, 32) for s in obj.systems]) if hasattr(obj, "systems") \
-        else wl.round_for_dtype(obj, 32)
+    obj = wl.Batch([wl.round_for_dtype(s, bits) for s in obj.systems]) if hasattr(obj, "systems") \
+        else wl.round_for_dtype(obj, bits)
     systems = obj.systems if hasattr(obj, "systems") else [obj]
     for s in systems:
         if s.params.get("closure"):
             s.params["closure_tol"] = 1e30 if math.isinf(tol) else tol
     w = _params(13, scale=0.3)
-    say(f"[closure eval] case={name} tol={tol} n={obj.n}")
-    with gpu.Simulation(obj, dtype_bits=32) as sim:
+    say(f"[closure eval] case={name} fp{bits} tol={tol} n={obj.n}")
+    with gpu.Simulation(obj, dtype_bits=bits) as sim:
         sim.set_closure(w)
         sim.evaluate()
         G = dict(st=sim.read("stencil"), out=sim.read("closure"), fb=sim.read("fallback"),
