@@ -3,7 +3,9 @@ WCSPH sweeps with surface tension and a predictor-corrector step, in HIP,
 behind the C-ABI of include/sph.h.
 
 ``Simulation`` is a thin ctypes handle on that library; PyTorch only provides
-device memory and the stream.
+device memory and the stream. ``closure`` holds the learned curvature closure's
+trainer handle, training data and shipped weights; ``train_closure`` trains and
+evaluates it.
 """
 from . import native  # noqa: F401
 from .sim import Simulation, autotune  # noqa: F401
