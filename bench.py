@@ -40,15 +40,15 @@ HBM_PEAK_GBS = 8000.0
 # cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, c,
 # rho, m/rho), neighbour mask 20 (one word per cell row).
 ALGO_BYTES = {
-    "colour": 16 + 4 + 4 + 4 + 20,                        # pos vol cell -> colour mask
-    "main": 4 + 16 + 8 + 16 + 4 + 20 + 4 + 4 + 8 + 8,     # tag pos vel eos colour mask cell -> drho acc nrm
+    "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20,               # pos vol cell dens -> colour eos mask
+    "main": 4 + 16 + 8 + 16 + 20 + 4 + 4 + 8 + 8,         # tag pos vel eos mask cell -> drho acc nrm
     "surface": 4 + 8 + 8 + 4 + 8 + 4 + 4,                 # tag nrm acc rho -> acc kappa kappa_plain (bulk)
-    "predict": 4 + 16 + 8 + 4 + 4 + 8 + 4 + 16 + 8 + 4 + 4 + 16,  # tag pos vel dens drho acc mass -> half state, vol, eos
+    "predict": 4 + 16 + 8 + 4 + 4 + 8 + 4 + 16 + 8 + 4 + 4,  # tag pos vel dens drho acc mass -> half state, vol
     "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,       # tag pos vel dens drho acc -> pos vel dens
     "sort_key": 16 + 4 + 4 + 4,                           # pos tag -> key slot
     "sort_scatter": 4 + 4 + 4 + 4 + 4,                    # key slot id -> tmp_src tmp_id
     "sort_cells": 16,                                     # tmp_src tmp_id read + write
-    "sort_permute": 4 + 4 + 4 + 36 + 40 + 4 + 4 + 16,     # tmp_src tmp_id key X -> Y cell vol eos
+    "sort_permute": 4 + 4 + 4 + 36 + 40 + 4 + 4,          # tmp_src tmp_id key X -> Y cell vol
 }
 
 

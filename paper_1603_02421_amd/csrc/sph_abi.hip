@@ -378,13 +378,12 @@ struct Impl : sph_ctx_base {
         v.flags = flags;
         v.mass = S.mass;
         v.vol = vol;
-        v.eos = eos;
         return v;
     }
 
     // Sort the current buffer into the other one; the other becomes current.
     void sort(hipStream_t st, KernelTimer* kt) {
-        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], vol, eos, st, kt);
+        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], vol, st, kt);
         cur ^= 1;
     }
 

@@ -159,46 +159,43 @@ __device__ __forceinline__ T kernel_f(const KernelConsts<T>& K, T r) {
     return K.gnorm * T(-0.75) * u * u * rcp(q);
 }
 
-// Tait equation: P / rho^2 and the sound speed from the stored deviation
-// dens = rho - rho0. With gamma = 7, (1 + d)^7 - 1 is expanded in d so a small
-// compression keeps its relative precision.
+// Tait equation: P / rho^2 from the stored deviation dens = rho - rho0. With
+// gamma = 7, (1 + d)^7 - 1 is expanded in d so a small compression keeps its
+// relative precision.
 template <typename T>
-__device__ __forceinline__ void tait(const SysDev<T>& S, T dens, T& rho, T& p_over_rho2, T& c) {
+__device__ __forceinline__ void tait(const SysDev<T>& S, T dens, T& rho, T& p_over_rho2) {
     T d = dens * S.inv_rho0;
     rho = S.rho0 + dens;
     T irho = rcp(rho);
-    T P, cr;
+    T P;
     if (S.gamma7) {
         T e = d * (T(7) + d * (T(21) + d * (T(35) + d * (T(35) + d * (T(21) + d * (T(7) + d))))));
         P = S.B * e;
-        T s = T(1) + d;
-        cr = s * s * s;
     } else {
-        T l = log1p(d);
-        P = S.B * expm1(S.gamma * l);
-        cr = exp(S.half_gm1 * l);
+        P = S.B * expm1(S.gamma * log1p(d));
     }
     p_over_rho2 = P * irho * irho;
-    c = S.c0 * cr;
 }
 
-// Per-particle quantities every neighbour sum needs, computed once per
-// evaluation: vol = m / rho and eos = (P / rho^2, c, rho, m / rho).
+// Sound speed of the Tait equation, c = c0 (rho / rho0)^((gamma - 1) / 2),
+// from the density itself (the sweeps keep rho, not c, per particle).
 template <typename T>
-__device__ __forceinline__ void particle_props(const SysDev<T>& S, T dens, T mass, T& vol, V4<T>& eos) {
-    T rho, pr, c;
-    tait(S, dens, rho, pr, c);
-    vol = mass * rcp(rho);
-    eos.x = pr;
-    eos.y = c;
-    eos.z = rho;
-    eos.w = vol;
+__device__ __forceinline__ T sound_speed(const SysDev<T>& S, T rho) {
+    const T s = rho * S.inv_rho0;
+    if (S.gamma7) return S.c0 * s * s * s;
+    return S.c0 * exp(S.half_gm1 * log(s));
+}
+
+// m / rho, which the colour sum needs of every neighbour.
+template <typename T>
+__device__ __forceinline__ T particle_vol(const SysDev<T>& S, T dens, T mass) {
+    return mass * rcp(S.rho0 + dens);
 }
 
 template <typename T>
 __device__ __forceinline__ T tait_pressure(const SysDev<T>& S, T dens) {
-    T rho, pr, c;
-    tait(S, dens, rho, pr, c);
+    T rho, pr;
+    tait(S, dens, rho, pr);
     return pr * rho * rho;
 }
 

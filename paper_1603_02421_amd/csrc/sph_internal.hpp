@@ -70,7 +70,7 @@ struct EvalView {
     T* kappa_plain;
     unsigned long long* dtmin;  // 2 per system: [h/(c+sig) min, sqrt(h/|a|) min]
     const T* vol;               // m / rho of every slot (this evaluation's state)
-    const V4<T>* eos;           // (P / rho^2, c, rho, m / rho)
+    V4<T>* eos;                 // (P / rho^2, colour, rho, m / rho), written by the colour sweep
     uint4* nmask;                // n: neighbour mask words of cell rows 0..3
     uint32_t* nmask4;            // n: word of row 4 (+ overflow bit 31)
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
@@ -149,8 +149,7 @@ struct IntegView {
     const double* dt;
     const double* time;
     uint32_t* flags;
-    T* vol;                // per-particle quantities of the half-step state
-    V4<T>* eos;
+    T* vol;                // m / rho of the half-step state
 };
 
 struct LaunchCfg {
@@ -190,7 +189,7 @@ void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st);
 
 template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
-                 T* vol, V4<T>* eos, hipStream_t st, KernelTimer* kt);
+                 T* vol, hipStream_t st, KernelTimer* kt);
 template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt);
 template <typename T>

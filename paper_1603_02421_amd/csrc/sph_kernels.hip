@@ -176,11 +176,11 @@ __global__ void k_cellsort(uint32_t ncells, const uint32_t* cstart, uint32_t* tm
     }
 }
 
-// Gather the state into cell order; also the per-particle quantities of the
-// first evaluation of the step.
+// Gather the state into cell order; also m / rho for the first evaluation of
+// the step.
 template <typename T>
 __global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* tmp_src, const uint32_t* tmp_id,
-                          const uint32_t* key, StateBuf<T> X, StateBuf<T> Y, uint32_t* cell, T* vol, V4<T>* eos) {
+                          const uint32_t* key, StateBuf<T> X, StateBuf<T> Y, uint32_t* cell, T* vol) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     uint32_t s = tmp_src[j];
@@ -193,13 +193,7 @@ __global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* tmp_src, 
     Y.tag[j] = t;
     Y.id[j] = tmp_id[j];
     cell[j] = key[s];
-    if (tag_type(t) != T_INACTIVE) {
-        T vl;
-        V4<T> e;
-        particle_props(sys[tag_sys(t)], dens, mass, vl, e);
-        vol[j] = vl;
-        eos[j] = e;
-    }
+    if (tag_type(t) != T_INACTIVE) vol[j] = particle_vol(sys[tag_sys(t)], dens, mass);
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -438,12 +432,15 @@ __device__ __forceinline__ void neighbours(const EvalView<T>& v, const SysDev<T>
     else scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute);  // rare: keep it lean
 }
 
-template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; T col; uint32_t tag; };
+template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; uint32_t tag; };
 template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 
 // Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included
 // (eq. 14). The cell scan of this sweep also records which candidates passed
-// the pair predicate, for the two sweeps that follow.
+// the pair predicate, for the two sweeps that follow, and the Tait equation
+// (eq. 26) is evaluated here once per particle: the record (P / rho^2, C, rho,
+// m / rho) is everything the main sweep gathers of a neighbour besides its
+// position and velocity (the sound speed follows from rho).
 // Eight waves per SIMD (at most 64 VGPRs): the candidate scan is issue-bound
 // and hides its gathers best with the most waves (measured 5% faster than 7).
 template <typename T>
@@ -455,7 +452,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     if (a >= v.sys_hi[sys]) return;
     const KernelConsts<T> K = kconsts(S);
     const double2 pa = v.pos[a];
-    T sum = v.vol[a] * S.W0;
+    const T vol_a = v.vol[a];
+    const T dens_a = v.dens[a];   // for the record written at the end
+    T sum = vol_a * S.W0;
     // mask words: `cur` collects the row being scanned, row_end files it
     RowMask M = {{0u, 0u, 0u, 0u, 0u}};
     uint32_t cur = 0;
@@ -495,6 +494,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     // bit 31 of the last word is the overflow flag, so that row holds 31 bits
     if (M.w[4] & MASK_OVERFLOW) overflow = true;
     v.colour[a] = sum;
+    // the record the later sweeps gather of every neighbour
+    T rho_a, pr_a;
+    tait(S, dens_a, rho_a, pr_a);
+    V4<T> e;
+    e.x = pr_a;
+    e.y = sum;
+    e.z = rho_a;
+    e.w = vol_a;
+    v.eos[a] = e;
     v.nmask[a] = make_uint4(M.w[0], M.w[1], M.w[2], M.w[3]);
     v.nmask4[a] = overflow ? (M.w[4] | MASK_OVERFLOW) : M.w[4];
 }
@@ -517,8 +525,8 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
         const double2 pa = v.pos[a];
         const V2<T> va = v.vel[a];
         const V4<T> ea = v.eos[a];
-        const T pr_a = ea.x, c_a = ea.y, rho_a = ea.z;
-        const T Ca = v.colour[a];
+        const T pr_a = ea.x, Ca = ea.y, rho_a = ea.z;
+        const T c_a = sound_speed(S, rho_a);
         const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
         const KernelConsts<T> K = kconsts(S);
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, sig_vr = 0, sig_r2 = 1;
@@ -527,13 +535,12 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
                 Pay2<T> p;
                 p.vel = v.vel[b];
                 p.eos = v.eos[b];
-                p.col = fluid ? v.colour[b] : T(0);
                 p.tag = fluid ? 0u : v.tag[b];
                 return p;
             },
             [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
                 if (!fluid && tag_type(p.tag) != T_FLUID) return;
-                const T pr_b = p.eos.x, c_b = p.eos.y, rho_b = p.eos.z, vol_b = p.eos.w;
+                const T pr_b = p.eos.x, C_b = p.eos.y, rho_b = p.eos.z, vol_b = p.eos.w;
                 const T m_b = vol_b * rho_b;
                 T r2 = dx * dx + dy * dy;
                 T F = kernel_f(K, sqrt_(r2));
@@ -549,14 +556,14 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
                 if (fluid) {
                     T pi = 0;
                     if (vr < T(0)) {
-                        T cbar = T(0.5) * (c_a + c_b);
+                        T cbar = T(0.5) * (c_a + sound_speed(S, rho_b));
                         T rbar = T(0.5) * (rho_a + rho_b);
                         pi = -alpha_h * cbar * vr * rcp(rbar * (r2 + eta2));
                     }
                     T coef = mF * (pr_a + pr_b + pi);
                     ax -= coef * dx;
                     ay -= coef * dy;
-                    T cn = vol_b * (p.col - Ca) * F;
+                    T cn = vol_b * (C_b - Ca) * F;
                     nx += cn * dx;
                     ny += cn * dy;
                 }
@@ -690,13 +697,7 @@ __global__ void k_predict(IntegView<T> v) {
     T dh = v.dens[a] + hdt * v.drho[a];
     if (ty != T_FLUID && dh < T(0)) dh = T(0);   // boundaries never below rho0: they only repel
     v.dens_h[a] = dh;
-    {
-        T vl;
-        V4<T> e;
-        particle_props(S, dh, v.mass[a], vl, e);
-        v.vol[a] = vl;
-        v.eos[a] = e;
-    }
+    v.vol[a] = particle_vol(S, dh, v.mass[a]);
     if (ty == T_FLUID) {
         V2<T> acc = v.acc[a];
         double2 q;
@@ -846,7 +847,7 @@ void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st) {
 
 template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
-                 T* vol, V4<T>* eos, hipStream_t st, KernelTimer* kt) {
+                 T* vol, hipStream_t st, KernelTimer* kt) {
     const int n = L.n;
     const int bs = L.block_stream;
     const uint32_t trash = B.trash;
@@ -866,7 +867,7 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     k_cellsort<<<nblk(trash, 256), 256, 0, st>>>(trash, B.cstart, B.tmp_src, B.tmp_id);
     kt->end(st);
     kt->begin("sort_permute", st);
-    k_permute<T><<<nb, bs, 0, st>>>(n, sys, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell, vol, eos);
+    k_permute<T><<<nb, bs, 0, st>>>(n, sys, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell, vol);
     kt->end(st);
     kt->begin("wave_table", st);
     k_wave_table<<<1, 1024, 0, st>>>(L.n_sys, B.sys_cell_base, B.cstart, B.sys_lo, B.sys_hi, B.chunk_base);
@@ -933,7 +934,7 @@ void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* 
 
 #define SPHJET_INSTANTIATE(T)                                                                               \
     template void launch_sort<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,        \
-                                 StateBuf<T>, T*, V4<T>*, hipStream_t, KernelTimer*);                      \
+                                 StateBuf<T>, T*, hipStream_t, KernelTimer*);                              \
     template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t, KernelTimer*);         \
     template void launch_dt<T>(int, const SysDev<T>*, unsigned long long*, double*, hipStream_t,           \
                                KernelTimer*);                                                              \
