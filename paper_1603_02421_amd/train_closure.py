@@ -32,23 +32,31 @@ def log(*a):
     print(*a, flush=True)
 
 
-TRAIN_JETS = [  # (nD coarse, Re, We, seed, piston amplitude)
+# (nD coarse, Re, We, seed, piston amplitude). The jet of the closure workload:
+# D = 20 dx, Re 500, We 20, kD 0.7, labelled by runs at 4x resolution; seeds
+# 100-103 are held out.
+TRAIN_JETS = [(20, 500.0, 20.0, seed, 0.01) for seed in range(8)]
+HELD_OUT_JETS = [(20, 500.0, 20.0, seed, 0.01) for seed in (100, 101, 102, 103)]
+# smaller, more varied jets (D = 10-16 dx, other Re/We, stronger inflow perturbation)
+SWEEP_JETS = [
     (10, 500.0, 20.0, 11, 0.01), (10, 200.0, 10.0, 12, 0.2), (12, 1000.0, 30.0, 13, 0.01),
     (12, 300.0, 8.0, 14, 0.2), (16, 800.0, 15.0, 15, 0.1), (10, 1500.0, 40.0, 16, 0.2),
     (14, 400.0, 25.0, 17, 0.1), (16, 2000.0, 50.0, 18, 0.01),
 ]
-HELD_OUT_JETS = [(10, 700.0, 12.0, 101, 0.1), (12, 250.0, 35.0, 102, 0.2), (16, 1200.0, 20.0, 103, 0.01)]
+SWEEP_HELD_OUT = [(10, 700.0, 12.0, 101, 0.1), (12, 250.0, 35.0, 102, 0.2), (16, 1200.0, 20.0, 103, 0.01)]
 
 
-def jet_sets(spec, snap_steps, n_fine, free_length):
+def jet_sets(spec, snap_steps, n_coarse, free_length):
+    """Coarse labelled sets from jets run at 4x resolution: the fine run has
+    16 n_coarse particles, so that its tank matches a coarse jet of n_coarse."""
     from . import closure as cl
     out = []
     from .native import SphError
     for (nD, Re, We, seed, amp) in spec:
         t0 = time.time()
         try:
-            snaps = cl.fine_jet_snapshots(nD, Re, We, seed, snap_steps, n_fine=n_fine, free_length=free_length,
-                                          piston_amp=amp)
+            snaps = cl.fine_jet_snapshots(nD, Re, We, seed, snap_steps, n_fine=16 * n_coarse,
+                                          free_length=free_length, piston_amp=amp)
         except SphError as e:
             log(f"[jets] nD={nD} Re={Re} We={We} amp={amp}: skipped ({e})")
             continue
@@ -91,16 +99,25 @@ def throughput(system, params, steps, closure: bool):
                 seconds_per_unit_time=dt / tau)
 
 
+def _snaps(text):
+    return [int(x) for x in text.split(",")]
+
+
 def main(argv=None):
     from . import closure as cl
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--shapes", type=int, default=4000)
     ap.add_argument("--held-out-shapes", type=int, default=400)
-    ap.add_argument("--jets", type=int, default=len(TRAIN_JETS))
-    ap.add_argument("--snap-steps", type=str, default="6000,12000,18000,24000,30000")
-    ap.add_argument("--n-fine", type=int, default=400_000)
-    ap.add_argument("--free-length", type=float, default=40.0)
+    ap.add_argument("--jets", type=int, default=len(TRAIN_JETS), help="training jets of the D = 20 dx workload")
+    ap.add_argument("--jet-n", type=int, default=300_000, help="particles of a coarse D = 20 dx jet")
+    ap.add_argument("--jet-free-length", type=float, default=60.0)
+    ap.add_argument("--jet-snap-steps", type=str, default="4000,8000,12000,16000,20000,24000,28000,32000",
+                    help="steps of the 4x-resolution run after which it is sampled")
+    ap.add_argument("--sweep-jets", type=int, default=len(SWEEP_JETS), help="smaller, varied jets to add")
+    ap.add_argument("--sweep-n", type=int, default=25_000)
+    ap.add_argument("--sweep-free-length", type=float, default=40.0)
+    ap.add_argument("--sweep-snap-steps", type=str, default="6000,12000,18000,24000,30000")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -108,23 +125,24 @@ def main(argv=None):
     ap.add_argument("--bench-steps", type=int, default=2000)
     ap.add_argument("--cost-n", type=int, default=300_000)
     ap.add_argument("--no-mirror", action="store_true", help="no mirror images of the training stencils")
+    ap.add_argument("--skip-eval", action="store_true", help="stop after training")
     ap.add_argument("--eval-only", action="store_true", help="skip data and training; evaluate the weights")
     ap.add_argument("--weights", default="", help="weights file for --eval-only (default: the shipped ones)")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
-    snap_steps = [int(x) for x in a.snap_steps.split(",")]
     rep = dict(args=vars(a))
 
     if a.eval_only:
         w = cl.load(a.weights) if a.weights else cl.load()
-        evaluate_and_cost(cl, w, a, snap_steps, rep)
+        evaluate_and_cost(cl, w, a, rep)
         return
     t0 = time.time()
     shapes = cl.shape_systems(a.shapes, seed=a.seed)
     Xs, Ts, Ps, _ = cl.harvest_shapes(shapes)
     del shapes
     log(f"[data] shapes: {len(Xs)} neighbourhoods ({time.time() - t0:.1f} s)")
-    jets = jet_sets(TRAIN_JETS[:a.jets], snap_steps, a.n_fine, a.free_length)
+    jets = jet_sets(TRAIN_JETS[:a.jets], _snaps(a.jet_snap_steps), a.jet_n, a.jet_free_length)
+    jets += jet_sets(SWEEP_JETS[:a.sweep_jets], _snaps(a.sweep_snap_steps), a.sweep_n, a.sweep_free_length)
     Xj, Tj, Pj, _, _ = cl.harvest_coarse(jets)
     del jets
     log(f"[data] jets: {len(Xj)} neighbourhoods ({time.time() - t0:.1f} s)")
@@ -142,11 +160,26 @@ def main(argv=None):
     cl.save(w, os.path.join(a.out, "closure_weights.npz"))
     del X, T
     log(f"[train] done in {time.time() - t1:.1f} s, final loss {hist[-1]:.4e}")
-    evaluate_and_cost(cl, w, a, snap_steps, rep)
+    if a.skip_eval:
+        with open(os.path.join(a.out, "closure_report.json"), "w") as f:
+            json.dump(rep, f, indent=1)
+        log("[done]")
+        return
+    evaluate_and_cost(cl, w, a, rep)
 
 
-def evaluate_and_cost(cl, w, a, snap_steps, rep):
+def held_out_jets(cl, w, spec, snaps, n, free_length):
+    hj = jet_sets(spec, snaps, n, free_length)
+    X2, T2, P2, K2, F2 = cl.harvest_coarse(hj, params=w)
+    Y2 = cl.predict(w, X2)
+    nh = Y2[:, :2] / np.linalg.norm(Y2[:, :2], axis=1, keepdims=True)
+    ang = np.degrees(np.arccos(np.clip(np.einsum("ij,ij->i", nh, T2[:, :2]), -1, 1)))
+    r = errors(T2[:, 2], P2, Y2[:, 2], K2)
+    r.update(fallback_fraction=float(F2.mean()), normal_angle_deg_median=float(np.median(ang)))
+    return r
 
+
+def evaluate_and_cost(cl, w, a, rep):
     # held-out shapes (exact labels)
     ho = cl.shape_systems(a.held_out_shapes, seed=a.seed + 1000)
     Xh, Th, Ph, Ih = cl.harvest_shapes(ho)
@@ -160,16 +193,14 @@ def evaluate_and_cost(cl, w, a, snap_steps, rep):
         if m.any():
             rep[f"held_out_shapes_{name}"] = errors(Th[m, 2], Ph[m], Yh[m, 2], cl.apply_fallback(Yh[m, 2], Ph[m]))
             log(f"[eval]   {name}: {rep[f'held_out_shapes_{name}']}")
-    # held-out jets, with the closure's curvature taken from the particle update
-    hj = jet_sets(HELD_OUT_JETS, snap_steps, a.n_fine, a.free_length)
-    X2, T2, P2, K2, F2 = cl.harvest_coarse(hj, params=w)
-    Y2 = cl.predict(w, X2)
-    ang = np.degrees(np.arccos(np.clip(np.einsum("ij,ij->i", Y2[:, :2] / np.linalg.norm(Y2[:, :2], axis=1,
-                                                                                          keepdims=True), T2[:, :2]),
-                                       -1, 1)))
-    rep["held_out_jets"] = errors(T2[:, 2], P2, Y2[:, 2], K2)
-    rep["held_out_jets"].update(fallback_fraction=float(F2.mean()), normal_angle_deg_median=float(np.median(ang)))
-    log(f"[eval] held-out jets: {rep['held_out_jets']}")
+    # held-out jets (the D = 20 dx workload at seeds 100-103, and varied smaller
+    # jets), with the closure's curvature taken from the particle update
+    rep["held_out_jets"] = held_out_jets(cl, w, HELD_OUT_JETS, _snaps(a.jet_snap_steps), a.jet_n,
+                                         a.jet_free_length)
+    log(f"[eval] held-out jets (D = 20 dx): {rep['held_out_jets']}")
+    rep["held_out_sweep_jets"] = held_out_jets(cl, w, SWEEP_HELD_OUT, _snaps(a.sweep_snap_steps), a.sweep_n,
+                                               a.sweep_free_length)
+    log(f"[eval] held-out jets (D = 10-16 dx): {rep['held_out_sweep_jets']}")
 
     # cost: plain vs closure on a jet at D = 20 dx, and the same jet at 4x
     # resolution (D = 80 dx, 16x the particles, plain), per unit simulated time
