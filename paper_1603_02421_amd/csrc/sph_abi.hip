@@ -292,12 +292,13 @@ struct Impl : sph_ctx_base {
         nmask4 = cv.take<uint32_t>(n_);
         int64_t nb = (n_ + block_stream - 1) / block_stream;
         sb.trash = trash;
+        sb.count = cv.take<uint32_t>((size_t)trash + 1);
         sb.cstart = cv.take<uint32_t>((size_t)trash + 2);
         sb.key = cv.take<uint32_t>(n_);
         sb.slot = cv.take<uint32_t>(n_);
         sb.blk = cv.take<uint32_t>(nb + 1);
-        sb.part = cv.take<uint32_t>(((int64_t)trash + 1 + SCAN_TILE - 1) / SCAN_TILE + 1);
-        sb.part2 = cv.take<uint32_t>((nb + SCAN_TILE - 1) / SCAN_TILE + 1);
+        sb.part = cv.take<uint32_t>(scan_tiles((int64_t)trash + 1) + 1);
+        sb.part2 = cv.take<uint32_t>(scan_tiles(nb) + 1);
         sb.tmp_src = cv.take<uint32_t>(n_);
         sb.tmp_id = cv.take<uint32_t>(n_);
         sb.cell = cv.take<uint32_t>(n_);
@@ -833,6 +834,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     launch_fill_u64(reinterpret_cast<unsigned long long*>(m->time), c->n_sys, 0ull, st);
     launch_fill_u32(m->flags, 4, 0u, st);
     launch_fill_u32(m->sb.cell, n, 0u, st);
+    launch_fill_u32(m->sb.count, (size_t)m->sb.trash + 1, 0u, st);   // kept zero between sorts
     if (m->closure) {
         launch_fill_u32(m->cl.count, 4, 0u, st);
         launch_fill_u32(m->cl.fallback, n, 0u, st);

@@ -12,7 +12,7 @@
 namespace sphjet {
 
 constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
 // One full set of per-slot state arrays.
@@ -28,6 +28,7 @@ struct StateBuf {
 
 struct SortBufs {
     uint32_t trash;     // number of cells of all systems = key of inactive particles
+    uint32_t* count;    // trash + 1: particles per cell (key kernel); zero between sorts
     uint32_t* cstart;   // trash + 2: first slot of every cell (+ inactive start + end)
     uint32_t* key;      // n: key of each slot before the sort
     uint32_t* slot;     // n: position inside its cell (atomic order)
@@ -184,6 +185,7 @@ private:
 };
 
 void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+int64_t scan_tiles(int64_t m);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
 void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st);
 

@@ -47,49 +47,115 @@ __device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total) {
 }
 
 // ------------------------------------------------------------------ scan (u32)
-// Exclusive prefix sum of data[0..m) in place, total stored at data[m].
-// Tiles of SCAN_TILE elements: reduce, scan of tile sums, apply.
+// Exclusive prefix sum out[i] = sum of in[0..i), out[m] = the total. Large
+// arrays take three passes over tiles of SCAN_TILE elements (tile sums, one
+// workgroup scanning the tile sums, apply); small ones one workgroup. Every
+// thread owns SCAN_ITEMS consecutive elements, loaded and stored as uint4.
+// With clear_in the apply pass zeroes the input after reading it, so the cell
+// counts are ready for the next sort without a separate clear.
 
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* data, int64_t m, uint32_t* part) {
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    uint32_t s = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = base + (int64_t)k * SCAN_THREADS + threadIdx.x;
-        if (i < m) s += data[i];
+// The SCAN_ITEMS elements of this thread starting at i0 (zeros past m).
+__device__ __forceinline__ void scan_load(const uint32_t* in, int64_t i0, int64_t m, uint32_t* v) {
+    if (i0 + SCAN_ITEMS <= m) {
+#pragma unroll
+        for (int u = 0; u < SCAN_ITEMS / 4; ++u) {
+            const uint4 q = reinterpret_cast<const uint4*>(in + i0)[u];
+            v[4 * u] = q.x;
+            v[4 * u + 1] = q.y;
+            v[4 * u + 2] = q.z;
+            v[4 * u + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = i0 + k < m ? in[i0 + k] : 0u;
     }
+}
+
+// out[i0 + k] = run + v[0] + ... + v[k - 1] (elements below m); returns the
+// running sum past the last element.
+__device__ __forceinline__ uint32_t scan_store(uint32_t* out, int64_t i0, int64_t m, const uint32_t* v, uint32_t run) {
+    if (i0 + SCAN_ITEMS <= m) {
+#pragma unroll
+        for (int u = 0; u < SCAN_ITEMS / 4; ++u) {
+            uint4 o;
+            o.x = run;
+            run += v[4 * u];
+            o.y = run;
+            run += v[4 * u + 1];
+            o.z = run;
+            run += v[4 * u + 2];
+            o.w = run;
+            run += v[4 * u + 3];
+            reinterpret_cast<uint4*>(out + i0)[u] = o;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            if (i0 + k < m) out[i0 + k] = run;
+            run += v[k];
+        }
+    }
+    return run;
+}
+
+// Zero the elements of this thread that were non-zero.
+__device__ __forceinline__ void scan_clear(uint32_t* in, int64_t i0, int64_t m, const uint32_t* v) {
+    if (i0 + SCAN_ITEMS <= m) {
+#pragma unroll
+        for (int u = 0; u < SCAN_ITEMS / 4; ++u)
+            if (v[4 * u] | v[4 * u + 1] | v[4 * u + 2] | v[4 * u + 3])
+                reinterpret_cast<uint4*>(in + i0)[u] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k)
+            if (i0 + k < m && v[k]) in[i0 + k] = 0u;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* in, int64_t m, uint32_t* part) {
+    const int64_t i0 = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    scan_load(in, i0, m, v);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
     uint32_t tot;
     block_exclusive_scan(s, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_parts(uint32_t* part, int64_t nb) {
-    // one workgroup of 1024 threads, each owning a contiguous chunk
-    int64_t per = (nb + 1023) / 1024;
-    int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
-    uint32_t s = 0;
-    for (int64_t i = b0; i < b1; ++i) s += part[i];
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan(s, &tot);
-    for (int64_t i = b0; i < b1; ++i) { uint32_t t = part[i]; part[i] = run; run += t; }
+// One workgroup of SCAN_THREADS threads scans all of in[0..m) in chunks of
+// SCAN_TILE, carrying the running total from chunk to chunk.
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_single(uint32_t* in, uint32_t* out, int64_t m) {
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < m; base += SCAN_TILE) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+        uint32_t v[SCAN_ITEMS];
+        scan_load(in, i0, m, v);
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+        uint32_t tot;
+        const uint32_t excl = block_exclusive_scan(s, &tot);
+        scan_store(out, i0, m, v, carry + excl);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[m] = carry;
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(uint32_t* data, int64_t m, const uint32_t* part) {
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    // each thread owns SCAN_ITEMS consecutive elements
-    int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(uint32_t* in, uint32_t* out, int64_t m,
+                                                           const uint32_t* part, int clear_in) {
+    const int64_t i0 = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
+    scan_load(in, i0, m, v);
     uint32_t s = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = (i0 + k < m) ? data[i0 + k] : 0u;
-        s += v[k];
-    }
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+    if (clear_in && s) scan_clear(in, i0, m, v);
     uint32_t tot;
-    uint32_t run = block_exclusive_scan(s, &tot) + part[blockIdx.x];
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        if (i0 + k < m) data[i0 + k] = run;
-        run += v[k];
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) data[m] = run;
+    const uint32_t excl = block_exclusive_scan(s, &tot);
+    const uint32_t run = scan_store(out, i0, m, v, part[blockIdx.x] + excl);
+    if (i0 < m && i0 + SCAN_ITEMS >= m) out[m] = run;   // the thread holding element m - 1
 }
 
 // ------------------------------------------------------------------ sort
@@ -831,12 +897,21 @@ void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipS
     if (n) k_fill_u64<<<nblk((int64_t)n, 256), 256, 0, st>>>(p, n, v);
 }
 
-void launch_scan(uint32_t* data, int64_t m, uint32_t* part, hipStream_t st, KernelTimer* kt) {
-    unsigned nb = nblk(m, SCAN_TILE);
+int64_t scan_tiles(int64_t m) { return (m + SCAN_TILE - 1) / SCAN_TILE; }
+
+// in[0..m) -> out[0..m] (in == out allowed unless clear_in); part holds
+// scan_tiles(m) + 1 words. Up to 8 tiles go to the one-workgroup kernel.
+static void launch_scan(uint32_t* in, uint32_t* out, int64_t m, bool clear_in, uint32_t* part, hipStream_t st,
+                        KernelTimer* kt) {
+    const int64_t nt = scan_tiles(m);
     kt->begin("scan", st);
-    k_scan_reduce<<<nb, SCAN_THREADS, 0, st>>>(data, m, part);
-    k_scan_parts<<<1, 1024, 0, st>>>(part, nb);
-    k_scan_apply<<<nb, SCAN_THREADS, 0, st>>>(data, m, part);
+    if (nt <= 8 && !clear_in) {
+        k_scan_single<<<1, SCAN_THREADS, 0, st>>>(in, out, m);
+    } else {
+        k_scan_reduce<<<(unsigned)nt, SCAN_THREADS, 0, st>>>(in, m, part);
+        k_scan_single<<<1, SCAN_THREADS, 0, st>>>(part, part, nt);
+        k_scan_apply<<<(unsigned)nt, SCAN_THREADS, 0, st>>>(in, out, m, part, clear_in ? 1 : 0);
+    }
     kt->end(st);
 }
 
@@ -852,14 +927,13 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     const int bs = L.block_stream;
     const uint32_t trash = B.trash;
     const unsigned nb = nblk(n, bs);
-    kt->begin("sort_clear", st);
-    launch_fill_u32(B.cstart, (size_t)trash + 2, 0u, st);
-    kt->end(st);
+    // the per-cell counts are zero here: the cell scan of the previous sort
+    // cleared them (and the first sort finds them cleared at set-up)
     kt->begin("sort_key", st);
-    k_key<T><<<nb, bs, 0, st>>>(n, sys, X.pos, X.tag, B.key, B.slot, B.cstart, trash, B.blk);
+    k_key<T><<<nb, bs, 0, st>>>(n, sys, X.pos, X.tag, B.key, B.slot, B.count, trash, B.blk);
     kt->end(st);
-    launch_scan(B.cstart, (int64_t)trash + 1, B.part, st, kt);
-    launch_scan(B.blk, (int64_t)nb, B.part2, st, kt);
+    launch_scan(B.count, B.cstart, (int64_t)trash + 1, true, B.part, st, kt);
+    launch_scan(B.blk, B.blk, (int64_t)nb, false, B.part2, st, kt);
     kt->begin("sort_scatter", st);
     k_scatter<<<nb, bs, 0, st>>>(n, B.key, B.slot, X.id, B.cstart, trash, B.blk, B.tmp_src, B.tmp_id);
     kt->end(st);
