@@ -46,16 +46,15 @@ ALGO_BYTES = {
     "predict": 4 + 16 + 8 + 4 + 4 + 8 + 4 + 16 + 8 + 4 + 4,  # tag pos vel dens drho acc mass -> half state, vol
     "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,       # tag pos vel dens drho acc -> pos vel dens
     "sort_key": 16 + 4 + 4 + 4,                           # pos tag -> key slot
-    "sort_scatter": 4 + 4 + 4 + 4 + 4,                    # key slot id -> tmp_src tmp_id
-    "sort_cells": 16,                                     # tmp_src tmp_id read + write
-    "sort_permute": 4 + 4 + 4 + 36 + 40 + 4 + 4,          # tmp_src tmp_id key X -> Y cell vol
+    "sort_scatter": 4 + 4 + 4 + 4 + 4,                    # key slot id cstart -> cell_ids
+    "sort_permute": 4 + 4 + 4 + 40 + 40 + 4 + 4,          # key cstart cell_ids X -> Y cell vol
 }
 
 
 KERNEL_NAMES = {  # device function -> the name the library's profiler gives it
     "k_colour": "colour", "k_main": "main", "k_surface": "surface", "k_permute": "sort_permute",
     "k_predict": "predict", "k_correct": "correct", "k_key": "sort_key", "k_scatter": "sort_scatter",
-    "k_cellsort": "sort_cells", "k_stencil": "closure_stencil", "k_closure_net": "closure_net",
+    "k_stencil": "closure_stencil", "k_closure_net": "closure_net",
 }
 
 

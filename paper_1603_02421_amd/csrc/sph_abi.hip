@@ -299,8 +299,8 @@ struct Impl : sph_ctx_base {
         sb.blk = cv.take<uint32_t>(nb + 1);
         sb.part = cv.take<uint32_t>(scan_tiles((int64_t)trash + 1) + 1);
         sb.part2 = cv.take<uint32_t>(scan_tiles(nb) + 1);
-        sb.tmp_src = cv.take<uint32_t>(n_);
-        sb.tmp_id = cv.take<uint32_t>(n_);
+        sb.cell_ids = cv.take<uint32_t>(n_);
+        sb.scratch = cv.take<uint32_t>(n_);
         sb.cell = cv.take<uint32_t>(n_);
         sb.sys_cell_base = cv.take<uint32_t>(n_sys_ + 1);
         sb.sys_lo = cv.take<uint32_t>(n_sys_);
@@ -636,7 +636,7 @@ int nbr_impl(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* tot
     const int n = m->n;
     hipStream_t st = c->stream;
     EvalView<T> v = m->eval_view(false, false);
-    uint32_t* cnt = m->sb.tmp_src;  // free between steps
+    uint32_t* cnt = m->sb.scratch;
     launch_nbr_count<T>(m->L, v, cnt, st);
     std::vector<uint32_t> counts(n), ids(n);
     HIP_OK(hipMemcpyAsync(counts.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, st));

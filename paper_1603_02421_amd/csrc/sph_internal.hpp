@@ -35,8 +35,8 @@ struct SortBufs {
     uint32_t* blk;      // workgroups + 1: inactive counts, then their offsets
     uint32_t* part;     // tile sums of the cell scan
     uint32_t* part2;    // tile sums of the workgroup scan
-    uint32_t* tmp_src;  // n: source slot of each destination slot
-    uint32_t* tmp_id;   // n: particle id of each destination slot
+    uint32_t* cell_ids; // n: ids of every cell's particles in its slot range (unordered)
+    uint32_t* scratch;  // n: free between steps (neighbour counts of sph_neighbors)
     uint32_t* cell;     // n: cell key of each sorted slot
     uint32_t* sys_cell_base;  // n_sys + 1: first cell of every system (last = trash)
     uint32_t* sys_lo;         // n_sys: first sorted slot of every system

@@ -159,9 +159,10 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(uint32_t* in, uint3
 }
 
 // ------------------------------------------------------------------ sort
-// Cell key of every slot, slot within its cell (atomic counter: the order
-// inside a cell is fixed afterwards by k_cellsort), and per-workgroup counts
-// of inactive particles (their order comes from a stable compaction).
+// Cell key of every slot, slot within its cell (atomic counter: only a place
+// for the particle's id, the order inside a cell is fixed by k_permute), and
+// per-workgroup counts of inactive particles (their order comes from a stable
+// compaction).
 
 template <typename T>
 __global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uint32_t* tag,
@@ -209,57 +210,52 @@ __global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uin
     if (threadIdx.x == 0) blk_inactive[blockIdx.x] = (uint32_t)c;
 }
 
+// The ids of every cell's particles, in the cell's slot range (in the
+// arbitrary order of the key kernel's atomics).
 __global__ void k_scatter(int n, const uint32_t* key, const uint32_t* slot, const uint32_t* id,
-                          const uint32_t* cstart, uint32_t trash, const uint32_t* blk_off,
-                          uint32_t* tmp_src, uint32_t* tmp_id) {
+                          const uint32_t* cstart, uint32_t trash, uint32_t* cell_ids) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t k = i < n ? key[i] : 0u;
-    bool inactive = i < n && k == trash;
-    uint32_t tot;
-    uint32_t rank = block_exclusive_scan(inactive ? 1u : 0u, &tot);
     if (i >= n) return;
-    uint32_t dst = inactive ? cstart[trash] + blk_off[blockIdx.x] + rank : cstart[k] + slot[i];
-    tmp_src[dst] = (uint32_t)i;
-    tmp_id[dst] = id[i];
+    const uint32_t k = key[i];
+    if (k != trash) cell_ids[cstart[k] + slot[i]] = id[i];
 }
 
-// Order every cell's slots by particle id (cells hold ~8 particles).
-__global__ void k_cellsort(uint32_t ncells, const uint32_t* cstart, uint32_t* tmp_src, uint32_t* tmp_id) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
-    uint32_t s = cstart[c], e = cstart[c + 1];
-    if (e - s < 2) return;
-    for (uint32_t j = s + 1; j < e; ++j) {
-        uint32_t kid = tmp_id[j], ksrc = tmp_src[j];
-        uint32_t m = j;
-        while (m > s && tmp_id[m - 1] > kid) {
-            tmp_id[m] = tmp_id[m - 1];
-            tmp_src[m] = tmp_src[m - 1];
-            --m;
-        }
-        tmp_id[m] = kid;
-        tmp_src[m] = ksrc;
-    }
-}
-
-// Gather the state into cell order; also m / rho for the first evaluation of
-// the step.
+// Move every particle to its slot of the sorted order, which is (cell key,
+// particle id): the first slot of its cell plus the number of the cell's
+// particles with a smaller id (ids are unique). Inactive particles follow all
+// cells in their previous order (stable compaction per workgroup, the same
+// workgroups as the key kernel). Also m / rho for the first evaluation of the
+// step.
 template <typename T>
-__global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* tmp_src, const uint32_t* tmp_id,
-                          const uint32_t* key, StateBuf<T> X, StateBuf<T> Y, uint32_t* cell, T* vol) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    uint32_t s = tmp_src[j];
-    T dens = X.dens[s], mass = X.mass[s];
-    uint32_t t = X.tag[s];
-    Y.pos[j] = X.pos[s];
-    Y.vel[j] = X.vel[s];
-    Y.dens[j] = dens;
-    Y.mass[j] = mass;
-    Y.tag[j] = t;
-    Y.id[j] = tmp_id[j];
-    cell[j] = key[s];
-    if (tag_type(t) != T_INACTIVE) vol[j] = particle_vol(sys[tag_sys(t)], dens, mass);
+__global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* key, const uint32_t* cstart,
+                          const uint32_t* cell_ids, uint32_t trash, const uint32_t* blk_off, StateBuf<T> X,
+                          StateBuf<T> Y, uint32_t* cell, T* vol) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t k = i < n ? key[i] : 0u;
+    const bool inactive = i < n && k == trash;
+    uint32_t tot;
+    const uint32_t rank = block_exclusive_scan(inactive ? 1u : 0u, &tot);
+    if (i >= n) return;
+    const uint32_t pid = X.id[i];
+    uint32_t dst;
+    if (inactive) {
+        dst = cstart[trash] + blk_off[blockIdx.x] + rank;
+    } else {
+        const uint32_t lo = cstart[k], hi = cstart[k + 1];
+        uint32_t r = 0;
+        for (uint32_t j = lo; j < hi; ++j) r += cell_ids[j] < pid ? 1u : 0u;
+        dst = lo + r;
+    }
+    const T dens = X.dens[i], mass = X.mass[i];
+    const uint32_t t = X.tag[i];
+    Y.pos[dst] = X.pos[i];
+    Y.vel[dst] = X.vel[i];
+    Y.dens[dst] = dens;
+    Y.mass[dst] = mass;
+    Y.tag[dst] = t;
+    Y.id[dst] = pid;
+    cell[dst] = k;
+    if (!inactive) vol[dst] = particle_vol(sys[tag_sys(t)], dens, mass);
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -935,13 +931,10 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     launch_scan(B.count, B.cstart, (int64_t)trash + 1, true, B.part, st, kt);
     launch_scan(B.blk, B.blk, (int64_t)nb, false, B.part2, st, kt);
     kt->begin("sort_scatter", st);
-    k_scatter<<<nb, bs, 0, st>>>(n, B.key, B.slot, X.id, B.cstart, trash, B.blk, B.tmp_src, B.tmp_id);
-    kt->end(st);
-    kt->begin("sort_cells", st);
-    k_cellsort<<<nblk(trash, 256), 256, 0, st>>>(trash, B.cstart, B.tmp_src, B.tmp_id);
+    k_scatter<<<nb, bs, 0, st>>>(n, B.key, B.slot, X.id, B.cstart, trash, B.cell_ids);
     kt->end(st);
     kt->begin("sort_permute", st);
-    k_permute<T><<<nb, bs, 0, st>>>(n, sys, B.tmp_src, B.tmp_id, B.key, X, Y, B.cell, vol);
+    k_permute<T><<<nb, bs, 0, st>>>(n, sys, B.key, B.cstart, B.cell_ids, trash, B.blk, X, Y, B.cell, vol);
     kt->end(st);
     kt->begin("wave_table", st);
     k_wave_table<<<1, 1024, 0, st>>>(L.n_sys, B.sys_cell_base, B.cstart, B.sys_lo, B.sys_hi, B.chunk_base);
