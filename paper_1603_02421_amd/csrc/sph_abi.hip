@@ -269,14 +269,14 @@ struct Impl : sph_ctx_base {
         }
         sys = cv.take<SysDev<T>>(n_sys_);
         for (int k = 0; k < 2; ++k) {
-            buf[k].pos = cv.take<double2>(n_);
+            buf[k].pos = cv.take<double2>(n_ + POS_PAD);
             buf[k].vel = cv.take<V2<T>>(n_);
             buf[k].dens = cv.take<T>(n_);
             buf[k].mass = cv.take<T>(n_);
             buf[k].tag = cv.take<uint32_t>(n_);
             buf[k].id = cv.take<uint32_t>(n_);
         }
-        pos_h = cv.take<double2>(n_);
+        pos_h = cv.take<double2>(n_ + POS_PAD);
         vel_h = cv.take<V2<T>>(n_);
         dens_h = cv.take<T>(n_);
         colour = cv.take<T>(n_);
@@ -834,6 +834,9 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     launch_fill_u64(reinterpret_cast<unsigned long long*>(m->time), c->n_sys, 0ull, st);
     launch_fill_u32(m->flags, 4, 0u, st);
     launch_fill_u32(m->sb.cell, n, 0u, st);
+    // the padding past the last position is read (and ignored) by the candidate scan
+    for (double2* p : {m->buf[0].pos, m->buf[1].pos, m->pos_h})
+        launch_fill_u32(reinterpret_cast<uint32_t*>(p + n), (size_t)POS_PAD * 4, 0u, st);
     launch_fill_u32(m->sb.count, (size_t)m->sb.trash + 1, 0u, st);   // kept zero between sorts
     if (m->closure) {
         launch_fill_u32(m->cl.count, 4, 0u, st);

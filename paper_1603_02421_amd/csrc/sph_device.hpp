@@ -134,17 +134,18 @@ __device__ __forceinline__ void kernel_wf(const KernelConsts<T>& K, T r, T& W, T
     }
 }
 
+// W(r) / wnorm: the kernel's shape, for sums that apply the normalisation once.
 template <typename T>
-__device__ __forceinline__ T kernel_w(const KernelConsts<T>& K, T r) {
+__device__ __forceinline__ T kernel_shape(const KernelConsts<T>& K, T r) {
     T q = r * K.inv_h;
     if (K.kernel == 0) {
         T u = T(1) - T(0.5) * q;
         T u2 = u * u;
-        return K.wnorm * u2 * u2 * (T(1) + T(2) * q);
+        return u2 * u2 * (T(1) + T(2) * q);
     }
-    if (q <= T(1)) return K.wnorm * (T(1) + q * q * (T(-1.5) + T(0.75) * q));
+    if (q <= T(1)) return T(1) + q * q * (T(-1.5) + T(0.75) * q);
     T u = T(2) - q;
-    return K.wnorm * T(0.25) * u * u * u;
+    return T(0.25) * u * u * u;
 }
 
 template <typename T>

@@ -11,6 +11,10 @@
 
 namespace sphjet {
 
+// Position arrays hold this many slots past the last particle: the candidate
+// scan loads four positions from one address and may run over a row's end.
+constexpr int POS_PAD = 4;
+
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;

@@ -311,9 +311,11 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 // Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that
 // passes the exact predicate |r_ab|^2 < (2h)^2. Candidates are taken four at a
 // time: their positions are loaded together, then the per-neighbour payload of
-// the accepted ones (load(b)), then compute(b, dx, dy, payload) with
-// r_ab = r_a - r_b in the working precision. Slot ranges come straight from
-// the cell starts: with the y index fastest, each cell row is one range.
+// the accepted ones (load(b)), then compute(b, k, dx, dy, r2, payload) with k
+// the slot's place in its cell row, r_ab = r_a - r_b in the working precision
+// and r2 = |r_ab|^2 as the predicate formed it (FP64). Slot ranges come
+// straight from the cell starts: with the y index fastest, each cell row is
+// one range.
 template <typename T, int NB = 4, typename LoadFn, typename ComputeFn, typename RowEndFn>
 __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
                                                 uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
@@ -334,16 +336,21 @@ __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32
         const uint32_t row = S.cell_base + (uint32_t)X * ny;
         const uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
         for (uint32_t b = b0; b < b1; b += NB) {
+            // NB positions from one address: the position arrays hold
+            // POS_PAD slots past the last particle, so a batch may run over
+            // the end of the row (those candidates fail the b + k < b1 test)
+            const double2* pb = pos + b;
             double2 q[NB];
 #pragma unroll
-            for (int k = 0; k < NB; ++k) q[k] = pos[b + k < b1 ? b + k : b1 - 1];
+            for (int k = 0; k < NB; ++k) q[k] = pb[k];
             bool ok[NB];
             T dx[NB], dy[NB];
+            double r2[NB];
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 double ex, ey;
-                double r2 = pair_r2(pa, q[k], ex, ey);
-                ok[k] = (b + k < b1) && (b + k != a) && (r2 < R2);
+                r2[k] = pair_r2(pa, q[k], ex, ey);
+                ok[k] = (b + k < b1) && (b + k != a) && (r2[k] < R2);
                 dx[k] = (T)ex;
                 dy[k] = (T)ey;
             }
@@ -353,7 +360,7 @@ __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32
                 if (ok[k]) pl[k] = load(b + k);
 #pragma unroll
             for (int k = 0; k < NB; ++k)
-                if (ok[k]) compute(b + k, b + k - b0, dx[k], dy[k], pl[k]);
+                if (ok[k]) compute(b + k, b + k - b0, dx[k], dy[k], r2[k], pl[k]);
         }
         row_end(r);
     }
@@ -364,7 +371,8 @@ __device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* _
                                            uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
                                            ComputeFn&& compute) {
     scan_cells_rows<T, NB>(S, cstart, cell, a, pa, pos, load,
-                       [&](uint32_t b, uint32_t, T dx, T dy, const auto& p) { compute(b, dx, dy, p); }, [](int) {});
+                           [&](uint32_t b, uint32_t, T dx, T dy, double, const auto& p) { compute(b, dx, dy, p); },
+                           [](int) {});
 }
 
 // Reference-style visitor, one candidate at a time (debug neighbour lists).
@@ -516,7 +524,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const double2 pa = v.pos[a];
     const T vol_a = v.vol[a];
     const T dens_a = v.dens[a];   // for the record written at the end
-    T sum = vol_a * S.W0;
+    T wsum = 0;   // sum_b (m_b / rho_b) W_ab / wnorm
     // mask words: `cur` collects the row being scanned, row_end files it
     RowMask M = {{0u, 0u, 0u, 0u, 0u}};
     uint32_t cur = 0;
@@ -534,27 +542,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         cur = 0;
     };
     auto load = [&](uint32_t b) { return v.vol[b]; };
-    auto acc = [&](uint32_t, T dx, T dy, T vol_b) { sum += vol_b * kernel_w(K, sqrt_(dx * dx + dy * dy)); };
+    auto acc = [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); };
     if (S.reach == 1) {
         // 3 x 3 blocks (about 3.5 candidates per neighbour): first the pair
         // predicate alone, recorded as the mask, then the kernel sum over the
         // accepted neighbours only, so lanes do not pay for each other's
         // accepted candidates
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
-                           [&](uint32_t, uint32_t k, T, T, int) { mark(k); }, row_end);
+                           [&](uint32_t, uint32_t k, T, T, double, int) { mark(k); }, row_end);
         if (!overflow) mask_neighbours<T>(v, S, a, pa, M, load, acc);
         else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc);
     } else {
         // 5 x 5 blocks (about 2.2 candidates per neighbour): one pass
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
-                           [&](uint32_t b, uint32_t k, T dx, T dy, T vol_b) {
-                               acc(b, dx, dy, vol_b);
+                           [&](uint32_t, uint32_t k, T, T, double r2, T vol_b) {
+                               wsum += vol_b * kernel_shape(K, sqrt_((T)r2));
                                mark(k);
                            },
                            row_end);
     }
     // bit 31 of the last word is the overflow flag, so that row holds 31 bits
     if (M.w[4] & MASK_OVERFLOW) overflow = true;
+    const T sum = vol_a * S.W0 + K.wnorm * wsum;
     v.colour[a] = sum;
     // the record the later sweeps gather of every neighbour
     T rho_a, pr_a;
