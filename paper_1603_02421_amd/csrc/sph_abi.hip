@@ -217,6 +217,9 @@ struct Impl : sph_ctx_base {
     V4<T>* eos = nullptr;
     uint4* nmask = nullptr;
     uint32_t* nmask4 = nullptr;
+    uint32_t surf_region = 0;
+    uint32_t* surf_count = nullptr;
+    uint32_t* surf_list = nullptr;
     // learned closure (only when some system uses it)
     bool closure = false;
     ClosureView cl{};
@@ -225,6 +228,7 @@ struct Impl : sph_ctx_base {
     V2<T>* nrm = nullptr;
     SortBufs sb{};
     unsigned long long* dtmin = nullptr;
+    double* dt_wave = nullptr;
     double* dt = nullptr;
     double* time = nullptr;
     uint32_t* flags = nullptr;
@@ -290,6 +294,9 @@ struct Impl : sph_ctx_base {
         eos = cv.take<V4<T>>(n_);
         nmask = cv.take<uint4>(n_);
         nmask4 = cv.take<uint32_t>(n_);
+        surf_region = (uint32_t)surface_region(n_, n_sys_);
+        surf_count = cv.take<uint32_t>(SURF_REGIONS);
+        surf_list = cv.take<uint32_t>((size_t)SURF_REGIONS * surf_region);
         int64_t nb = (n_ + block_stream - 1) / block_stream;
         sb.trash = trash;
         sb.count = cv.take<uint32_t>((size_t)trash + 1);
@@ -307,6 +314,7 @@ struct Impl : sph_ctx_base {
         sb.sys_hi = cv.take<uint32_t>(n_sys_);
         sb.chunk_base = cv.take<uint32_t>(n_sys_ + 1);
         dtmin = cv.take<unsigned long long>(2 * n_sys_);
+        dt_wave = cv.take<double>(2 * surface_chunks(n_, n_sys_));
         dt = cv.take<double>(n_sys_);
         time = cv.take<double>(n_sys_);
         flags = cv.take<uint32_t>(4);
@@ -340,10 +348,14 @@ struct Impl : sph_ctx_base {
         v.kappa = kappa;
         v.kappa_plain = kappa_plain;
         v.dtmin = dtmin;
+        v.dt_wave = dt_wave;
         v.vol = vol;
         v.eos = eos;
         v.nmask = nmask;
         v.nmask4 = nmask4;
+        v.surf_region = surf_region;
+        v.surf_count = surf_count;
+        v.surf_list = surf_list;
         if (closure) {
             v.cl_count = cl.count;
             v.cl_list = cl.list;
@@ -392,7 +404,7 @@ struct Impl : sph_ctx_base {
     void step(hipStream_t st, KernelTimer* kt) {
         sort(st, kt);
         evaluate(false, true, st, kt);
-        launch_dt<T>(n_sys, sys, dtmin, dt, st, kt);
+        launch_dt<T>(n_sys, sys, sb.chunk_base, dt_wave, dtmin, dt, st, kt);
         launch_predict<T>(L, integ_view(), st, kt);
         evaluate(true, false, st, kt);
         launch_correct<T>(L, integ_view(), n_sys, dt, time, st, kt);
@@ -426,7 +438,7 @@ int evaluate_impl(sph_ctx* c) {
     Impl<T>* m = impl_of<T>(c);
     m->sort(c->stream, &c->timer);
     m->evaluate(false, true, c->stream, &c->timer);
-    launch_dt<T>(m->n_sys, m->sys, m->dtmin, m->dt, c->stream, &c->timer);
+    launch_dt<T>(m->n_sys, m->sys, m->sb.chunk_base, m->dt_wave, m->dtmin, m->dt, c->stream, &c->timer);
     HIP_OK(hipGetLastError());
     return SPH_OK;
 }
@@ -526,13 +538,21 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
             unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
             break;
         case SPH_F_CURV:
-            HIP_OK(fetch(m->kappa, n * sizeof(T), tmp));
-            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
+        case SPH_F_CURV_PLAIN: {
+            // the curvature arrays hold values for particles that pass the
+            // normal filter only; every other particle reads 0
+            int32_t* dev = reinterpret_cast<int32_t*>(m->aux);
+            k_nflag<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, m->sys, S.tag, m->nrm, dev);
+            std::vector<char> fl;
+            HIP_OK(fetch(dev, n * 4, fl));
+            HIP_OK(fetch(field == SPH_F_CURV ? m->kappa : m->kappa_plain, n * sizeof(T), tmp));
+            T* kv = reinterpret_cast<T*>(tmp.data());
+            const int32_t* f = reinterpret_cast<const int32_t*>(fl.data());
+            for (int64_t j = 0; j < n; ++j)
+                if (!f[j]) kv[j] = T(0);
+            unpermute(ids, kv, 1, out);
             break;
-        case SPH_F_CURV_PLAIN:
-            HIP_OK(fetch(m->kappa_plain, n * sizeof(T), tmp));
-            unpermute(ids, reinterpret_cast<const T*>(tmp.data()), 1, out);
-            break;
+        }
         case SPH_F_TYPE: {
             HIP_OK(fetch(S.tag, n * 4, tmp));
             const uint32_t* tg = reinterpret_cast<const uint32_t*>(tmp.data());

@@ -220,16 +220,20 @@ __device__ __forceinline__ void atomic_min_bits(unsigned long long* dst, double 
 
 // Minimum of non-negative values v into dst[sys] (stored as FP64 bits, whose
 // unsigned order equals the numeric order for non-negative numbers). Every lane
-// of the wave must call this; lanes with valid = false contribute nothing.
+// of the wave must call this (from uniform control flow); lanes with valid =
+// false contribute nothing. The wave is taken one system at a time: a wave
+// minimum and one atomic per distinct system among its lanes.
 __device__ __forceinline__ void atomic_min_per_system(unsigned long long* dst, int stride, int sys,
                                                       double v, bool valid) {
-    int s_first = __builtin_amdgcn_readfirstlane(valid ? sys : -1);
-    bool uniform = __all(!valid || sys == s_first);
-    if (uniform) {
-        double m = wave_min(valid ? v : __builtin_inf());
-        if (__lane_id() == 0 && s_first >= 0 && m < __builtin_inf()) atomic_min_bits(dst + (size_t)s_first * stride, m);
-    } else if (valid && v < __builtin_inf()) {
-        atomic_min_bits(dst + (size_t)sys * stride, v);
+    const bool live = valid && v < __builtin_inf();
+    unsigned long long todo = __ballot(live);
+    while (todo) {
+        const int l = __ffsll((long long)todo) - 1;
+        const int s0 = __builtin_amdgcn_readfirstlane(__shfl(sys, l, 64));
+        const bool mine = live && sys == s0;
+        const double m = wave_min(mine ? v : __builtin_inf());
+        if (__lane_id() == 0) atomic_min_bits(dst + (size_t)s0 * stride, m);
+        todo &= ~__ballot(mine);
     }
 }
 

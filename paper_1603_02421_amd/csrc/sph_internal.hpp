@@ -15,6 +15,10 @@ namespace sphjet {
 // scan loads four positions from one address and may run over a row's end.
 constexpr int POS_PAD = 4;
 
+// The surface list of an evaluation is split into this many regions, each
+// with its own counter, so its appends do not all contend for one address.
+constexpr int SURF_REGIONS = 64;
+
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
@@ -73,7 +77,8 @@ struct EvalView {
     V2<T>* nrm;
     T* kappa;
     T* kappa_plain;
-    unsigned long long* dtmin;  // 2 per system: [h/(c+sig) min, sqrt(h/|a|) min]
+    unsigned long long* dtmin;  // 2 per system: [h/(c+sig) min, sqrt(h/|a|) min] (atomic minima)
+    double* dt_wave;            // 2 per sweep chunk: the main sweep's wave minima of the same
     const T* vol;               // m / rho of every slot (this evaluation's state)
     V4<T>* eos;                 // (P / rho^2, colour, rho, m / rho), written by the colour sweep
     uint4* nmask;                // n: neighbour mask words of cell rows 0..3
@@ -81,7 +86,9 @@ struct EvalView {
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
     uint32_t* cl_list;
     uint32_t cl_capacity;
-    uint32_t pad2_;
+    uint32_t surf_region;        // capacity of one region of the surface list
+    uint32_t* surf_count;        // SURF_REGIONS counters (cleared by the colour sweep)
+    uint32_t* surf_list;         // SURF_REGIONS regions: slots that pass the normal filter
 };
 
 // Learned closure network: parameter count and offsets of the flat FP32
@@ -190,6 +197,8 @@ private:
 
 void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 int64_t scan_tiles(int64_t m);
+int64_t surface_region(int64_t n, int n_sys);   // slots of one surface-list region
+int64_t surface_chunks(int64_t n, int n_sys);   // bound on the sweeps' 64-slot chunks
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
 void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st);
 
@@ -199,7 +208,8 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
 template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt);
 template <typename T>
-void launch_dt(int n_sys, const SysDev<T>* sys, unsigned long long* dtmin, double* dt, hipStream_t st,
+void launch_dt(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base, const double* dt_wave,
+               unsigned long long* dtmin, double* dt, hipStream_t st,
                KernelTimer* kt);
 template <typename T>
 void launch_predict(const LaunchCfg& L, const IntegView<T>& v, hipStream_t st, KernelTimer* kt);

@@ -286,9 +286,10 @@ __global__ void __launch_bounds__(1024) k_wave_table(int n_sys, const uint32_t* 
 // The system and slot of this lane; false (for the whole wave) when the wave
 // has no chunk. Slots past the end of the system are not valid.
 template <typename T>
-__device__ __forceinline__ bool wave_assign(const EvalView<T>& v, int& sys, uint32_t& a) {
+__device__ __forceinline__ bool wave_assign(const EvalView<T>& v, int& sys, uint32_t& a, uint32_t* chunk = nullptr) {
     const int wpb = (int)(blockDim.x >> 6);
     const uint32_t wave = (uint32_t)(tile_index(v.xcd) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    if (chunk) *chunk = wave;
     const uint32_t total = v.chunk_base[v.n_sys];
     if (wave >= total) return false;
     int lo = 0, hi = v.n_sys - 1;
@@ -583,14 +584,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 // artificial-viscosity acceleration (eq. 9-10) and the interface normal
 // n_a = sum_b (m_b/rho_b)(C_b - C_a) grad_a W_ab (eq. 18); the signal term
 // max_b |h v_ab . r_ab| / r_ab^2 feeds the eq. 31 limit.
+// The normal filter N_a = [|n_a| > eps] (eq. 20-21) is applied here: a fluid
+// particle that fails it has no surface force (kappa = 0: the curvature arrays
+// hold values for filtered particles only), so its total acceleration (eq. 25,
+// gravity added) and eq. 30 term are final; one that passes is appended to the
+// surface list for k_surface. The list has SURF_REGIONS regions with a counter
+// each (a wave appends to region chunk % SURF_REGIONS), which spreads the
+// appends over that many addresses. The wave's minima of the two dt terms go
+// to its own slot of dt_wave (plain stores); k_dt_finalize reduces them.
+// FP32: six waves per SIMD (at most 80 VGPRs) fit without spilling.
 template <typename T>
-__global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) k_main(EvalView<T> v) {
     int sys;
-    uint32_t a;
-    if (!wave_assign(v, sys, a)) return;
+    uint32_t a, chunk;
+    if (!wave_assign(v, sys, a, &chunk)) return;
     const SysDev<T>& S = v.sys[sys];
     const bool valid = a < v.sys_hi[sys];
-    double dtcv = __builtin_inf();
+    double dtcv = __builtin_inf(), dtf = __builtin_inf();
+    bool surf = false;
     if (valid) {
         const bool fluid = tag_type(v.tag[a]) == T_FLUID;
         const double2 pa = v.pos[a];
@@ -642,44 +653,98 @@ __global__ void __launch_bounds__(256) k_main(EvalView<T> v) {
         const T vsig = h * sig_vr / sig_r2;
         v.drho[a] = drho;
         V2<T> acc, nrm;
-        acc.x = ax;
-        acc.y = ay;
         nrm.x = nx;
         nrm.y = ny;
-        v.acc[a] = acc;
         v.nrm[a] = nrm;
         dtcv = (double)(h / (c_a + vsig));
+        const T mag = sqrt_(nx * nx + ny * ny);
+        surf = fluid && mag > S.eps;
+        if (fluid && !surf) {
+            // no surface force: acceleration and curvature are final here
+            acc.x = ax + S.gx;
+            acc.y = ay + S.gy;
+            const T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
+            if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
+        } else {
+            // filtered particles: k_surface adds the surface force and gravity
+            acc.x = ax;
+            acc.y = ay;
+        }
+        v.acc[a] = acc;
     }
-    if (v.do_dt) wave_atomic_min(v.dtmin + 2 * sys, dtcv, valid);
+    if (v.do_dt) {
+        const double m_cv = wave_min(valid ? dtcv : __builtin_inf());
+        const double m_f = wave_min(valid && !surf ? dtf : __builtin_inf());
+        if (__lane_id() == 0) {
+            v.dt_wave[2 * (size_t)chunk] = m_cv;
+            v.dt_wave[2 * (size_t)chunk + 1] = m_f;
+        }
+    }
+    const unsigned long long bal = __ballot(surf);
+    if (bal) {
+        const uint32_t r = chunk % SURF_REGIONS;
+        const int first = __ffsll((long long)bal) - 1;
+        uint32_t base = 0;
+        if (__lane_id() == first) base = atomicAdd(v.surf_count + r, (uint32_t)__popcll(bal));
+        base = __shfl(base, first, 64);
+        if (surf) {
+            const uint32_t idx = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
+            if (idx < v.surf_region) v.surf_list[(size_t)r * v.surf_region + idx] = a;
+        }
+    }
 }
 
-// Sweep 3 (fluid only): normal filter N_a = [|n_a| > eps] (eq. 20-21),
-// curvature kappa_a = sum_b min(N_a,N_b)(m_b/rho_b)(nh_b - nh_a).grad_a W_ab /
+// Sweep 3, over the surface list (fluid particles with N_a = 1): curvature
+// kappa_a = sum_b min(N_a,N_b)(m_b/rho_b)(nh_b - nh_a).grad_a W_ab /
 // sum_b min(N_a,N_b)(m_b/rho_b) W_ab (eq. 23, self in the denominator),
 // surface-tension acceleration -(sigma/rho_a) kappa_a n_a (eq. 24) and the
 // total acceleration (eq. 25); |a| feeds the eq. 30 limit. Boundary particles
 // carry n = 0, so they fail the filter and drop out of both sums.
+// The list holds a few percent of the particles, from every system, so the
+// waves here are dense but not system-uniform: the system's constants are
+// per lane. A fixed grid strides over the regions, taken as one list.
 template <typename T>
 __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
-    int sys;
-    uint32_t a;
-    if (!wave_assign(v, sys, a)) return;
-    const SysDev<T>& S = v.sys[sys];
-    const bool valid = a < v.sys_hi[sys] && tag_type(v.tag[a]) == T_FLUID;
-    double dtf = __builtin_inf();
-    bool listed = false;
-    if (valid) {
-        const T eps = S.eps;
-        const KernelConsts<T> K = kconsts(S);
-        const V2<T> n_a = v.nrm[a];
-        const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
-        V2<T> acc = v.acc[a];
-        T kappa = 0;
-        const T rho_a = v.eos[a].z;
-        // with the learned closure the surface force of a filtered particle is
-        // added later, from the network's curvature or the plain fallback
-        listed = v.cl_count != nullptr && S.closure != 0 && mag > eps;
-        if (mag > eps) {
+    __shared__ uint32_t pre[4][SURF_REGIONS];
+    static_assert(SURF_REGIONS == 64, "one region per lane");
+    const int lane = __lane_id(), w = (int)(threadIdx.x >> 6);
+    // exclusive prefix of the region counts (one per lane), kept in LDS so the
+    // entries below can look it up from divergent code
+    const uint32_t cnt = v.surf_count[lane] < v.surf_region ? v.surf_count[lane] : v.surf_region;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    pre[w][lane] = incl - cnt;
+    const uint32_t total = __shfl(incl, 63, 64);
+    __syncthreads();
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t e = (blockIdx.x * (blockDim.x >> 6) + (uint32_t)w) * 64u; e < total; e += nwaves * 64u) {
+        const uint32_t idx = e + (uint32_t)lane;
+        // region holding entry idx: the last r with pre[r] <= idx
+        int r = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (pre[w][r + step] <= idx) r += step;
+        const uint32_t off = idx - pre[w][r];
+        const bool in = idx < total && off < v.surf_region;
+        const uint32_t a = in ? v.surf_list[(size_t)r * v.surf_region + off] : 0u;
+        const uint32_t sys = in ? tag_sys(v.tag[a]) : 0u;
+        const SysDev<T>& S = v.sys[sys];
+        double dtf = __builtin_inf();
+        bool listed = false;
+        if (in) {
+            const T eps = S.eps;
+            const KernelConsts<T> K = kconsts(S);
+            const V2<T> n_a = v.nrm[a];
+            const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
+            V2<T> acc = v.acc[a];
+            const T rho_a = v.eos[a].z;
+            // with the learned closure the surface force of a filtered particle is
+            // added later, from the network's curvature or the plain fallback
+            listed = v.cl_count != nullptr && S.closure != 0;
             const T im = rcp(mag);
             const T hx = n_a.x * im, hy = n_a.y * im;
             T num = 0;
@@ -691,36 +756,36 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
                     T mb = sqrt_(p.nrm.x * p.nrm.x + p.nrm.y * p.nrm.y);
                     if (mb > eps) {
                         T ib = rcp(mb);
-                        T r = sqrt_(dx * dx + dy * dy);
+                        T rr = sqrt_(dx * dx + dy * dy);
                         T W, F;
-                        kernel_wf(K, r, W, F);
+                        kernel_wf(K, rr, W, F);
                         num += p.vol * F * ((p.nrm.x * ib - hx) * dx + (p.nrm.y * ib - hy) * dy);
                         den += p.vol * W;
                     }
                 });
-            kappa = num / den;
+            const T kappa = num / den;
+            v.kappa_plain[a] = kappa;
+            T f = listed ? T(0) : -S.sigma * rcp(rho_a) * kappa;
+            acc.x += f * n_a.x + S.gx;
+            acc.y += f * n_a.y + S.gy;
+            v.acc[a] = acc;
+            v.kappa[a] = kappa;
+            T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
+            if (am > T(0) && !listed) dtf = sqrt((double)S.h / (double)am);
         }
-        v.kappa_plain[a] = kappa;
-        T f = listed ? T(0) : -S.sigma * rcp(rho_a) * kappa;
-        acc.x += f * n_a.x + S.gx;
-        acc.y += f * n_a.y + S.gy;
-        v.acc[a] = acc;
-        v.kappa[a] = kappa;
-        T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
-        if (am > T(0) && !listed) dtf = sqrt((double)S.h / (double)am);
-    }
-    if (v.do_dt) wave_atomic_min(v.dtmin + 2 * sys + 1, dtf, valid);
-    if (v.cl_count) {
-        // append the listed slots, one atomic per wave
-        const unsigned long long bal = __ballot(listed);
-        if (bal) {
-            const int first = __ffsll((long long)bal) - 1;
-            uint32_t base = 0;
-            if (__lane_id() == first) base = atomicAdd(v.cl_count, (uint32_t)__popcll(bal));
-            base = __shfl(base, first, 64);
-            if (listed) {
-                const uint32_t idx = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
-                if (idx < v.cl_capacity) v.cl_list[idx] = a;
+        if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, (int)sys, dtf, in);
+        if (v.cl_count) {
+            // append the listed slots, one atomic per wave
+            const unsigned long long bal = __ballot(listed);
+            if (bal) {
+                const int first = __ffsll((long long)bal) - 1;
+                uint32_t base = 0;
+                if (lane == first) base = atomicAdd(v.cl_count, (uint32_t)__popcll(bal));
+                base = __shfl(base, first, 64);
+                if (listed) {
+                    const uint32_t ci = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                    if (ci < v.cl_capacity) v.cl_list[ci] = a;
+                }
             }
         }
     }
@@ -728,19 +793,45 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
 
 // ------------------------------------------------------------------ time step
 
+// dt of every system (eq. 32): the minima of h/(c + sig) (eq. 31) and
+// sqrt(h/|a|) (eq. 30) over the per-wave minima of the main sweep (dt_wave,
+// one pair per chunk of the system) and what the surface and closure kernels
+// folded into dtmin; dtmin is reset for the next step. One workgroup per system.
 template <typename T>
-__global__ void k_dt_finalize(int n_sys, const SysDev<T>* sys, unsigned long long* dtmin, double* dt) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_dt_finalize(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base,
+                                                    const double* dt_wave, unsigned long long* dtmin, double* dt) {
+    __shared__ double red[2][4];
+    const int s = blockIdx.x;
     if (s >= n_sys) return;
-    const SysDev<T>& S = sys[s];
-    double f = __longlong_as_double((long long)dtmin[2 * s + 1]);   // sqrt(h/|a|)
-    double cv = __longlong_as_double((long long)dtmin[2 * s + 0]);  // h/(c + sig)
-    double d = S.dt_fixed > 0.0 ? S.dt_fixed : S.courant * fmin(f, cv);
-    if (!(d < __builtin_inf())) d = 0.0;
-    dt[s] = d;
-    unsigned long long inf_bits = (unsigned long long)__double_as_longlong(__builtin_inf());
-    dtmin[2 * s] = inf_bits;
-    dtmin[2 * s + 1] = inf_bits;
+    const uint32_t c0 = chunk_base[s], c1 = chunk_base[s + 1];
+    double cv = __builtin_inf(), f = __builtin_inf();
+    for (uint32_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        cv = fmin(cv, dt_wave[2 * (size_t)c]);
+        f = fmin(f, dt_wave[2 * (size_t)c + 1]);
+    }
+    cv = wave_min(cv);
+    f = wave_min(f);
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+        red[0][w] = cv;
+        red[1][w] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            cv = fmin(cv, red[0][k]);
+            f = fmin(f, red[1][k]);
+        }
+        const SysDev<T>& S = sys[s];
+        f = fmin(f, __longlong_as_double((long long)dtmin[2 * s + 1]));   // sqrt(h/|a|)
+        cv = fmin(cv, __longlong_as_double((long long)dtmin[2 * s + 0]));  // h/(c + sig)
+        double d = S.dt_fixed > 0.0 ? S.dt_fixed : S.courant * fmin(f, cv);
+        if (!(d < __builtin_inf())) d = 0.0;
+        dt[s] = d;
+        const unsigned long long inf_bits = (unsigned long long)__double_as_longlong(__builtin_inf());
+        dtmin[2 * s] = inf_bits;
+        dtmin[2 * s + 1] = inf_bits;
+    }
 }
 
 __device__ __forceinline__ double piston_travel(double U, double A, double w, double t) {
@@ -950,6 +1041,19 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     kt->end(st);
 }
 
+int64_t surface_chunks(int64_t n, int n_sys) { return (n + 63) / 64 + n_sys; }
+
+int64_t surface_region(int64_t n, int n_sys) {
+    return (surface_chunks(n, n_sys) + SURF_REGIONS - 1) / SURF_REGIONS * 64;
+}
+
+// The surface kernel's grid: enough waves for a list of 1/16 of the
+// particles in one pass, at least 256 workgroups.
+static unsigned surface_blocks(int64_t n) {
+    const int64_t want = (n / 16 + 255) / 256;
+    return (unsigned)(want < 256 ? 256 : (want > 4096 ? 4096 : want));
+}
+
 template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt) {
     const int bs = L.block_sweep;
@@ -958,19 +1062,20 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     kt->begin("colour", st);
     k_colour<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
+    launch_fill_u32(v.surf_count, SURF_REGIONS, 0u, st);   // the surface list starts empty
     kt->begin("main", st);
     k_main<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
     kt->begin("surface", st);
-    k_surface<T><<<nb, bs, 0, st>>>(v);
+    k_surface<T><<<surface_blocks(L.n), 256, 0, st>>>(v);
     kt->end(st);
 }
 
 template <typename T>
-void launch_dt(int n_sys, const SysDev<T>* sys, unsigned long long* dtmin, double* dt, hipStream_t st,
-               KernelTimer* kt) {
+void launch_dt(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base, const double* dt_wave,
+               unsigned long long* dtmin, double* dt, hipStream_t st, KernelTimer* kt) {
     kt->begin("dt", st);
-    k_dt_finalize<T><<<nblk(n_sys, 64), 64, 0, st>>>(n_sys, sys, dtmin, dt);
+    k_dt_finalize<T><<<(unsigned)n_sys, 256, 0, st>>>(n_sys, sys, chunk_base, dt_wave, dtmin, dt);
     kt->end(st);
 }
 
@@ -1012,7 +1117,8 @@ void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* 
     template void launch_sort<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,        \
                                  StateBuf<T>, T*, hipStream_t, KernelTimer*);                              \
     template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t, KernelTimer*);         \
-    template void launch_dt<T>(int, const SysDev<T>*, unsigned long long*, double*, hipStream_t,           \
+    template void launch_dt<T>(int, const SysDev<T>*, const uint32_t*, const double*, unsigned long long*, \
+                               double*, hipStream_t,                                                       \
                                KernelTimer*);                                                              \
     template void launch_predict<T>(const LaunchCfg&, const IntegView<T>&, hipStream_t, KernelTimer*);     \
     template void launch_correct<T>(const LaunchCfg&, const IntegView<T>&, int, const double*, double*,    \
