@@ -296,6 +296,7 @@ struct Impl : sph_ctx_base {
         nmask4 = cv.take<uint32_t>(n_);
         surf_region = (uint32_t)surface_region(n_, n_sys_);
         surf_count = cv.take<uint32_t>(SURF_REGIONS);
+        sb.surf_count = surf_count;
         surf_list = cv.take<uint32_t>((size_t)SURF_REGIONS * surf_region);
         int64_t nb = (n_ + block_stream - 1) / block_stream;
         sb.trash = trash;
@@ -391,6 +392,7 @@ struct Impl : sph_ctx_base {
         v.flags = flags;
         v.mass = S.mass;
         v.vol = vol;
+        v.surf_count = surf_count;
         return v;
     }
 

@@ -18,6 +18,7 @@ constexpr int POS_PAD = 4;
 // The surface list of an evaluation is split into this many regions, each
 // with its own counter, so its appends do not all contend for one address.
 constexpr int SURF_REGIONS = 64;
+constexpr int SURF_BLOCK = 32;   // consecutive sweep chunks that share a region
 
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
@@ -50,6 +51,7 @@ struct SortBufs {
     uint32_t* sys_lo;         // n_sys: first sorted slot of every system
     uint32_t* sys_hi;         // n_sys: one past its last active slot
     uint32_t* chunk_base;     // n_sys + 1: first 64-slot wave chunk of every system
+    uint32_t* surf_count;     // SURF_REGIONS surface-list counters (cleared with the wave table)
 };
 
 // What the three sweeps read and write.
@@ -87,7 +89,7 @@ struct EvalView {
     uint32_t* cl_list;
     uint32_t cl_capacity;
     uint32_t surf_region;        // capacity of one region of the surface list
-    uint32_t* surf_count;        // SURF_REGIONS counters (cleared by the colour sweep)
+    uint32_t* surf_count;        // SURF_REGIONS counters (cleared by the wave table and the predictor)
     uint32_t* surf_list;         // SURF_REGIONS regions: slots that pass the normal filter
 };
 
@@ -162,6 +164,7 @@ struct IntegView {
     const double* time;
     uint32_t* flags;
     T* vol;                // m / rho of the half-step state
+    uint32_t* surf_count;  // surface-list counters, cleared for the half-step evaluation
 };
 
 struct LaunchCfg {

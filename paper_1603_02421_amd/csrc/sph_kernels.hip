@@ -124,11 +124,12 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* in
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// One workgroup of SCAN_THREADS threads scans all of in[0..m) in chunks of
-// SCAN_TILE, carrying the running total from chunk to chunk.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_single(uint32_t* in, uint32_t* out, int64_t m) {
+// One workgroup (up to 1024 threads) scans all of in[0..m) in chunks of
+// blockDim.x * SCAN_ITEMS, carrying the running total from chunk to chunk.
+__global__ void __launch_bounds__(1024) k_scan_single(uint32_t* in, uint32_t* out, int64_t m) {
+    const int64_t tile = (int64_t)blockDim.x * SCAN_ITEMS;
     uint32_t carry = 0;
-    for (int64_t base = 0; base < m; base += SCAN_TILE) {
+    for (int64_t base = 0; base < m; base += tile) {
         const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
         uint32_t v[SCAN_ITEMS];
         scan_load(in, i0, m, v);
@@ -264,7 +265,9 @@ __global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* key, cons
 // constants are wave-uniform and live in scalar registers.
 
 __global__ void __launch_bounds__(1024) k_wave_table(int n_sys, const uint32_t* cell_base, const uint32_t* cstart,
-                                                    uint32_t* sys_lo, uint32_t* sys_hi, uint32_t* chunk_base) {
+                                                    uint32_t* sys_lo, uint32_t* sys_hi, uint32_t* chunk_base,
+                                                    uint32_t* surf_count) {
+    if (threadIdx.x < SURF_REGIONS) surf_count[threadIdx.x] = 0u;   // the first evaluation's surface list
     int per = (n_sys + 1023) / 1024;
     int s0 = (int)threadIdx.x * per, s1 = s0 + per < n_sys ? s0 + per : n_sys;
     uint32_t sum = 0;
@@ -589,8 +592,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 // hold values for filtered particles only), so its total acceleration (eq. 25,
 // gravity added) and eq. 30 term are final; one that passes is appended to the
 // surface list for k_surface. The list has SURF_REGIONS regions with a counter
-// each (a wave appends to region chunk % SURF_REGIONS), which spreads the
-// appends over that many addresses. The wave's minima of the two dt terms go
+// each: a wave appends to region (chunk / SURF_BLOCK) % SURF_REGIONS, so the
+// waves running at one time spread their appends over the counters while a
+// region collects neighbouring chunks (its neighbours share cache lines). The wave's minima of the two dt terms go
 // to its own slot of dt_wave (plain stores); k_dt_finalize reduces them.
 // FP32: six waves per SIMD (at most 80 VGPRs) fit without spilling.
 template <typename T>
@@ -682,7 +686,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     }
     const unsigned long long bal = __ballot(surf);
     if (bal) {
-        const uint32_t r = chunk % SURF_REGIONS;
+        const uint32_t r = (chunk / SURF_BLOCK) % SURF_REGIONS;
         const int first = __ffsll((long long)bal) - 1;
         uint32_t base = 0;
         if (__lane_id() == first) base = atomicAdd(v.surf_count + r, (uint32_t)__popcll(bal));
@@ -798,9 +802,9 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
 // one pair per chunk of the system) and what the surface and closure kernels
 // folded into dtmin; dtmin is reset for the next step. One workgroup per system.
 template <typename T>
-__global__ void __launch_bounds__(256) k_dt_finalize(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base,
-                                                    const double* dt_wave, unsigned long long* dtmin, double* dt) {
-    __shared__ double red[2][4];
+__global__ void __launch_bounds__(1024) k_dt_finalize(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base,
+                                                     const double* dt_wave, unsigned long long* dtmin, double* dt) {
+    __shared__ double red[2][16];
     const int s = blockIdx.x;
     if (s >= n_sys) return;
     const uint32_t c0 = chunk_base[s], c1 = chunk_base[s + 1];
@@ -846,6 +850,7 @@ __device__ __forceinline__ double piston_speed(double U, double A, double w, dou
 template <typename T>
 __global__ void k_predict(IntegView<T> v) {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < SURF_REGIONS) v.surf_count[threadIdx.x] = 0u;   // the half step's list
     if (a >= v.n) return;
     uint32_t t = v.tag[a];
     uint32_t ty = tag_type(t);
@@ -996,16 +1001,16 @@ void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipS
 int64_t scan_tiles(int64_t m) { return (m + SCAN_TILE - 1) / SCAN_TILE; }
 
 // in[0..m) -> out[0..m] (in == out allowed unless clear_in); part holds
-// scan_tiles(m) + 1 words. Up to 8 tiles go to the one-workgroup kernel.
+// scan_tiles(m) + 1 words. Up to 32 tiles go to the one-workgroup kernel.
 static void launch_scan(uint32_t* in, uint32_t* out, int64_t m, bool clear_in, uint32_t* part, hipStream_t st,
                         KernelTimer* kt) {
     const int64_t nt = scan_tiles(m);
     kt->begin("scan", st);
-    if (nt <= 8 && !clear_in) {
-        k_scan_single<<<1, SCAN_THREADS, 0, st>>>(in, out, m);
+    if (nt <= 32 && !clear_in) {
+        k_scan_single<<<1, 1024, 0, st>>>(in, out, m);
     } else {
         k_scan_reduce<<<(unsigned)nt, SCAN_THREADS, 0, st>>>(in, m, part);
-        k_scan_single<<<1, SCAN_THREADS, 0, st>>>(part, part, nt);
+        k_scan_single<<<1, 1024, 0, st>>>(part, part, nt);
         k_scan_apply<<<(unsigned)nt, SCAN_THREADS, 0, st>>>(in, out, m, part, clear_in ? 1 : 0);
     }
     kt->end(st);
@@ -1037,14 +1042,16 @@ void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, St
     k_permute<T><<<nb, bs, 0, st>>>(n, sys, B.key, B.cstart, B.cell_ids, trash, B.blk, X, Y, B.cell, vol);
     kt->end(st);
     kt->begin("wave_table", st);
-    k_wave_table<<<1, 1024, 0, st>>>(L.n_sys, B.sys_cell_base, B.cstart, B.sys_lo, B.sys_hi, B.chunk_base);
+    k_wave_table<<<1, 1024, 0, st>>>(L.n_sys, B.sys_cell_base, B.cstart, B.sys_lo, B.sys_hi, B.chunk_base,
+                                     B.surf_count);
     kt->end(st);
 }
 
 int64_t surface_chunks(int64_t n, int n_sys) { return (n + 63) / 64 + n_sys; }
 
 int64_t surface_region(int64_t n, int n_sys) {
-    return (surface_chunks(n, n_sys) + SURF_REGIONS - 1) / SURF_REGIONS * 64;
+    const int64_t blocks = (surface_chunks(n, n_sys) + SURF_BLOCK - 1) / SURF_BLOCK;
+    return (blocks + SURF_REGIONS - 1) / SURF_REGIONS * SURF_BLOCK * 64;
 }
 
 // The surface kernel's grid: enough waves for a list of 1/16 of the
@@ -1062,7 +1069,6 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     kt->begin("colour", st);
     k_colour<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
-    launch_fill_u32(v.surf_count, SURF_REGIONS, 0u, st);   // the surface list starts empty
     kt->begin("main", st);
     k_main<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
@@ -1075,7 +1081,7 @@ template <typename T>
 void launch_dt(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base, const double* dt_wave,
                unsigned long long* dtmin, double* dt, hipStream_t st, KernelTimer* kt) {
     kt->begin("dt", st);
-    k_dt_finalize<T><<<(unsigned)n_sys, 256, 0, st>>>(n_sys, sys, chunk_base, dt_wave, dtmin, dt);
+    k_dt_finalize<T><<<(unsigned)n_sys, 1024, 0, st>>>(n_sys, sys, chunk_base, dt_wave, dtmin, dt);
     kt->end(st);
 }
 
