@@ -69,9 +69,15 @@ def _cases():
     clump = wl.scenarios._assemble(clump.params, [(clump.pos, (0.0, 0.0), 1.0, wl.FLUID),
                                                   (extra, (0.0, 0.0), 1.0, wl.FLUID)])
     clump.vel = rng.normal(0, 0.05, size=clump.vel.shape)
+    # both kernels and a disc in one batch: the surface sweep's waves take
+    # particles of several systems and kernel types, the dt minima stay per system
+    mixed = wl.Batch([wl.jet(n_target=6_000, nD=10, Re=500, We=20, seed=3, free_length=6.0, prefill=3.0),
+                      wl.jet(n_target=6_000, nD=10, Re=300, We=10, seed=4, kernel=wl.CUBIC, free_length=6.0,
+                             prefill=3.0),
+                      wl.circle(9.0, dx=1.0, jitter=0.03, seed=6, layout="rings")])
     return dict(small_jet=small_jet, cubic_jet=cubic_jet, cloud=cloud, reach2=reach2, disc=disc,
                 batch=batch, empty_mid=empty_mid, walls_only=walls_only, overlap=overlap,
-                jet_reach2=jet_reach2, clump=clump)
+                jet_reach2=jet_reach2, clump=clump, mixed=mixed)
 
 
 CASES = _cases()
@@ -108,7 +114,7 @@ def test_neighbour_lists_bit_exact(gpu, orc, name):
 
 
 @pytest.mark.parametrize("name", ["small_jet", "cubic_jet", "cloud", "reach2", "disc", "batch", "overlap",
-                                  "empty_mid", "walls_only", "jet_reach2", "clump"])
+                                  "empty_mid", "walls_only", "jet_reach2", "clump", "mixed"])
 def test_single_evaluation_fp32(gpu, orc, name):
     obj = _rounded(CASES[name], 32)
     say(f"[eval fp32] case={name} n={obj.n}")
@@ -121,6 +127,33 @@ def test_single_evaluation_fp32(gpu, orc, name):
     say("  ", rep)
     ok = np.isfinite(o["dt"]) & (o["dt"] > 0)
     assert np.allclose(g["dt"][ok], o["dt"][ok], rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("name", ["mixed", "disc", "small_jet"])
+def test_curvature_read_back(gpu, orc, name):
+    """The plain curvature (eq. 23) as read back: exactly 0 where the normal
+    filter fails (eq. 20-21), and on interface particles (|n| h >= 0.05, away
+    from the filter threshold) within 5e-4 of the largest |kappa| of the oracle:
+    the FP32 normals carry errors up to 1e-5 of their absolute-sum scale, which
+    the unit normals of eq. 23 can magnify tenfold where |n| is small against
+    that scale, and eq. 23 differences them."""
+    obj = _rounded(CASES[name], 32)
+    with _sim(gpu, obj) as sim:
+        g = gpu_eval(sim)
+    o = orc.evaluate(obj)
+    start, nbr = orc.neighbors(obj)
+    eps = _eps_per_particle(obj)
+    from parity_util import near_threshold_mask
+    keep = ~near_threshold_mask(o, eps, start, nbr)
+    assert np.all(g["kappa"][g["nflag"] == 0] == 0.0)
+    h = np.concatenate([np.full(int(b - a), p["h"]) for p, a, b in
+                        zip(_plist(obj), _offsets(obj)[:-1], _offsets(obj)[1:])])
+    iface = keep & (o["nflag"] == 1) & (np.linalg.norm(o["nrm"], axis=1) * h >= 0.05)
+    assert iface.sum() > 20
+    kmax = np.abs(o["kappa"][iface]).max()
+    err = np.abs(g["kappa"][iface] - o["kappa"][iface]).max()
+    say(f"[curv] case={name} {int(iface.sum())} interface particles, max |dk| / max |k| = {err / kmax:.2e}")
+    assert err <= 5e-4 * kmax
 
 
 @pytest.mark.parametrize("kernel", [wl.WENDLAND, wl.CUBIC])
