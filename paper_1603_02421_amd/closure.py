@@ -320,7 +320,11 @@ def fine_jet_snapshots(nD_coarse: int, Re: float, We: float, seed: int, steps: S
 def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int):
     """Poisson-disk subsample of a fine snapshot at the coarse spacing (number
     density 1/dx^2) with reference labels; returns a closure System whose
-    meta holds (nhat_ref, kappa_ref, has_ref)."""
+    meta holds (nhat_ref, kappa_ref, has_ref).
+
+    The meta also holds kappa_halves (n x 2) and has_halves: the same label
+    computed from each half of a seeded random split of the fine interface
+    particles. Their spread measures the label's own noise (split-half)."""
     import workloads as wl
     from scipy.spatial import cKDTree
     dxc = 1.0 / nD_coarse
@@ -338,6 +342,9 @@ def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int):
     nref = np.zeros((len(pc), 2))
     kref = np.zeros(len(pc))
     has = np.zeros(len(pc), dtype=bool)
+    half = np.random.default_rng(seed + 7).integers(0, 2, size=len(sp))
+    khalf = np.zeros((len(pc), 2))
+    has_half = np.zeros(len(pc), dtype=bool)
     for i, lst in enumerate(nbrs):
         if len(lst) < 3:
             continue
@@ -349,19 +356,27 @@ def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int):
         nref[i] = v / np.linalg.norm(v)
         kref[i] = (w * sk[idx]).sum() / w.sum()
         has[i] = True
+        hs = half[idx]
+        wa, wb = w[hs == 0], w[hs == 1]
+        if (hs == 0).sum() >= 2 and (hs == 1).sum() >= 2 and wa.sum() > 0 and wb.sum() > 0:
+            khalf[i, 0] = (wa * sk[idx][hs == 0]).sum() / wa.sum()
+            khalf[i, 1] = (wb * sk[idx][hs == 1]).sum() / wb.sum()
+            has_half[i] = True
     p = wl.scenarios.jet_params(nD_coarse, Re, We)
     p.update(closure=1, box_lo=tuple(pc.min(0) - 4 * dxc), box_hi=tuple(pc.max(0) + 4 * dxc))
     n = len(pc)
     return wl.System(p, pc.copy(), np.zeros((n, 2)), np.ones(n), np.full(n, dxc * dxc), np.zeros(n, np.int32),
-                     name="jet_coarse", meta=dict(nhat_ref=nref, kappa_ref=kref, has_ref=has, nD=nD_coarse))
+                     name="jet_coarse", meta=dict(nhat_ref=nref, kappa_ref=kref, has_ref=has, nD=nD_coarse,
+                                                  kappa_halves=khalf, has_halves=has_half))
 
 
-def harvest_coarse(systems, device="cuda:0", chunk_particles: int = 2_000_000, params=None):
+def harvest_coarse(systems, device="cuda:0", chunk_particles: int = 2_000_000, params=None, halves=False):
     """(stencils, targets, plain kappa h, closure kappa h, fallback flags) of
     the listed particles of coarse jet sets that carry a reference label; with
-    `params` the closure runs in the same evaluation (else its kappa is 0)."""
+    `params` the closure runs in the same evaluation (else its kappa is 0).
+    With `halves` also the split-half labels (kappa h, n x 2) and their mask."""
     from .sim import Simulation
-    X, T, P, K, F = [], [], [], [], []
+    X, T, P, K, F, H, HM = [], [], [], [], [], [], []
     for grp in _chunks(systems, chunk_particles):
         with Simulation(grp, dtype_bits=32, device=device) as sim:
             if params is not None:
@@ -381,7 +396,12 @@ def harvest_coarse(systems, device="cuda:0", chunk_particles: int = 2_000_000, p
             P.append(kplain[sl][m] * h)
             K.append(kfin[sl][m] * h)
             F.append(fb[sl][m])
+            if halves:
+                H.append(s.meta["kappa_halves"][m] * h)
+                HM.append(s.meta["has_halves"][m])
     cat = np.concatenate
+    if halves:
+        return cat(X), cat(T), cat(P), cat(K), cat(F), cat(H), cat(HM)
     return cat(X), cat(T), cat(P), cat(K), cat(F)
 
 

@@ -170,12 +170,20 @@ def main(argv=None):
 
 def held_out_jets(cl, w, spec, snaps, n, free_length):
     hj = jet_sets(spec, snaps, n, free_length)
-    X2, T2, P2, K2, F2 = cl.harvest_coarse(hj, params=w)
+    X2, T2, P2, K2, F2, H2, HM2 = cl.harvest_coarse(hj, params=w, halves=True)
     Y2 = cl.predict(w, X2)
     nh = Y2[:, :2] / np.linalg.norm(Y2[:, :2], axis=1, keepdims=True)
     ang = np.degrees(np.arccos(np.clip(np.einsum("ij,ij->i", nh, T2[:, :2]), -1, 1)))
     r = errors(T2[:, 2], P2, Y2[:, 2], K2)
     r.update(fallback_fraction=float(F2.mean()), normal_angle_deg_median=float(np.median(ang)))
+    # the reference's own noise, split-half: each label recomputed from either
+    # half of the fine interface particles; with independent halves the full
+    # label's noise is half their difference, a floor for any predictor's error
+    if HM2.any():
+        ref = T2[HM2, 2]
+        d = H2[HM2, 0] - H2[HM2, 1]
+        r.update(n_split=int(HM2.sum()), reference_noise_floor=float(0.5 * np.linalg.norm(d) / np.linalg.norm(ref)),
+                 mlp_on_split=cl.rel_l2(Y2[HM2, 2], ref), plain_on_split=cl.rel_l2(P2[HM2], ref))
     return r
 
 

@@ -65,3 +65,41 @@ def test_poisson_subsample_spacing_and_density():
     d, _ = cKDTree(pos[k]).query(pos[k], k=2)
     assert d[:, 1].min() >= 0.078
     assert 0.9 * 1600 <= len(k) <= 1.1 * 1600   # about one point per 0.1 x 0.1 cell of the 4 x 4 square
+
+
+def _disc_snapshot(R, dxf, noise, seed):
+    """A fine lattice disc whose outer two rows are interface particles with
+    the exact outward normal and curvature -1/R, the curvature perturbed by
+    relative Gaussian noise."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(R / dxf) + 2
+    i, j = np.meshgrid(np.arange(-n, n + 1), np.arange(-n, n + 1), indexing="ij")
+    pos = np.stack([i.ravel() * dxf, j.ravel() * dxf], 1)
+    r = np.hypot(pos[:, 0], pos[:, 1])
+    pos = pos[r < R]
+    r = r[r < R]
+    iface = r > R - 2.0 * dxf
+    nhat = pos / np.maximum(r, 1e-12)[:, None]
+    kappa = -1.0 / R * (1.0 + noise * rng.normal(size=len(pos)))
+    return dict(pos=pos, iface=iface, nhat=nhat, kappa=kappa)
+
+
+def test_split_half_labels_measure_the_reference_noise():
+    """Coarse labels from a fine snapshot: with exact fine curvature both
+    half-labels equal the label; with noisy fine curvature, half the spread of
+    the two halves estimates the noise left in the full (averaged) label."""
+    R, dxc = 1.0, 0.1
+    s0 = cl.coarse_from_snapshot(_disc_snapshot(R, dxc / 4, 0.0, 1), 10, 500.0, 20.0, seed=3)
+    m = s0.meta["has_halves"]
+    assert m.sum() > 20 and np.all(s0.meta["has_ref"][m])
+    kh = s0.meta["kappa_halves"][m]
+    assert np.allclose(kh[:, 0], -1.0 / R, rtol=1e-12) and np.allclose(kh[:, 1], -1.0 / R, rtol=1e-12)
+    assert np.allclose(s0.meta["kappa_ref"][m], -1.0 / R, rtol=1e-12)
+    s1 = cl.coarse_from_snapshot(_disc_snapshot(R, dxc / 4, 0.5, 2), 10, 500.0, 20.0, seed=3)
+    m = s1.meta["has_halves"]
+    ref = s1.meta["kappa_ref"][m]
+    kh = s1.meta["kappa_halves"][m]
+    floor = 0.5 * np.linalg.norm(kh[:, 0] - kh[:, 1]) / np.linalg.norm(ref)
+    actual = np.linalg.norm(ref + 1.0 / R) / np.linalg.norm(ref)
+    assert 0.02 < actual < 0.5
+    assert 0.6 * actual < floor < 1.6 * actual
