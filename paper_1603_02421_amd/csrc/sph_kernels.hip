@@ -470,10 +470,11 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
         double2 q[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) q[j] = v.pos[bb[j]];
-        P pl[NB] = {};
+        // payloads unconditionally: a spent lane's index is its own slot, so
+        // every load is in bounds and none needs a branch around it
+        P pl[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-            if (ok[j]) pl[j] = load(bb[j]);
+        for (int j = 0; j < NB; ++j) pl[j] = load(bb[j]);
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (ok[j]) {
