@@ -196,6 +196,9 @@ def closure_leg(sph, batch, bits, block_sweep, cell_factor, args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     n1 = int(sim.read("nactive", allow_unstable=True).sum())
+    prof = sim.profile(args.profile_steps)
+    kernels = {k: dict(avg_ms=round(v["avg_ms"], 4), calls=v["calls"])
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"])}
     sim.evaluate()
     listed = sim.read("closure", allow_unstable=True)[:, 3] == 1.0
     fb = sim.read("fallback", allow_unstable=True)
@@ -203,7 +206,8 @@ def closure_leg(sph, batch, bits, block_sweep, cell_factor, args):
     value = args.steps * 0.5 * (n0 + n1) / (ms * 1e-3)
     print(f"[bench] closure: {args.steps} steps in {ms:.1f} ms, {value:.4g} particle-steps/s", flush=True)
     return dict(value=value, unit="particle-steps/s", ms_per_step=ms / args.steps, tolerance=0.2,
-                listed=int(listed.sum()), fallback_fraction=float(fb[listed].mean()) if listed.any() else 0.0)
+                listed=int(listed.sum()), fallback_fraction=float(fb[listed].mean()) if listed.any() else 0.0,
+                kernels=kernels)
 
 
 def main():

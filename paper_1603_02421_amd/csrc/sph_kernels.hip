@@ -724,9 +724,12 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
     }
     pre[w][lane] = incl - cnt;
     const uint32_t total = __shfl(incl, 63, 64);
+    __shared__ uint32_t cl_n[4], cl_base;
     __syncthreads();
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t e = (blockIdx.x * (blockDim.x >> 6) + (uint32_t)w) * 64u; e < total; e += nwaves * 64u) {
+    // the workgroup takes 256 consecutive entries per pass (64 per wave), so
+    // all its waves run the same passes and can share the closure-list atomic
+    for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < total; e0 += gridDim.x * blockDim.x) {
+        const uint32_t e = e0 + (uint32_t)w * 64u;
         const uint32_t idx = e + (uint32_t)lane;
         // region holding entry idx: the last r with pre[r] <= idx
         int r = 0;
@@ -780,18 +783,21 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
         }
         if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, (int)sys, dtf, in);
         if (v.cl_count) {
-            // append the listed slots, one atomic per wave
+            // append the listed slots, one atomic per workgroup and pass
             const unsigned long long bal = __ballot(listed);
-            if (bal) {
-                const int first = __ffsll((long long)bal) - 1;
-                uint32_t base = 0;
-                if (lane == first) base = atomicAdd(v.cl_count, (uint32_t)__popcll(bal));
-                base = __shfl(base, first, 64);
-                if (listed) {
-                    const uint32_t ci = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                    if (ci < v.cl_capacity) v.cl_list[ci] = a;
-                }
+            if (lane == 0) cl_n[w] = (uint32_t)__popcll(bal);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t tot = cl_n[0] + cl_n[1] + cl_n[2] + cl_n[3];
+                cl_base = tot ? atomicAdd(v.cl_count, tot) : 0u;
             }
+            __syncthreads();
+            if (listed) {
+                uint32_t ci = cl_base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                for (int k = 0; k < w; ++k) ci += cl_n[k];
+                if (ci < v.cl_capacity) v.cl_list[ci] = a;
+            }
+            __syncthreads();
         }
     }
 }

@@ -52,10 +52,61 @@ __device__ __forceinline__ float colsum(f4 v) {
 
 // ----------------------------------------------------------------- forward
 
+// tanh x = 1 - 2 / (e^{2x} + 1) from the hardware exp2 and reciprocal. Its
+// absolute error (about 1e-7) is far below the BF16 rounding the hidden
+// activations get next; the limits give exactly +-1.
+__device__ __forceinline__ float tanh_fast(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // e^{2x} = 2^{2x / ln 2}
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// The B fragments and biases this lane needs, read from the weights in memory
+// (the training kernel, whose registers hold the gradient sums) ...
+struct WMem {
+    const MlpView& W;
+    __device__ bf4 w1(int nb, int kb, int r, int g) const { return load4(W.wt1 + (16 * nb + r) * 64 + 16 * kb + 4 * g); }
+    __device__ bf4 w2(int nb, int kb, int r, int g) const { return load4(W.wt2 + (16 * nb + r) * 64 + 16 * kb + 4 * g); }
+    __device__ bf4 w3(int kb, int r, int g) const { return load4(W.wt3 + r * 64 + 16 * kb + 4 * g); }
+    __device__ float b1(int nb, int r) const { return W.b1[16 * nb + r]; }
+    __device__ float b2(int nb, int r) const { return W.b2[16 * nb + r]; }
+    __device__ float b3(int r) const { return W.b3[r]; }
+};
+
+// ... or held in registers for every tile a wave processes (72 VGPRs of
+// fragments, loaded once per wave).
+struct WReg {
+    bf4 f1[4][4], f2[4][4], f3[4];
+    float c1[4], c2[4], c3;
+    __device__ void load(const MlpView& W) {
+        const int l = __lane_id(), r = l & 15, g = l >> 4;
+        const WMem M{W};
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                f1[nb][kb] = M.w1(nb, kb, r, g);
+                f2[nb][kb] = M.w2(nb, kb, r, g);
+            }
+            c1[nb] = M.b1(nb, r);
+            c2[nb] = M.b2(nb, r);
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) f3[kb] = M.w3(kb, r, g);
+        c3 = M.b3(r);
+    }
+    __device__ bf4 w1(int nb, int kb, int, int) const { return f1[nb][kb]; }
+    __device__ bf4 w2(int nb, int kb, int, int) const { return f2[nb][kb]; }
+    __device__ bf4 w3(int kb, int, int) const { return f3[kb]; }
+    __device__ float b1(int nb, int) const { return c1[nb]; }
+    __device__ float b2(int nb, int) const { return c2[nb]; }
+    __device__ float b3(int) const { return c3; }
+};
+
 // One 16-row tile through the network. X: 16 x 64 BF16 in LDS (row-major).
 // h1, h2: LDS scratch 16 x 64 BF16. Returns the layer outputs in D layout:
 // H1[nb], H2[nb] (FP32, 4 column blocks) and Y (columns 0..2 valid).
-__device__ __forceinline__ void mlp_tile_forward(const MlpView& W, const uint16_t* xs, uint16_t* h1s, uint16_t* h2s,
+template <typename WS>
+__device__ __forceinline__ void mlp_tile_forward(const WS& W, const uint16_t* xs, uint16_t* h1s, uint16_t* h2s,
                                                  f4 H1[4], f4 H2[4], f4& Y) {
     const int l = __lane_id(), r = l & 15, g = l >> 4;
     bf4 xa[4];
@@ -65,11 +116,11 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpView& W, const uint16_
     for (int nb = 0; nb < 4; ++nb) {
         f4 acc = zero4();
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = mfma(xa[kb], load4(W.wt1 + (16 * nb + r) * 64 + 16 * kb + 4 * g), acc);
-        const float bias = W.b1[16 * nb + r];
+        for (int kb = 0; kb < 4; ++kb) acc = mfma(xa[kb], W.w1(nb, kb, r, g), acc);
+        const float bias = W.b1(nb, r);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float h = tanhf(acc[i] + bias);
+            float h = tanh_fast(acc[i] + bias);
             acc[i] = h;
             h1s[(4 * g + i) * 64 + 16 * nb + r] = f2bf(h);
         }
@@ -83,11 +134,11 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpView& W, const uint16_
     for (int nb = 0; nb < 4; ++nb) {
         f4 acc = zero4();
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = mfma(ha[kb], load4(W.wt2 + (16 * nb + r) * 64 + 16 * kb + 4 * g), acc);
-        const float bias = W.b2[16 * nb + r];
+        for (int kb = 0; kb < 4; ++kb) acc = mfma(ha[kb], W.w2(nb, kb, r, g), acc);
+        const float bias = W.b2(nb, r);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float h = tanhf(acc[i] + bias);
+            float h = tanh_fast(acc[i] + bias);
             acc[i] = h;
             h2s[(4 * g + i) * 64 + 16 * nb + r] = f2bf(h);
         }
@@ -96,9 +147,8 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpView& W, const uint16_
     __syncthreads();
     f4 acc = zero4();
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-        acc = mfma(load4(h2s + r * 64 + 16 * kb + 4 * g), load4(W.wt3 + r * 64 + 16 * kb + 4 * g), acc);
-    const float bias = W.b3[r];
+    for (int kb = 0; kb < 4; ++kb) acc = mfma(load4(h2s + r * 64 + 16 * kb + 4 * g), W.w3(kb, r, g), acc);
+    const float bias = W.b3(r);
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] += bias;
     Y = acc;
@@ -126,10 +176,12 @@ __global__ void __launch_bounds__(64) k_mlp_forward(MlpView W, const uint16_t* X
     __shared__ uint16_t xs[16 * 64], h1s[16 * 64], h2s[16 * 64];
     const int l = __lane_id(), r = l & 15, g = l >> 4;
     const int64_t ntiles = (m + 15) / 16;
+    WReg F;
+    F.load(W);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         load_tile(X, m, t * 16, xs);
         f4 H1[4], H2[4], y;
-        mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
+        mlp_tile_forward(F, xs, h1s, h2s, H1, H2, y);
         if (r < 3) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -168,7 +220,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(MlpView W, const uint16_t* X, c
         const int64_t row0 = t * 16;
         load_tile(X, m, row0, xs);
         f4 H1[4], H2[4], y;
-        mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
+        mlp_tile_forward(WMem{W}, xs, h1s, h2s, H1, H2, y);
         // output error: dY = 2 (Y - T) / (3 m) on valid rows and columns
         f4 dY;
 #pragma unroll
@@ -618,6 +670,8 @@ __global__ void __launch_bounds__(64) k_closure_net(EvalView<T> v, ClosureView C
     const int l = __lane_id(), r = l & 15, g = l >> 4;
     const int64_t m = (int64_t)*C.count;
     const int64_t ntiles = (m + 15) / 16;
+    WReg F;
+    F.load(W);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t row = t * 16 + l;
         const bool valid = l < 16 && row < m;
@@ -625,7 +679,7 @@ __global__ void __launch_bounds__(64) k_closure_net(EvalView<T> v, ClosureView C
         if (valid) in = closure_apply_load<T>(v, C.list[row]);
         load_tile(C.stencil, m, t * 16, xs);
         f4 H1[4], H2[4], y;
-        mlp_tile_forward(W, xs, h1s, h2s, H1, H2, y);
+        mlp_tile_forward(F, xs, h1s, h2s, H1, H2, y);
         if (r < 3) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -646,7 +700,8 @@ __global__ void __launch_bounds__(64) k_closure_net(EvalView<T> v, ClosureView C
 
 void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y, int ystride, hipStream_t st) {
     int64_t ntiles = (m + 15) / 16;
-    unsigned grid = (unsigned)(ntiles < 8192 ? (ntiles > 0 ? ntiles : 1) : 8192);
+    // every wave loads the weights once and walks several tiles
+    unsigned grid = (unsigned)(ntiles < 2048 ? (ntiles > 0 ? ntiles : 1) : 2048);
     k_mlp_forward<<<grid, 64, 0, st>>>(W, X, m, Y, ystride);
 }
 
@@ -688,7 +743,8 @@ void launch_closure(const EvalView<T>& v, const ClosureView& C, const MlpView& W
     k_stencil<T><<<sgrid, 64, 0, st>>>(v, C);
     kt->end(st);
     kt->begin("closure_net", st);
-    const unsigned ngrid = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1024, capacity / 512));
+    // the network's waves load the weights once and walk several tiles each
+    const unsigned ngrid = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(256, capacity / 2048));
     k_closure_net<T><<<ngrid, 64, 0, st>>>(v, C, W);
     kt->end(st);
 }
