@@ -217,6 +217,8 @@ struct Impl : sph_ctx_base {
     V4<T>* eos = nullptr;
     uint4* nmask = nullptr;
     uint32_t* nmask4 = nullptr;
+    uint4* smask = nullptr;      // skin mask (pairs within R s) of the first evaluation of a step
+    uint32_t* smask4 = nullptr;
     uint32_t surf_region = 0;
     uint32_t* surf_count = nullptr;
     uint32_t* surf_list = nullptr;
@@ -294,6 +296,8 @@ struct Impl : sph_ctx_base {
         eos = cv.take<V4<T>>(n_);
         nmask = cv.take<uint4>(n_);
         nmask4 = cv.take<uint32_t>(n_);
+        smask = cv.take<uint4>(n_);
+        smask4 = cv.take<uint32_t>(n_);
         surf_region = (uint32_t)surface_region(n_, n_sys_);
         surf_count = cv.take<uint32_t>(SURF_REGIONS);
         sb.surf_count = surf_count;
@@ -352,8 +356,14 @@ struct Impl : sph_ctx_base {
         v.dt_wave = dt_wave;
         v.vol = vol;
         v.eos = eos;
-        v.nmask = nmask;
-        v.nmask4 = nmask4;
+        // the first evaluation of a step scans the cells and writes the exact
+        // mask and the skin mask; the half-step evaluation walks the skin mask
+        // with the exact pair predicate
+        v.skin = half ? 1 : 0;
+        v.nmask = half ? smask : nmask;
+        v.nmask4 = half ? smask4 : nmask4;
+        v.smask = half ? nullptr : smask;
+        v.smask4 = half ? nullptr : smask4;
         v.surf_region = surf_region;
         v.surf_count = surf_count;
         v.surf_list = surf_list;
@@ -723,6 +733,9 @@ SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     s.R2 = (2.0 * p.h) * (2.0 * p.h);
     double skin = g.reach * p.cell_size - 2.0 * p.h;
     s.skin2 = 0.25 * skin * skin;
+    // pairs within 2h after a half step of at most skin/2 per particle were
+    // within R s = 2h + skin before it (the margin covers rounding)
+    s.Rs2 = (g.reach * p.cell_size) * (g.reach * p.cell_size) * (1.0 + 1e-12);
     s.nx = (int32_t)g.nx;
     s.ny = (int32_t)g.ny;
     s.reach = g.reach;

@@ -49,6 +49,7 @@ struct SysDev {
     // neighbour grid (FP64, so keys and the predicate are exact)
     double x0, y0, inv_s, R2;      // grid origin, 1/cell size, (2h)^2
     double skin2;                  // (half the skin)^2: allowed half-step displacement squared
+    double Rs2;                    // (R s)^2: radius^2 of the skin mask kept for the half step
     int32_t nx, ny, reach, kernel;
     uint32_t cell_base, pad_;
     // physics in the working precision

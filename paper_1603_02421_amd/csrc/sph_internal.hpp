@@ -83,8 +83,12 @@ struct EvalView {
     double* dt_wave;            // 2 per sweep chunk: the main sweep's wave minima of the same
     const T* vol;               // m / rho of every slot (this evaluation's state)
     V4<T>* eos;                 // (P / rho^2, colour, rho, m / rho), written by the colour sweep
-    uint4* nmask;                // n: neighbour mask words of cell rows 0..3
+    uint4* nmask;                // n: neighbour mask words of cell rows 0..3 (the mask the sweeps walk)
     uint32_t* nmask4;            // n: word of row 4 (+ overflow bit 31)
+    uint4* smask;                // n: skin mask (pairs within R s), written by the first colour sweep
+    uint32_t* smask4;
+    int skin;                    // 1: nmask is a skin mask, walkers apply the exact pair predicate
+    int pad3_;
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
     uint32_t* cl_list;
     uint32_t cl_capacity;

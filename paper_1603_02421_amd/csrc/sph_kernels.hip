@@ -313,7 +313,8 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 }
 
 // Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that
-// passes the exact predicate |r_ab|^2 < (2h)^2. Candidates are taken four at a
+// passes the exact predicate |r_ab|^2 < rp2 (rp2 = (2h)^2 for the neighbours,
+// (R s)^2 for the skin mask of the colour sweep). Candidates are taken four at a
 // time: their positions are loaded together, then the per-neighbour payload of
 // the accepted ones (load(b)), then compute(b, k, dx, dy, r2, payload) with k
 // the slot's place in its cell row, r_ab = r_a - r_b in the working precision
@@ -323,7 +324,7 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 template <typename T, int NB = 4, typename LoadFn, typename ComputeFn, typename RowEndFn>
 __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
                                                 uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
-                                                ComputeFn&& compute, RowEndFn&& row_end) {
+                                                ComputeFn&& compute, RowEndFn&& row_end, double rp2) {
     using P = typename std::decay<decltype(load(0u))>::type;
     const uint32_t ny = (uint32_t)S.ny;
     const uint32_t local = cell - S.cell_base;
@@ -334,7 +335,7 @@ __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32
     const int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
     const int xlo = cx - R < 0 ? 0 : cx - R;
     const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
-    const double R2 = S.R2;
+    const double R2 = rp2;
     int r = 0;   // row of the block, 0 at x = xlo
     for (int X = xlo; X <= xhi; ++X, ++r) {
         const uint32_t row = S.cell_base + (uint32_t)X * ny;
@@ -376,7 +377,7 @@ __device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* _
                                            ComputeFn&& compute) {
     scan_cells_rows<T, NB>(S, cstart, cell, a, pa, pos, load,
                            [&](uint32_t b, uint32_t, T dx, T dy, double, const auto& p) { compute(b, dx, dy, p); },
-                           [](int) {});
+                           [](int) {}, S.R2);
 }
 
 // Reference-style visitor, one candidate at a time (debug neighbour lists).
@@ -406,7 +407,8 @@ __device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_
 // Visit the neighbours recorded in slot a's mask words, four at a time
 // (positions and payloads, then compute). Bit k of word r is the k-th slot of
 // cell row r of the block; r_ab = r_a - r_b is formed in FP64 exactly as in
-// the scan.
+// the scan. A skin mask (v.skin) also holds pairs out to R s: those that fail
+// the exact predicate |r_ab|^2 < (2h)^2 are skipped.
 template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
                                                 const RowMask& M, LoadFn&& load, ComputeFn&& compute) {
@@ -479,8 +481,8 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
         for (int j = 0; j < NB; ++j) {
             if (ok[j]) {
                 double ex, ey;
-                pair_r2(pa, q[j], ex, ey);
-                compute(bb[j], (T)ex, (T)ey, pl[j]);
+                const double r2 = pair_r2(pa, q[j], ex, ey);
+                if (!v.skin || r2 < S.R2) compute(bb[j], (T)ex, (T)ey, pl[j]);
             }
         }
     }
@@ -511,13 +513,62 @@ template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; uint32_t tag; };
 template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 
 // Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included
-// (eq. 14). The cell scan of this sweep also records which candidates passed
-// the pair predicate, for the two sweeps that follow, and the Tait equation
-// (eq. 26) is evaluated here once per particle: the record (P / rho^2, C, rho,
-// m / rho) is everything the main sweep gathers of a neighbour besides its
-// position and velocity (the sound speed follows from rho).
+// (eq. 14). The Tait equation (eq. 26) is evaluated here once per particle:
+// the record (P / rho^2, C, rho, m / rho) is everything the main sweep
+// gathers of a neighbour besides its position and velocity (the sound speed
+// follows from rho).
+//
+// The first evaluation of a step scans the cells. Its candidates within R s
+// (the cell block's radius) are recorded as the skin mask; those within 2h
+// enter the colour sum and the exact mask that the other sweeps walk. The
+// half-step evaluation (k_colour_skin) walks the skin mask instead of the
+// cells: the predictor keeps every particle within half the skin of its
+// step-start position, so every pair within 2h at the half step is in it.
 // Eight waves per SIMD (at most 64 VGPRs): the candidate scan is issue-bound
 // and hides its gathers best with the most waves (measured 5% faster than 7).
+
+// Mask words under construction: `cur` collects the row being scanned,
+// row_end files it.
+struct MaskBuilder {
+    RowMask M = {{0u, 0u, 0u, 0u, 0u}};
+    uint32_t cur = 0;
+    bool overflow = false;
+    __device__ void mark(uint32_t k) {
+        if (k < MASK_ROW_BITS) cur |= 1u << k;
+        else overflow = true;
+    }
+    __device__ void row_end(int r) {
+        M.w[0] = r == 0 ? cur : M.w[0];
+        M.w[1] = r == 1 ? cur : M.w[1];
+        M.w[2] = r == 2 ? cur : M.w[2];
+        M.w[3] = r == 3 ? cur : M.w[3];
+        M.w[4] = r == 4 ? cur : M.w[4];
+        cur = 0;
+    }
+    // bit 31 of the last word is the overflow flag, so that row holds 31 bits
+    __device__ void store(uint4* w03, uint32_t* w4, uint32_t a) {
+        if (M.w[4] & MASK_OVERFLOW) overflow = true;
+        w03[a] = make_uint4(M.w[0], M.w[1], M.w[2], M.w[3]);
+        w4[a] = overflow ? (M.w[4] | MASK_OVERFLOW) : M.w[4];
+    }
+};
+
+// The colour, then the record of slot a.
+template <typename T>
+__device__ __forceinline__ void colour_finish(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, T vol_a,
+                                              T dens_a, T wsum) {
+    const T sum = vol_a * S.W0 + S.wnorm * wsum;
+    v.colour[a] = sum;
+    T rho_a, pr_a;
+    tait(S, dens_a, rho_a, pr_a);
+    V4<T> e;
+    e.x = pr_a;
+    e.y = sum;
+    e.z = rho_a;
+    e.w = vol_a;
+    v.eos[a] = e;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_colour(EvalView<T> v) {
     int sys;
@@ -529,58 +580,63 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const double2 pa = v.pos[a];
     const T vol_a = v.vol[a];
     const T dens_a = v.dens[a];   // for the record written at the end
+    const double R2 = S.R2;
     T wsum = 0;   // sum_b (m_b / rho_b) W_ab / wnorm
-    // mask words: `cur` collects the row being scanned, row_end files it
-    RowMask M = {{0u, 0u, 0u, 0u, 0u}};
-    uint32_t cur = 0;
-    bool overflow = false;
-    auto mark = [&](uint32_t k) {
-        if (k < MASK_ROW_BITS) cur |= 1u << k;
-        else overflow = true;
-    };
-    auto row_end = [&](int r) {
-        M.w[0] = r == 0 ? cur : M.w[0];
-        M.w[1] = r == 1 ? cur : M.w[1];
-        M.w[2] = r == 2 ? cur : M.w[2];
-        M.w[3] = r == 3 ? cur : M.w[3];
-        M.w[4] = r == 4 ? cur : M.w[4];
-        cur = 0;
-    };
+    MaskBuilder E, Sk;   // exact mask (pairs within 2h) and skin mask (within R s)
     auto load = [&](uint32_t b) { return v.vol[b]; };
     auto acc = [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); };
+    auto row_end = [&](int r) {
+        E.row_end(r);
+        Sk.row_end(r);
+    };
     if (S.reach == 1) {
         // 3 x 3 blocks (about 3.5 candidates per neighbour): first the pair
-        // predicate alone, recorded as the mask, then the kernel sum over the
-        // accepted neighbours only, so lanes do not pay for each other's
-        // accepted candidates
+        // predicates alone, recorded as the masks, then the kernel sum over the
+        // exact mask only, so lanes do not pay for each other's accepted
+        // candidates
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
-                           [&](uint32_t, uint32_t k, T, T, double, int) { mark(k); }, row_end);
-        if (!overflow) mask_neighbours<T>(v, S, a, pa, M, load, acc);
+                           [&](uint32_t, uint32_t k, T, T, double r2, int) {
+                               Sk.mark(k);
+                               if (r2 < R2) E.mark(k);
+                           },
+                           row_end, S.Rs2);
+        if (!E.overflow) mask_neighbours<T>(v, S, a, pa, E.M, load, acc);
         else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc);
     } else {
         // 5 x 5 blocks (about 2.2 candidates per neighbour): one pass
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
                            [&](uint32_t, uint32_t k, T, T, double r2, T vol_b) {
-                               wsum += vol_b * kernel_shape(K, sqrt_((T)r2));
-                               mark(k);
+                               Sk.mark(k);
+                               if (r2 < R2) {
+                                   wsum += vol_b * kernel_shape(K, sqrt_((T)r2));
+                                   E.mark(k);
+                               }
                            },
-                           row_end);
+                           row_end, S.Rs2);
     }
-    // bit 31 of the last word is the overflow flag, so that row holds 31 bits
-    if (M.w[4] & MASK_OVERFLOW) overflow = true;
-    const T sum = vol_a * S.W0 + K.wnorm * wsum;
-    v.colour[a] = sum;
-    // the record the later sweeps gather of every neighbour
-    T rho_a, pr_a;
-    tait(S, dens_a, rho_a, pr_a);
-    V4<T> e;
-    e.x = pr_a;
-    e.y = sum;
-    e.z = rho_a;
-    e.w = vol_a;
-    v.eos[a] = e;
-    v.nmask[a] = make_uint4(M.w[0], M.w[1], M.w[2], M.w[3]);
-    v.nmask4[a] = overflow ? (M.w[4] | MASK_OVERFLOW) : M.w[4];
+    colour_finish(v, S, a, vol_a, dens_a, wsum);
+    E.store(v.nmask, v.nmask4, a);
+    Sk.store(v.smask, v.smask4, a);
+}
+
+// Sweep 1 of the half-step evaluation: the same colour sum over the skin mask
+// of the first evaluation (v.nmask with v.skin set), which the walk filters by
+// the exact predicate; the sweeps that follow walk the same skin mask.
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_colour_skin(EvalView<T> v) {
+    int sys;
+    uint32_t a;
+    if (!wave_assign(v, sys, a)) return;
+    const SysDev<T>& S = v.sys[sys];
+    if (a >= v.sys_hi[sys]) return;
+    const KernelConsts<T> K = kconsts(S);
+    const double2 pa = v.pos[a];
+    const T vol_a = v.vol[a];
+    const T dens_a = v.dens[a];
+    T wsum = 0;
+    neighbours<T>(v, S, a, pa, [&](uint32_t b) { return v.vol[b]; },
+                  [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); });
+    colour_finish(v, S, a, vol_a, dens_a, wsum);
 }
 
 // Sweep 2: continuity (eq. 7) for every active particle (a boundary particle
@@ -1074,7 +1130,8 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
     const unsigned nb = nblk(max_waves, bs / 64);
     kt->begin("colour", st);
-    k_colour<T><<<nb, bs, 0, st>>>(v);
+    if (v.skin) k_colour_skin<T><<<nb, bs, 0, st>>>(v);
+    else k_colour<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
     kt->begin("main", st);
     k_main<T><<<nb, bs, 0, st>>>(v);

@@ -412,8 +412,8 @@ __device__ __forceinline__ int select_bit(uint32_t m, int i) {
 }
 
 // Candidates of a listed slot: the set bits of its mask words, or, when the
-// mask overflowed, every slot of its block up to the 128th (then the distance
-// test is redone here).
+// mask overflowed, every slot of its block up to the 128th. The distance test
+// is redone for each candidate (a skin mask also holds pairs out to R s).
 __device__ __forceinline__ int stencil_candidates(const RowMask& M) {
     if (M.w[4] & MASK_OVERFLOW) return 128;
     return __popc(M.w[0]) + __popc(M.w[1]) + __popc(M.w[2]) + __popc(M.w[3]) + __popc(M.w[4]);
@@ -489,7 +489,9 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
             if (b == 0xFFFFFFFFu || b == a) continue;
             double ex, ey;
             const double r2 = pair_r2(pa, v.pos[b], ex, ey);
-            if (overflow && !(r2 < S.R2)) continue;
+            // an overflowed mask lists every slot of the block, and the
+            // half step's skin mask pairs out to R s: the exact predicate
+            if (!(r2 < S.R2)) continue;
             if (tag_type(v.tag[b]) != T_FLUID) continue;
             // relative position of b as seen from a, in units of h, then in the frame (e1, e2)
             const float x = -(float)ex * ih, y = -(float)ey * ih;
