@@ -40,7 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, c,
 # rho, m/rho), neighbour mask 20 (one word per cell row).
 ALGO_BYTES = {
-    "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20,               # pos vol cell dens -> colour eos mask
+    "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20 + 20,          # pos vol cell dens -> colour eos mask skin-mask
+    "colour_skin": 16 + 4 + 4 + 4 + 20 + 4 + 16,          # pos vol cell dens skin-mask -> colour eos
     "main": 4 + 16 + 8 + 16 + 20 + 4 + 4 + 8 + 8,         # tag pos vel eos mask cell -> drho acc nrm
     # per filtered particle: list entry tag nrm acc rho vol pos mask cell -> acc kappa kappa_plain
     # (88 B), over active particles at the 2.9% filtered on the 64-jet batch
@@ -54,8 +55,8 @@ ALGO_BYTES = {
 
 
 KERNEL_NAMES = {  # device function -> the name the library's profiler gives it
-    "k_colour": "colour", "k_main": "main", "k_surface": "surface", "k_permute": "sort_permute",
-    "k_predict": "predict", "k_correct": "correct", "k_key": "sort_key", "k_scatter": "sort_scatter",
+    "k_colour": "colour", "k_colour_skin": "colour_skin", "k_main": "main", "k_surface": "surface",
+    "k_permute": "sort_permute", "k_predict": "predict", "k_correct": "correct", "k_key": "sort_key", "k_scatter": "sort_scatter",
     "k_stencil": "closure_stencil", "k_closure_net": "closure_net",
 }
 

@@ -1129,9 +1129,13 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     const int bs = L.block_sweep;
     const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
     const unsigned nb = nblk(max_waves, bs / 64);
-    kt->begin("colour", st);
-    if (v.skin) k_colour_skin<T><<<nb, bs, 0, st>>>(v);
-    else k_colour<T><<<nb, bs, 0, st>>>(v);
+    if (v.skin) {
+        kt->begin("colour_skin", st);
+        k_colour_skin<T><<<nb, bs, 0, st>>>(v);
+    } else {
+        kt->begin("colour", st);
+        k_colour<T><<<nb, bs, 0, st>>>(v);
+    }
     kt->end(st);
     kt->begin("main", st);
     k_main<T><<<nb, bs, 0, st>>>(v);
