@@ -77,19 +77,23 @@ def traffic_path(workload: str) -> str:
 
 
 def measured_traffic(workload: str, cell_factor: float, block_sweep: int, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, when it was taken on these sources and this launch shape."""
+    """(HBM bytes per launch of `kernel`, the launch shape they were taken on)
+    from the committed rocprofv3 counter summary, when it was taken on these
+    sources and this cell size (the bytes a kernel moves follow its cells, not
+    its workgroup size); (None, None) otherwise."""
     try:
         with open(traffic_path(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
+        return None, None
     if t.get("sources_sha256") != sources_digest():
-        return None
-    if abs(t.get("cell_factor", 0) - cell_factor) > 1e-9 or t.get("block_sweep") != block_sweep:
-        return None
+        return None, None
+    if abs(t.get("cell_factor", 0) - cell_factor) > 1e-9:
+        return None, None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    if k is None:
+        return None, None
+    return k["fetch_bytes"] + k["write_bytes"], f"cell size {t['cell_factor']} h, {t['block_sweep']}-thread sweep blocks"
 
 
 def _pmc(path: str, counter: str):
@@ -301,6 +305,7 @@ def main():
                        share=round(v["avg_ms"] * v["calls"] / args.profile_steps / step_ms, 4))
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"])}
     step_bytes = sum(ALGO_BYTES.get(k, 0) * v["calls"] for k, v in prof.items()) / args.profile_steps
+    traffic_bytes, traffic_launch = measured_traffic(args.workload, cell_factor, block_sweep, dom)
     out = {
         "metric": "particle-steps/s (plain vs learned closure, batched jets); % HBM roofline",
         "value": value,
@@ -319,7 +324,7 @@ def main():
                    "autotune": tune},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, cell_factor, block_sweep, dom),
+                     "traffic": traffic_bytes, "traffic_launch": traffic_launch,
                      "algo_bytes_per_particle": ALGO_BYTES[dom], "avg_launch_ms": avg},
         "step_model": {"algo_bytes_per_particle_step": step_bytes,
                        "hbm_frac": step_bytes * value / (HBM_PEAK_GBS * 1e9)},

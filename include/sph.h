@@ -209,7 +209,7 @@ sph_status sph_profile(sph_ctx* ctx, int32_t n_steps, int32_t max_stats, const c
 
 /* Pick the cell size and sweep block shape for these systems by timing: for
  * cell sizes 1.05, 1.1, 1.2 h (5 x 5 cell blocks) and 2.05, 2.2 h (3 x 3) and
- * block_sweep 128 and 256, a throwaway context is built from the given initial
+ * block_sweep 256 and 128, a throwaway context is built from the given initial
  * state inside d_workspace (the caller's arrays are not modified), run for two
  * warm-up steps and two windows of trial_steps timed steps (the faster window
  * counts), and freed. A configuration later in that order replaces the best so

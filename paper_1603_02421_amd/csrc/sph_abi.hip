@@ -1063,7 +1063,7 @@ sph_status sph_autotune(const sph_options* opt, int32_t n_sys, const sph_params*
         return SPH_OK;
     }
     const double factors[] = {1.05, 1.1, 1.2, 2.05, 2.2};
-    const int blocks[] = {128, 256};
+    const int blocks[] = {256, 128};   // the usual winner first: a later one must beat it by 2%
     std::vector<sph_params> q(p, p + n_sys);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
