@@ -470,29 +470,48 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
         for (int it = 0; it < 2; ++it) {
             const int idx = j + width * it;
             if (idx >= total || (width == 32 && it == 1)) continue;
-            // the idx-th candidate: the idx-th set bit over the rows' words, or,
-            // after an overflow, the idx-th slot of the block
-            uint32_t ord0 = 0, b = 0xFFFFFFFFu;
-            int r = 0;
-            for (int X = xlo; X <= xhi; ++X, ++r) {
-                const uint32_t rowc = S.cell_base + (uint32_t)X * ny;
-                const uint32_t b0 = v.cstart[rowc + ylo];
-                const uint32_t wr = r == 0 ? M.w[0] : r == 1 ? M.w[1] : r == 2 ? M.w[2] : r == 3 ? M.w[3] : M.w[4];
-                const uint32_t cnt = overflow ? v.cstart[rowc + yhi + 1] - b0 : (uint32_t)__popc(wr);
-                if ((uint32_t)idx < ord0 + cnt) {
-                    const uint32_t k = (uint32_t)idx - ord0;
-                    b = b0 + (overflow ? k : (uint32_t)select_bit(wr, (int)k));
-                    break;
+            // the idx-th candidate: the idx-th set bit over the rows' words (its
+            // row found from the words' bit counts, then one cell-start load),
+            // or, after an overflow, the idx-th slot of the block
+            uint32_t b = 0xFFFFFFFFu;
+            if (!overflow) {
+                uint32_t ord0 = 0, wsel = 0, k = 0;
+                int rsel = -1;
+#pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    const uint32_t cnt = (uint32_t)__popc(M.w[r]);
+                    const bool here = rsel < 0 && (uint32_t)idx < ord0 + cnt;
+                    rsel = here ? r : rsel;
+                    wsel = here ? M.w[r] : wsel;
+                    k = here ? (uint32_t)idx - ord0 : k;
+                    ord0 += cnt;
                 }
-                ord0 += cnt;
+                // rows past the grid edge have no bits, so rsel <= xhi - xlo
+                if (rsel >= 0)
+                    b = v.cstart[S.cell_base + (uint32_t)(xlo + rsel) * ny + ylo] + (uint32_t)select_bit(wsel, (int)k);
+            } else {
+                uint32_t ord0 = 0;
+                for (int X = xlo; X <= xhi; ++X) {
+                    const uint32_t rowc = S.cell_base + (uint32_t)X * ny;
+                    const uint32_t b0 = v.cstart[rowc + ylo];
+                    const uint32_t cnt = v.cstart[rowc + yhi + 1] - b0;
+                    if ((uint32_t)idx < ord0 + cnt) {
+                        b = b0 + ((uint32_t)idx - ord0);
+                        break;
+                    }
+                    ord0 += cnt;
+                }
             }
             if (b == 0xFFFFFFFFu || b == a) continue;
+            // b is a slot of the block: its position, tag and id are loaded together
+            const double2 pb = v.pos[b];
+            const uint32_t tb = v.tag[b], idb = v.id[b];
             double ex, ey;
-            const double r2 = pair_r2(pa, v.pos[b], ex, ey);
+            const double r2 = pair_r2(pa, pb, ex, ey);
             // an overflowed mask lists every slot of the block, and the
             // half step's skin mask pairs out to R s: the exact predicate
             if (!(r2 < S.R2)) continue;
-            if (tag_type(v.tag[b]) != T_FLUID) continue;
+            if (tag_type(tb) != T_FLUID) continue;
             // relative position of b as seen from a, in units of h, then in the frame (e1, e2)
             const float x = -(float)ex * ih, y = -(float)ey * ih;
             const float xl = x * e1x + y * e1y, yl = y * e1x - x * e1y;
@@ -503,7 +522,7 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
             iy[it] = yl;
             id2[it] = x * x + y * y;
             ian[it] = ang;
-            iid[it] = v.id[b];
+            iid[it] = idb;
         }
     }
     // compact the group's valid items into its LDS slots [0, k)
@@ -577,8 +596,10 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
 // written as 64 BF16 values per row. A wave takes two listed particles, one
 // per half, when both have at most 32 candidates (the usual case on a free
 // surface), and otherwise builds them one after the other with all 64 lanes.
+// The kernel waits on chains of dependent loads: eight waves per SIMD (at most
+// 64 VGPRs, no spills) hide more of them than seven.
 template <typename T>
-__global__ void __launch_bounds__(64) k_stencil(EvalView<T> v, ClosureView C) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) k_stencil(EvalView<T> v, ClosureView C) {
     __shared__ float sx[128], sy[128], sd[128], sa[128];
     __shared__ uint32_t sid[128], skeep[128];
     const int l = __lane_id();
