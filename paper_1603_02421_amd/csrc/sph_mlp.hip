@@ -766,8 +766,10 @@ void launch_closure(const EvalView<T>& v, const ClosureView& C, const MlpView& W
     k_stencil<T><<<sgrid, 64, 0, st>>>(v, C);
     kt->end(st);
     kt->begin("closure_net", st);
-    // the network's waves load the weights once and walk several tiles each
-    const unsigned ngrid = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(256, capacity / 2048));
+    // the network's waves load the weights once and walk several tiles each;
+    // at most 3072 of them, one per wave slot of the chip at this kernel's three
+    // waves per SIMD
+    const unsigned ngrid = (unsigned)std::min<int64_t>(3072, std::max<int64_t>(256, capacity / 2048));
     k_closure_net<T><<<ngrid, 64, 0, st>>>(v, C, W);
     kt->end(st);
 }
