@@ -1,0 +1,73 @@
+"""Parity at the benchmark's full size: the batch of 64 jets, 7.88M particles in
+FP32, that bench.py times, in the launch shape its autotuner picks there (cell
+size 1.05 h, 256-thread sweep blocks) and with graph-replayed steps.
+
+Every particle of every jet is compared with the FP64 oracle: one evaluation to
+1e-5 of each quantity's absolute-sum scale (the bound of the small cases), and
+a three-step trajectory to 1e-4 (positions in units of the jet's dx, density
+of rho0 = 1, velocities of the largest speed). The jets are independent
+systems, so the oracle runs them as one batch as well.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from parity_util import compare_eval, gpu_eval
+
+pytestmark = pytest.mark.gpu
+
+CELL_FACTOR, BLOCK_SWEEP = 1.05, 256
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import bench
+    batch, _, bits = bench.make_workload("c3")
+    assert bits == 32 and len(batch.systems) == 64
+    for sy in batch.systems:
+        sy.params["cell_size"] = CELL_FACTOR * sy.params["h"]
+    return batch
+
+
+def _per_particle(batch, f):
+    return np.concatenate([np.full(s.n, f(s)) for s in batch.systems])
+
+
+def test_full_batch_single_evaluation(gpu, orc, c3):
+    say(f"[full size] evaluation: 64 jets, n={c3.n}, cell {CELL_FACTOR} h, block {BLOCK_SWEEP}")
+    with gpu.Simulation(c3, dtype_bits=32, block_sweep=BLOCK_SWEEP) as sim:
+        g = gpu_eval(sim)
+    o = orc.evaluate(c3)
+    start, nbr = orc.neighbors(c3)
+    say(f"   oracle: {len(nbr)} neighbour pairs")
+    eps = _per_particle(c3, lambda s: s.params["eps_h"] / s.params["h"])
+    rep = compare_eval(g, o, eps, start, nbr, 1e-5, c3.cat("type") == wl.FLUID)
+    say("  ", rep)
+    ok = np.isfinite(o["dt"]) & (o["dt"] > 0)
+    assert ok.sum() == 64
+    assert np.allclose(g["dt"][ok], o["dt"][ok], rtol=1e-5, atol=0)
+
+
+def test_full_batch_trajectory(gpu, orc, c3):
+    n_steps = 3
+    say(f"[full size] trajectory: 64 jets, n={c3.n}, {n_steps} graph-replayed steps")
+    st = orc.State(c3)
+    with gpu.Simulation(c3, dtype_bits=32, block_sweep=BLOCK_SWEEP, use_graph=1, graph_steps=2) as sim:
+        sim.step(n_steps)
+        pos, vel, rho = sim.read("pos"), sim.read("vel"), sim.read("rho")
+        typ, flags, t = sim.read("type"), sim.read("flags")[0], sim.read("time")
+    st.step(n_steps)
+    assert flags == 0
+    assert np.array_equal(typ, st.type)
+    assert np.allclose(t, st.time, rtol=1e-5)
+    act = st.type != wl.INACTIVE
+    dx = _per_particle(c3, lambda s: s.meta["dx"])
+    ep = (np.linalg.norm(pos - st.pos, axis=1) / dx)[act].max()
+    er = np.abs(rho - st.rho)[act].max()
+    ev = np.linalg.norm(vel - st.vel, axis=1)[act].max() / np.linalg.norm(st.vel, axis=1)[act].max()
+    say(f"   after {n_steps} steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
+    assert ep <= 1e-4 and er <= 1e-4 and ev <= 1e-4
