@@ -6,7 +6,8 @@ Every particle of every jet is compared with the FP64 oracle: one evaluation to
 1e-5 of each quantity's absolute-sum scale (the bound of the small cases), and
 a three-step trajectory to 1e-4 (positions in units of the jet's dx, density
 of rho0 = 1, velocities of the largest speed). The jets are independent
-systems, so the oracle runs them as one batch as well.
+systems, so the oracle runs them as one batch as well. The closure leg is
+checked on the same batch with the closure bounds of the small cases.
 """
 import numpy as np
 import pytest
@@ -71,3 +72,17 @@ def test_full_batch_trajectory(gpu, orc, c3):
     ev = np.linalg.norm(vel - st.vel, axis=1)[act].max() / np.linalg.norm(st.vel, axis=1)[act].max()
     say(f"   after {n_steps} steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
     assert ep <= 1e-4 and er <= 1e-4 and ev <= 1e-4
+
+
+def test_full_batch_closure_evaluation(gpu, orc, c3):
+    """The closure leg of the benchmark: the same batch with the learned closure
+    in every jet (random network weights). The listed particles, network
+    outputs, fallback decisions, accelerations and dt are compared everywhere;
+    the stencils of 4,000 listed particles one by one, the others by a check
+    that they hold the oracle's points in its order."""
+    from test_gpu_closure import check_closure_evaluation
+    batch = wl.Batch([s.copy() for s in c3.systems])
+    for s in batch.systems:
+        s.params["closure"] = 1
+    say(f"[full size] closure evaluation: 64 jets, n={batch.n}")
+    check_closure_evaluation(gpu, orc, batch, 32, 0.2, sim_kw=dict(block_sweep=BLOCK_SWEEP), sample=4000)
