@@ -196,6 +196,28 @@ def test_short_trajectory_fp32_jet(gpu, orc, use_graph):
         assert np.array_equal(sim.read("type"), st.type)
 
 
+def test_inviscid_jet(gpu, orc):
+    """The paper's inviscid setting (alpha = 0): the viscosity term vanishes;
+    one evaluation and a short trajectory match the oracle."""
+    obj = _rounded(CASES["small_jet"], 32).copy()
+    obj.params["alpha"] = 0.0
+    dx = obj.meta["dx"]
+    say(f"[inviscid] small_jet alpha=0 n={obj.n}")
+    with _sim(gpu, obj) as sim:
+        g = gpu_eval(sim)
+    o = orc.evaluate(obj)
+    start, nbr = orc.neighbors(obj)
+    rep = compare_eval(g, o, _eps_per_particle(obj), start, nbr, 1e-5, obj.type == wl.FLUID)
+    say("  ", rep)
+    st = orc.State(obj)
+    with _sim(gpu, obj) as sim:
+        sim.step(10)
+        st.step(10)
+        ep, er, ev = _traj_errors(sim, st, dx, 1.0)
+    say(f"   after 10 steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
+    assert ep <= 1e-4 and er <= 1e-4 and ev <= 1e-4
+
+
 def test_fast_particles_within_the_cell_skin(gpu, orc):
     """Particles moving 0.04-0.08h in the half step, close to the 0.1h the
     cell skin allows (cells of 2.2h, one ring): the half-step evaluation,
