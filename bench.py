@@ -248,8 +248,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": src.numel() * 4, "copies": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the batched jets shard "
-              "across GPUs by whole jets, which this build does not run).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the batched jets would "
+              "shard across GPUs by whole jets; the library runs on one GPU per process).", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
