@@ -234,10 +234,16 @@ __global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* key, cons
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t k = i < n ? key[i] : 0u;
     const bool inactive = i < n && k == trash;
+    // the particle's state is loaded before the compaction scan and the rank
+    // search, so those loads overlap their latency
+    const int j = i < n ? i : 0;
+    const double2 p = X.pos[j];
+    const V2<T> u = X.vel[j];
+    const T dens = X.dens[j], mass = X.mass[j];
+    const uint32_t t = X.tag[j], pid = X.id[j];
     uint32_t tot;
     const uint32_t rank = block_exclusive_scan(inactive ? 1u : 0u, &tot);
     if (i >= n) return;
-    const uint32_t pid = X.id[i];
     uint32_t dst;
     if (inactive) {
         dst = cstart[trash] + blk_off[blockIdx.x] + rank;
@@ -247,10 +253,8 @@ __global__ void k_permute(int n, const SysDev<T>* sys, const uint32_t* key, cons
         for (uint32_t j = lo; j < hi; ++j) r += cell_ids[j] < pid ? 1u : 0u;
         dst = lo + r;
     }
-    const T dens = X.dens[i], mass = X.mass[i];
-    const uint32_t t = X.tag[i];
-    Y.pos[dst] = X.pos[i];
-    Y.vel[dst] = X.vel[i];
+    Y.pos[dst] = p;
+    Y.vel[dst] = u;
     Y.dens[dst] = dens;
     Y.mass[dst] = mass;
     Y.tag[dst] = t;
