@@ -968,22 +968,24 @@ template <typename T>
 __global__ void k_correct(IntegView<T> v) {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= v.n) return;
-    uint32_t t = v.tag[a];
-    uint32_t ty = tag_type(t);
+    // the slot's state with its tag: the loads do not wait for the type test
+    const uint32_t t = v.tag[a];
+    double2 p = v.pos[a];
+    V2<T> u = v.vel[a];
+    const V2<T> acc = v.acc[a];
+    const T dens0 = v.dens[a], drho = v.drho[a];
+    const uint32_t ty = tag_type(t);
     if (ty == T_INACTIVE) return;
     const SysDev<T>& S = v.sys[tag_sys(t)];
     double dt = v.dt[tag_sys(t)];
     T tdt = (T)dt;
-    T dens = v.dens[a] + tdt * v.drho[a];
+    T dens = dens0 + tdt * drho;
     if (ty != T_FLUID && dens < T(0)) dens = T(0);   // boundaries never below rho0
     v.dens[a] = dens;
     uint32_t flags = 0;
     if (!isfinite(dens)) flags |= FLAG_NONFINITE;
     else if (dens < T(-0.5) * S.rho0 || dens > S.rho0) flags |= FLAG_DENSITY;
-    double2 p = v.pos[a];
     if (ty == T_FLUID) {
-        V2<T> u = v.vel[a];
-        V2<T> acc = v.acc[a];
         p.x = p.x + dt * ((double)u.x + 0.5 * dt * (double)acc.x);
         p.y = p.y + dt * ((double)u.y + 0.5 * dt * (double)acc.y);
         u.x += tdt * acc.x;
