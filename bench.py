@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, c,
 # rho, m/rho), neighbour mask 20 (one word per cell row).
 ALGO_BYTES = {
-    "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20 + 20,          # pos vol cell dens -> colour eos mask skin-mask
+    "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20,               # pos vol cell tag dens -> colour eos skin-mask
     "colour_skin": 16 + 4 + 4 + 4 + 20 + 4 + 16,          # pos vol cell dens skin-mask -> colour eos
     "main": 4 + 16 + 8 + 16 + 20 + 4 + 4 + 8 + 8,         # tag pos vel eos mask cell -> drho acc nrm
     # per filtered particle: list entry tag nrm acc rho vol pos mask cell -> acc kappa kappa_plain

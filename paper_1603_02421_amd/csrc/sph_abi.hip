@@ -215,8 +215,6 @@ struct Impl : sph_ctx_base {
     T *colour = nullptr, *drho = nullptr, *kappa = nullptr, *kappa_plain = nullptr, *aux = nullptr;
     T* vol = nullptr;
     V4<T>* eos = nullptr;
-    uint4* nmask = nullptr;
-    uint32_t* nmask4 = nullptr;
     uint4* smask = nullptr;      // skin mask (pairs within R s) of the first evaluation of a step
     uint32_t* smask4 = nullptr;
     uint32_t surf_region = 0;
@@ -294,8 +292,6 @@ struct Impl : sph_ctx_base {
         aux = cv.take<T>(n_ < 2 ? 2 : n_);
         vol = cv.take<T>(n_);
         eos = cv.take<V4<T>>(n_);
-        nmask = cv.take<uint4>(n_);
-        nmask4 = cv.take<uint32_t>(n_);
         smask = cv.take<uint4>(n_);
         smask4 = cv.take<uint32_t>(n_);
         surf_region = (uint32_t)surface_region(n_, n_sys_);
@@ -356,12 +352,12 @@ struct Impl : sph_ctx_base {
         v.dt_wave = dt_wave;
         v.vol = vol;
         v.eos = eos;
-        // the first evaluation of a step scans the cells and writes the exact
-        // mask and the skin mask; the half-step evaluation walks the skin mask
-        // with the exact pair predicate
-        v.skin = half ? 1 : 0;
-        v.nmask = half ? smask : nmask;
-        v.nmask4 = half ? smask4 : nmask4;
+        // the first evaluation of a step scans the cells and writes the skin
+        // mask (pairs within R s); both evaluations walk it with the exact pair
+        // predicate
+        v.skin = 1;
+        v.nmask = smask;
+        v.nmask4 = smask4;
         v.smask = half ? nullptr : smask;
         v.smask4 = half ? nullptr : smask4;
         v.surf_region = surf_region;

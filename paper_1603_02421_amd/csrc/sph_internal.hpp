@@ -85,8 +85,8 @@ struct EvalView {
     V4<T>* eos;                 // (P / rho^2, colour, rho, m / rho), written by the colour sweep
     uint4* nmask;                // n: neighbour mask words of cell rows 0..3 (the mask the sweeps walk)
     uint32_t* nmask4;            // n: word of row 4 (+ overflow bit 31)
-    uint4* smask;                // n: skin mask (pairs within R s), written by the first colour sweep
-    uint32_t* smask4;
+    uint4* smask;                // n: where the first colour sweep writes the skin mask (pairs within
+    uint32_t* smask4;            //   R s); null in the half-step evaluation
     int skin;                    // 1: nmask is a skin mask, walkers apply the exact pair predicate
     int pad3_;
     uint32_t* cl_count;          // closure list (null when no system uses the closure)

@@ -523,11 +523,13 @@ template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 // follows from rho).
 //
 // The first evaluation of a step scans the cells. Its candidates within R s
-// (the cell block's radius) are recorded as the skin mask; those within 2h
-// enter the colour sum and the exact mask that the other sweeps walk. The
-// half-step evaluation (k_colour_skin) walks the skin mask instead of the
-// cells: the predictor keeps every particle within half the skin of its
-// step-start position, so every pair within 2h at the half step is in it.
+// (the cell block's radius) are recorded as the skin mask, and those within 2h
+// enter the colour sum. Every other sweep of the step walks the skin mask with
+// the exact pair predicate: the first evaluation's main and surface sweeps,
+// and the whole half-step evaluation (k_colour_skin first), since the predictor
+// keeps every particle within half the skin of its step-start position, so
+// every pair within 2h at the half step is in it. The walk visits the pairs
+// within 2h in the order a scan would.
 // Eight waves per SIMD (at most 64 VGPRs): the candidate scan is issue-bound
 // and hides its gathers best with the most waves (measured 5% faster than 7).
 
@@ -586,46 +588,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const T dens_a = v.dens[a];   // for the record written at the end
     const double R2 = S.R2;
     T wsum = 0;   // sum_b (m_b / rho_b) W_ab / wnorm
-    MaskBuilder E, Sk;   // exact mask (pairs within 2h) and skin mask (within R s)
+    MaskBuilder Sk;   // the skin mask: pairs within R s
     auto load = [&](uint32_t b) { return v.vol[b]; };
     auto acc = [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); };
-    auto row_end = [&](int r) {
-        E.row_end(r);
-        Sk.row_end(r);
-    };
+    auto row_end = [&](int r) { Sk.row_end(r); };
     if (S.reach == 1) {
         // 3 x 3 blocks (about 3.5 candidates per neighbour): first the pair
-        // predicates alone, recorded as the masks, then the kernel sum over the
-        // exact mask only, so lanes do not pay for each other's accepted
-        // candidates
+        // predicates alone, recorded as the mask, then the kernel sum over the
+        // mask, whose walk applies the exact predicate, so lanes do not pay for
+        // each other's rejected candidates
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
-                           [&](uint32_t, uint32_t k, T, T, double r2, int) {
-                               Sk.mark(k);
-                               if (r2 < R2) E.mark(k);
-                           },
-                           row_end, S.Rs2);
-        if (!E.overflow) mask_neighbours<T>(v, S, a, pa, E.M, load, acc);
+                           [&](uint32_t, uint32_t k, T, T, double, int) { Sk.mark(k); }, row_end, S.Rs2);
+        if (!Sk.overflow) mask_neighbours<T>(v, S, a, pa, Sk.M, load, acc);
         else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc);
     } else {
         // 5 x 5 blocks (about 2.2 candidates per neighbour): one pass
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
                            [&](uint32_t, uint32_t k, T, T, double r2, T vol_b) {
                                Sk.mark(k);
-                               if (r2 < R2) {
-                                   wsum += vol_b * kernel_shape(K, sqrt_((T)r2));
-                                   E.mark(k);
-                               }
+                               if (r2 < R2) wsum += vol_b * kernel_shape(K, sqrt_((T)r2));
                            },
                            row_end, S.Rs2);
     }
     colour_finish(v, S, a, vol_a, dens_a, wsum);
-    E.store(v.nmask, v.nmask4, a);
     Sk.store(v.smask, v.smask4, a);
 }
 
 // Sweep 1 of the half-step evaluation: the same colour sum over the skin mask
-// of the first evaluation (v.nmask with v.skin set), which the walk filters by
-// the exact predicate; the sweeps that follow walk the same skin mask.
+// of the first evaluation (v.nmask), which the walk filters by the exact
+// predicate; the sweeps that follow walk the same skin mask.
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_colour_skin(EvalView<T> v) {
     int sys;
@@ -1135,10 +1126,11 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     const int bs = L.block_sweep;
     const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
     const unsigned nb = nblk(max_waves, bs / 64);
-    if (v.skin) {
+    if (!v.smask) {
         kt->begin("colour_skin", st);
         k_colour_skin<T><<<nb, bs, 0, st>>>(v);
     } else {
+        // the first evaluation of a step: the cell scan that writes the mask
         kt->begin("colour", st);
         k_colour<T><<<nb, bs, 0, st>>>(v);
     }
