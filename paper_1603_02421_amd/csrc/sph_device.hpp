@@ -209,6 +209,25 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
+// Maximum of non-negative values over the wave: the unsigned maximum of the
+// bit patterns (the same order for non-negative numbers), one shuffle and one
+// integer max per step.
+__device__ __forceinline__ float wave_max_nonneg(float x) {
+    uint32_t u = __float_as_uint(x);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) u = max(u, (uint32_t)__shfl_xor((int)u, o, 64));
+    return __uint_as_float(u);
+}
+__device__ __forceinline__ double wave_max_nonneg(double x) {
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long q = __shfl_xor(u, o, 64);
+        u = q > u ? q : u;
+    }
+    return __longlong_as_double((long long)u);
+}
+
 // atomicMin on the bit pattern of a non-negative double, skipped when the
 // stored value is already no larger (values only decrease between the clears,
 // so a stale read can only cost an unneeded atomic): thousands of waves

@@ -656,7 +656,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     if (!wave_assign(v, sys, a, &chunk)) return;
     const SysDev<T>& S = v.sys[sys];
     const bool valid = a < v.sys_hi[sys];
-    double dtcv = __builtin_inf(), dtf = __builtin_inf();
+    // the arguments of this particle's dt terms: c_a + v_sig (eq. 31) and, when
+    // the sweep finishes the particle, |a| (eq. 30); 0 where there is none
+    T cvs = 0, amf = 0;
     bool surf = false;
     if (valid) {
         const bool fluid = tag_type(v.tag[a]) == T_FLUID;
@@ -712,7 +714,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         nrm.x = nx;
         nrm.y = ny;
         v.nrm[a] = nrm;
-        dtcv = (double)(h / (c_a + vsig));
+        cvs = c_a + vsig;
         const T mag = sqrt_(nx * nx + ny * ny);
         surf = fluid && mag > S.eps;
         if (fluid && !surf) {
@@ -720,7 +722,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             acc.x = ax + S.gx;
             acc.y = ay + S.gy;
             const T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
-            if (am > T(0)) dtf = sqrt((double)S.h / (double)am);
+            amf = am;
         } else {
             // filtered particles: k_surface adds the surface force and gravity
             acc.x = ax;
@@ -729,11 +731,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         v.acc[a] = acc;
     }
     if (v.do_dt) {
-        const double m_cv = wave_min(valid ? dtcv : __builtin_inf());
-        const double m_f = wave_min(valid && !surf ? dtf : __builtin_inf());
+        // h / (c + v_sig) and sqrt(h / |a|) fall as their arguments grow, after
+        // rounding too, so the wave's smallest terms are those of its largest
+        // arguments: one maximum each, then one division per wave (a NaN
+        // argument fails > 0 and drops out, as it would from a minimum)
+        const T m_cv = wave_max_nonneg(cvs > T(0) ? cvs : T(0));
+        const T m_f = wave_max_nonneg(amf > T(0) ? amf : T(0));
         if (__lane_id() == 0) {
-            v.dt_wave[2 * (size_t)chunk] = m_cv;
-            v.dt_wave[2 * (size_t)chunk + 1] = m_f;
+            const T h = S.h;
+            v.dt_wave[2 * (size_t)chunk] = m_cv > T(0) ? (double)(h / m_cv) : __builtin_inf();
+            v.dt_wave[2 * (size_t)chunk + 1] = m_f > T(0) ? sqrt((double)S.h / (double)m_f) : __builtin_inf();
         }
     }
     const unsigned long long bal = __ballot(surf);
