@@ -1,6 +1,6 @@
 """Throughput of the SPH particle update on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c5|c1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c2-cubic|c5|c1]
 
 Default workload: the batched Re/We sweep -- 64 independent tank-fed jets
 (Re log-uniform in [100, 2000], We uniform in [5, 50], D resolved by 10-40
@@ -141,9 +141,12 @@ def make_workload(name: str):
         desc = ("batched Re/We sweep: 64 tank-fed jets, Re logU[100,2000], We U[5,50], D/dx U{10..40}, "
                 "N logU[20k,400k] per jet, seed 1234, FP32, Wendland")
         return wl.Batch([wl.round_for_dtype(s, 32) for s in b.systems]), desc, 32
-    if name == "c2":
-        s = wl.round_for_dtype(wl.jet(n_target=300_000, nD=20, Re=500, We=20, kD=0.7, seed=0), 32)
-        return wl.Batch([s]), "single jet D=20dx, Re=500, We=20, kD=0.7, N~300k, FP32, Wendland", 32
+    if name in ("c2", "c2-cubic"):
+        cubic = name == "c2-cubic"
+        s = wl.round_for_dtype(wl.jet(n_target=300_000, nD=20, Re=500, We=20, kD=0.7, seed=0,
+                                      kernel=wl.CUBIC if cubic else wl.WENDLAND), 32)
+        return wl.Batch([s]), ("single jet D=20dx, Re=500, We=20, kD=0.7, N~300k, FP32, "
+                               + ("cubic spline" if cubic else "Wendland")), 32
     if name == "c5":
         s = wl.round_for_dtype(wl.jet(n_target=4_000_000, nD=80, Re=1000, We=30, seed=0,
                                       free_length=100.0, prefill=50.0), 32)
