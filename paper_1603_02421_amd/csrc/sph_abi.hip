@@ -819,6 +819,14 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
         return fail(c, SPH_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws) & 255) return fail(c, SPH_EINVAL, "workspace must be 256-byte aligned");
     m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream, with_closure);
+    if (with_closure) {
+        // the stencil kernel builds four stencils per wave once two per wave
+        // would more than fill the chip's wave slots (8 per SIMD, 4 SIMDs per CU)
+        int dev = 0, ncu = 0;
+        HIP_OK(hipGetDevice(&dev));
+        HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        m->cl.quad_min = 2u * 32u * (uint32_t)ncu;
+    }
     const int64_t n = c->n;
     hipStream_t st = c->stream;
     // host staging in device format

@@ -145,7 +145,7 @@ struct ClosureView {
     float* out;          // 4 per listed particle: n_x, n_y, kappa h, unused
     uint32_t* fallback;  // per slot: 1 where the plain curvature was used
     uint32_t capacity;
-    uint32_t pad_;
+    uint32_t quad_min;   // listed counts above this build four stencils per wave
 };
 
 // What the predictor and corrector read and write.

@@ -430,23 +430,18 @@ __device__ __forceinline__ RowMask closure_mask(const uint4* nmask, const uint32
     return M;
 }
 
-// One listed slot's stencil, built by a group of `width` lanes (32 or 64) of
-// the wave; `j` is the lane's index in the group and `lds` the group's 128
-// (width 64) or 32 (width 32) LDS slots. Every lane of the wave calls this
-// the same number of times (barriers); inactive groups pass active = false.
+// One listed slot's stencil, built by a group of `width` lanes (16, 32 or 64)
+// of the wave, each lane taking candidates j and j + width, so a group takes
+// at most 2 width of them; `a` is the slot, `M` its mask words, `j` the lane's
+// index in the group and `lds` the group's 2 width LDS slots. Every lane of the
+// wave calls this the same number of times (barriers); inactive groups pass
+// active = false.
 template <typename T>
 __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const ClosureView& C, uint32_t row, bool active,
-                                              int base, int width, int j, float* sx, float* sy, float* sd,
-                                              float* sa, uint32_t* sid, uint32_t* skeep) {
+                                              uint32_t a, const RowMask& M, int base, int width, int j, float* sx,
+                                              float* sy, float* sd, float* sa, uint32_t* sid, uint32_t* skeep) {
     const int l = __lane_id();
-    uint32_t a = 0;
-    RowMask M = {{0u, 0u, 0u, 0u, 0u}};
-    int total = 0;
-    if (active) {
-        a = C.list[row];
-        M = closure_mask(v.nmask, v.nmask4, a);
-        total = stencil_candidates(M);
-    }
+    const int total = active ? stencil_candidates(M) : 0;
     const bool overflow = (M.w[4] & MASK_OVERFLOW) != 0;
     float ix[2] = {0.f, 0.f}, iy[2] = {0.f, 0.f}, id2[2] = {0.f, 0.f}, ian[2] = {0.f, 0.f};
     uint32_t iid[2] = {0u, 0u};
@@ -469,7 +464,7 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             const int idx = j + width * it;
-            if (idx >= total || (width == 32 && it == 1)) continue;
+            if (idx >= total) continue;
             // the idx-th candidate: the idx-th set bit over the rows' words (its
             // row found from the words' bit counts, then one cell-start load),
             // or, after an overflow, the idx-th slot of the block
@@ -526,7 +521,7 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
         }
     }
     // compact the group's valid items into its LDS slots [0, k)
-    const unsigned long long gmask = width == 64 ? ~0ull : (0xFFFFFFFFull << base);
+    const unsigned long long gmask = width == 64 ? ~0ull : (((1ull << width) - 1ull) << base);
     const unsigned long long g0 = __ballot(val[0]) & gmask, g1 = __ballot(val[1]) & gmask;
     const int k0 = __popcll(g0), k = k0 + __popcll(g1);
     const unsigned long long below = (1ull << l) - 1ull;
@@ -593,29 +588,49 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
 // id), expressed in the frame e1 = n_a/|n_a| (eq. 18), e2 = e1 turned by +90
 // degrees, ordered by their angle in that frame in (-pi, pi] (ties: nearer,
 // then lower id; the cut at angle pi faces away from the liquid), zero-padded;
-// written as 64 BF16 values per row. A wave takes two listed particles, one
-// per half, when both have at most 32 candidates (the usual case on a free
-// surface), and otherwise builds them one after the other with all 64 lanes.
-// The kernel waits on chains of dependent loads: eight waves per SIMD (at most
-// 64 VGPRs, no spills) hide more of them than seven.
+// written as 64 BF16 values per row. On a long list a wave takes four listed
+// particles, one per 16 lanes, when each has at most 32 candidates (the usual
+// case on a free surface); otherwise, and on a short list, it takes them two
+// at a time, one per half, or one at a time with all 64 lanes. The kernel waits on chains of dependent loads: four
+// chains per wave and eight waves per SIMD (at most 64 VGPRs, no spills) keep
+// more of them in flight.
 template <typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) k_stencil(EvalView<T> v, ClosureView C) {
     __shared__ float sx[128], sy[128], sd[128], sa[128];
     __shared__ uint32_t sid[128], skeep[128];
     const int l = __lane_id();
     const uint32_t count = *C.count;
-    for (uint32_t pair = blockIdx.x; 2 * pair < count; pair += gridDim.x) {
-        const uint32_t r0 = 2 * pair, r1 = r0 + 1;
-        const uint32_t a0 = C.list[r0], a1 = r1 < count ? C.list[r1] : a0;
-        const int t0 = stencil_candidates(closure_mask(v.nmask, v.nmask4, a0));
-        const int t1 = r1 < count ? stencil_candidates(closure_mask(v.nmask, v.nmask4, a1)) : 0;
-        if (t0 <= 32 && t1 <= 32) {
-            const int g = l >> 5;
-            build_stencil<T>(v, C, g ? r1 : r0, g ? r1 < count : true, 32 * g, 32, l & 31, sx + 64 * g,
-                             sy + 64 * g, sd + 64 * g, sa + 64 * g, sid + 64 * g, skeep + 64 * g);
-        } else {
-            build_stencil<T>(v, C, r0, true, 0, 64, l, sx, sy, sd, sa, sid, skeep);
-            build_stencil<T>(v, C, r1, r1 < count, 0, 64, l, sx, sy, sd, sa, sid, skeep);
+    // four rows per wave only when two per wave would already more than fill
+    // the chip's wave slots; a short list keeps more waves at two rows each
+    const uint32_t per = count > C.quad_min ? 4u : 2u;
+    for (uint32_t q = blockIdx.x; per * q < count; q += gridDim.x) {
+        const uint32_t end = per * q + per < count ? per * q + per : count;
+        // rows r .. r + 64/width - 1, one per group of `width` lanes, each lane
+        // taking candidates j and j + width: a group of 16 or 32 lanes is used
+        // only when every one of its rows has at most 2 width candidates (a
+        // wave-uniform test, so no lane reaches a barrier alone)
+        uint32_t r = per * q;
+        int width = per == 4u ? 16 : 32;
+        while (r < end) {
+            const int g = l / width;
+            const uint32_t row = r + (uint32_t)g;
+            const bool active = row < end;
+            uint32_t a = 0;
+            RowMask M = {{0u, 0u, 0u, 0u, 0u}};
+            if (active) {
+                a = C.list[row];
+                M = closure_mask(v.nmask, v.nmask4, a);
+            }
+            if (width < 64 && __ballot(active && stencil_candidates(M) > 2 * width) != 0ull) {
+                width *= 2;
+                continue;
+            }
+            const int o = 2 * width * g;
+            build_stencil<T>(v, C, row, active, a, M, width * g, width, l - width * g, sx + o, sy + o, sd + o,
+                             sa + o, sid + o, skeep + o);
+            r += (uint32_t)(64 / width);
+            // after the first row of a pair built alone, its second alone too
+            width = width == 64 && ((r & 1u) != 0u) ? 64 : 32;
         }
     }
 }
