@@ -591,9 +591,10 @@ __device__ __forceinline__ void build_stencil(const EvalView<T>& v, const Closur
 // written as 64 BF16 values per row. On a long list a wave takes four listed
 // particles, one per 16 lanes, when each has at most 32 candidates (the usual
 // case on a free surface); otherwise, and on a short list, it takes them two
-// at a time, one per half, or one at a time with all 64 lanes. The kernel waits on chains of dependent loads: four
-// chains per wave and eight waves per SIMD (at most 64 VGPRs, no spills) keep
-// more of them in flight.
+// at a time, one per half (at most 64 candidates each), or one at a time with
+// all 64 lanes. The kernel waits on chains of dependent loads: four chains per
+// wave and eight waves per SIMD (at most 64 VGPRs, no spills) keep more of
+// them in flight.
 template <typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) k_stencil(EvalView<T> v, ClosureView C) {
     __shared__ float sx[128], sy[128], sd[128], sa[128];
