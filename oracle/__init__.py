@@ -10,6 +10,7 @@ or ``Batch`` (or raw arrays) and return plain numpy arrays.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -23,15 +24,36 @@ _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc the oracle source `src` into the shared library `out` (FP64, no FMA
+    contraction, OpenMP)."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-Wall", "-I", _HERE, "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    """Compile the C oracle with gcc into liborc.so beside its source."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
+
+
+@contextlib.contextmanager
+def using(path: str):
+    """Route every function of this module to the oracle library at `path`
+    for the duration of the block (the mutation tests load deliberately
+    broken copies of the oracle this way)."""
+    global _lib
+    saved = _lib
+    _lib = _declare(C.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 class Params(C.Structure):
@@ -64,26 +86,30 @@ def _params(d: Dict) -> Params:
     return p
 
 
+def _declare(L):
+    """Declare the C signatures of an oracle library handle."""
+    vp = C.c_void_p
+    L.orc_kernel_w.restype = C.c_double
+    L.orc_kernel_w.argtypes = [C.c_int, C.c_double, C.c_double]
+    L.orc_kernel_f.restype = C.c_double
+    L.orc_kernel_f.argtypes = [C.c_int, C.c_double, C.c_double]
+    L.orc_eos.argtypes = [vp, C.c_int64, vp, vp, vp]
+    L.orc_grid.argtypes = [vp, vp, vp]
+    L.orc_neighbors.restype = C.c_int64
+    L.orc_neighbors.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, vp, vp, C.c_int64]
+    L.orc_sort.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp]
+    L.orc_eval.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_step.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+    L.orc_threads.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = C.CDLL(_LIB)
-        vp = C.c_void_p
-        L.orc_kernel_w.restype = C.c_double
-        L.orc_kernel_w.argtypes = [C.c_int, C.c_double, C.c_double]
-        L.orc_kernel_f.restype = C.c_double
-        L.orc_kernel_f.argtypes = [C.c_int, C.c_double, C.c_double]
-        L.orc_eos.argtypes = [vp, C.c_int64, vp, vp, vp]
-        L.orc_grid.argtypes = [vp, vp, vp]
-        L.orc_neighbors.restype = C.c_int64
-        L.orc_neighbors.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, vp, vp, C.c_int64]
-        L.orc_sort.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp]
-        L.orc_eval.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.orc_step.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
-        L.orc_threads.restype = C.c_int
-        _lib = L
+        _lib = _declare(C.CDLL(_LIB))
     return _lib
 
 

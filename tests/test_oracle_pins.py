@@ -215,6 +215,110 @@ def test_artificial_viscosity_dissipates(orc):
     assert dE < 0.0
 
 
+def test_shear_wave_viscosity(orc):
+    """Magnitude of the artificial viscosity (eq. 10). For a shear wave
+    u_x = U sin(k y) at rho = rho0 (P = 0, so only Pi acts) a Taylor expansion of
+    eq. 9-10 about particle a gives a_x = nu u_x'' = -nu k^2 u_x with, for the term
+    applied to every pair, nu = alpha h c0 / 8 in 2-D: the lattice sum
+    sum_b m_b F r_x^2 r_y^2 / r^2 tends to rho0 int F r_x^2 r_y^2 / r^2 dA
+    = -rho0 / 4 by the gradient moment above. Eq. 10 acts only where
+    v_ab . r_ab < 0; in a shear that keeps, to leading order, exactly two of the
+    four quadrants of r_ab, and r_x^2 r_y^2 is even in each, so the switch halves
+    it: nu = alpha h c0 / 16. The eta^2 = 0.01 h^2 of the denominator lowers
+    that by the factor int F r^5 / (r^2 + eta^2) dr / int F r^3 dr (about 0.984,
+    by quadrature below). The oracle's a_x is fitted against -k^2 u_x in the
+    block interior; the fit must be exact in shape and its coefficient converge
+    to that continuum value as h/dx grows (lattice error at the paper's
+    h = 1.3 dx: 0.40 Wendland, 0.43 cubic, in units of alpha h c0 / 8). SI-like
+    units (dx = 0.01, rho0 = 1000) keep a missing factor h or an eta^2 taken in
+    place of eta^2 h^2 visible."""
+    def continuum(kernel):
+        h = 1.0
+        F = lambda r: orc.kernel_f(kernel, r, h)
+        num = _gl_integrate(lambda r: F(r) * r ** 5 / (r * r + 0.01 * h * h), 0, h, 100) + \
+            _gl_integrate(lambda r: F(r) * r ** 5 / (r * r + 0.01 * h * h), h, 2 * h, 100)
+        den = _gl_integrate(lambda r: F(r) * r ** 3, 0, h, 100) + _gl_integrate(lambda r: F(r) * r ** 3, h, 2 * h, 100)
+        return 0.5 * num / den
+
+    def nu_ratio(hf, kernel):
+        dx = 0.01
+        nx, ny = 60, 200
+        s = wl.lattice_block(nx, ny, dx=dx, kernel=kernel)
+        h = hf * dx
+        s.params.update(h=h, cell_size=2.2 * h, alpha=0.3, c0=10.0, sigma=0.0, gravity=(0.0, 0.0),
+                        rho0=1000.0)
+        s.rho[:] = 1000.0
+        s.mass[:] = 1000.0 * dx * dx
+        k, U = 2 * math.pi / (ny * dx), 0.05
+        s.vel[:, 0] = U * np.sin(k * s.pos[:, 1])
+        s.vel[:, 1] = 0.0
+        r = orc.evaluate(s)
+        inner = ((s.pos[:, 0] > 3 * h) & (s.pos[:, 0] < nx * dx - 3 * h) &
+                 (s.pos[:, 1] > 3 * h) & (s.pos[:, 1] < ny * dx - 3 * h))
+        f = -k * k * U * np.sin(k * s.pos[inner, 1])
+        ax = r["apv"][inner, 0]
+        nu = (ax * f).sum() / (f * f).sum()
+        assert np.abs(ax - nu * f).max() <= 1e-3 * np.abs(ax).max()   # exactly the shape -k^2 u_x
+        return nu / (0.3 * h * 10.0 / 8.0)
+
+    for kernel in (wl.WENDLAND, wl.CUBIC):
+        ratios = [nu_ratio(hf, kernel) for hf in (1.3, 2.0, 3.0)]
+        expect = continuum(kernel)
+        assert 0.49 < expect < 0.495
+        assert ratios[0] < ratios[1] < ratios[2]              # lattice error shrinks
+        assert abs(ratios[2] - expect) < 0.006
+        assert 0.38 < ratios[0] < 0.45                        # the paper's h = 1.3 dx
+
+
+@pytest.mark.parametrize("wall_fraction,rho_factor", [(0.0, 1.0), (0.25, 1.0), (0.0, 1.01)])
+def test_signal_term_uniform_compression(orc, wall_fraction, rho_factor):
+    """Eq. 31 in closed form. Under uniform compression v = -e (r - r_c) every
+    pair has v_ab = -e r_ab, so v_ab . r_ab / r_ab^2 = -e and
+    max_b |h v_ab . r_ab| / r_ab^2 = h e for every particle with a neighbour,
+    whatever the arrangement. At rho = rho0 (c_a = c0), alpha = 0 (P = 0 and
+    Pi = 0, so the only acceleration is g) the step of eq. 30-32 is
+    Cr min(sqrt(h/|g|), h/(c0 + h e)) exactly. At a uniform rho = 1.01 rho0 the
+    sound speed is c0 1.01^3 (eq. 26) and dt_cv = h/(c + h e); the pressure then
+    accelerates the particles, so only dt_cv has a closed form."""
+    s = wl.random_cloud(1500, extent=25.0, seed=3, wall_fraction=wall_fraction, sigma=0.0,
+                        gravity=(0.0, -0.1), alpha=0.0, rho_jitter=0.0)
+    e = 0.37
+    s.vel = -e * (s.pos - s.pos.mean(0))
+    s.rho[:] = rho_factor
+    r = orc.evaluate(s)
+    h, c0 = s.params["h"], s.params["c0"] * rho_factor ** 3
+    has = r["nnb"] > 0
+    assert has.sum() > 0.9 * s.n
+    assert np.allclose(r["vsig"][has], h * e, rtol=1e-12, atol=0)
+    assert np.all(r["vsig"][~has] == 0.0)
+    dt_cv = h / (c0 + h * e)
+    assert math.isclose(r["dt_cv"][0], dt_cv, rel_tol=1e-12)
+    if rho_factor != 1.0:
+        return
+    assert math.isclose(r["dt_f"][0], math.sqrt(h / 0.1), rel_tol=1e-12)
+    assert math.isclose(r["dt"][0], 0.2 * min(dt_cv, math.sqrt(h / 0.1)), rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("approach", [True, False])
+def test_viscosity_acts_on_approaching_pairs_only(orc, approach):
+    """Eq. 10 applies only where v_ab . r_ab < 0, i.e. to particles that close
+    in on each other. Two fluid particles at rho0 (P = 0, so eq. 9 reduces to the
+    viscous term) moving head-on are pushed apart along their line; moving
+    apart they feel no force at all."""
+    s = wl.lattice_block(2, 1, dx=1.0)
+    s.params.update(alpha=0.3, sigma=0.0, gravity=(0.0, 0.0))
+    u = 0.2 if approach else -0.2
+    s.vel[:] = [[u, 0.0], [-u, 0.0]]            # particle 0 sits left of particle 1
+    r = orc.evaluate(s)
+    a = r["apv"]
+    assert np.all(a[:, 1] == 0.0)
+    if approach:
+        assert a[0, 0] < 0.0 < a[1, 0]          # decelerated: each pushed back
+        assert a[0, 0] == -a[1, 0]
+    else:
+        assert np.all(a == 0.0)
+
+
 def test_uniform_translation_keeps_density(orc):
     s = wl.lattice_block(25, 25, vel=(0.3, -0.2))
     r = orc.evaluate(s)
@@ -356,6 +460,86 @@ def test_curvature_error_decreases_with_resolution(orc):
         outer = np.hypot(s.pos[:, 0], s.pos[:, 1]) > R - 1.0
         errs.append(abs(np.mean(r["kappa"][outer]) + 1.0 / R))
     assert errs[0] > errs[1] > errs[2]
+
+
+def _colour_jump_integral():
+    """The continuum value of the integral of |n| across a flat free surface,
+    for eq. 14 (C = sum_b V_b W_ab) and eq. 18 (n_a = sum_b V_b (C_b - C_a)
+    grad_a W_ab) of a single liquid phase. As sums become integrals over the
+    liquid region L, n = grad C~ - C grad C with C~ the kernel smoothing of C
+    restricted to L. Across a flat surface at y = 0 (liquid below), with w1 the
+    kernel's projection on y (any normalised symmetric kernel) and
+    S(u) = int_u^inf w1: C(-u) = 1 - S(u), C(0) = 1/2, C~(0) = int_0^inf
+    (1 - S) w1 du = 1/2 - 1/8 = 3/8, and int n_y dy = C~(0) - 1 - (C(0)^2 - 1)/2
+    = -1/4 (pointing into the liquid). The test below checks the same number by
+    quadrature of the projected Wendland kernel, independently of the oracle."""
+    u = np.linspace(0.0, 2.0, 4001)
+    # projected kernel w1(u) = int W(sqrt(u^2 + x^2)) dx for the unit-h Wendland kernel
+    x = np.linspace(-2.0, 2.0, 4001)
+    q = np.sqrt(u[:, None] ** 2 + x[None, :] ** 2)
+    W = np.where(q < 2.0, 7.0 / (4.0 * math.pi) * (1.0 - q / 2.0) ** 4 * (1.0 + 2.0 * q), 0.0)
+    w1 = np.trapezoid(W, x, axis=1)
+    S = np.array([np.trapezoid(w1[i:], u[i:]) for i in range(len(u))])
+    Ct0 = np.trapezoid((1.0 - S) * w1, u)
+    return Ct0 - 1.0 - ((0.5) ** 2 - 1.0) / 2.0
+
+
+def test_flat_surface_normal_integral(orc):
+    """Magnitude of the normal (eq. 18): sum_a V_a |n_a| per unit length of a flat
+    free surface tends to 1/4 (continuum value, see _colour_jump_integral) as
+    h/dx grows; at the paper's h = 1.3 dx the lattice gives 0.196 (Wendland).
+    The mass differs from the volume, so a mass taken for m_b/rho_b shows."""
+    assert abs(_colour_jump_integral() + 0.25) < 1e-4
+    vals = []
+    for hf in (1.3, 2.0, 3.5):
+        nx, ny = 80, 40
+        sl = wl.flat_slab(nx, ny, dx=1.0)
+        sl.params.update(h=hf, cell_size=2.2 * hf, rho0=1000.0)   # m = 1000, V = 1
+        sl.rho[:] = 1000.0
+        sl.mass[:] = 1000.0
+        r = orc.evaluate(sl)
+        mid = np.abs(sl.pos[:, 0] - nx / 2) < 10
+        top = sl.pos[:, 1] > -ny / 2
+        cols = (mid & np.isclose(sl.pos[:, 1], sl.pos[:, 1].max())).sum()
+        V = sl.mass / sl.rho
+        n = r["nrm"][mid & top]
+        assert np.all(n[:, 1] <= 1e-12)                       # into the liquid
+        vals.append((V[mid & top] * np.linalg.norm(n, axis=1)).sum() / cols)
+    assert vals[0] < vals[1] < vals[2]
+    assert abs(vals[2] - 0.25) < 0.01
+    assert abs(vals[0] - 0.196) < 0.005
+
+
+@pytest.mark.parametrize("kernel", [wl.WENDLAND, wl.CUBIC])
+def test_disc_surface_tension_magnitude(orc, kernel):
+    """Magnitude of the surface-tension force (eq. 24), in SI-like units
+    (rho0 = 1000, sigma = 0.072) so that a dropped 1/rho_a or a unit normal in
+    place of n shows. On a disc of radius R with its interface band
+    r > R - 4h: kappa = -1/R (eq. 23) and n points inward, so
+    sum_a m_a a_s . (-r_hat) = (sigma/R) sum_a V_a |n_a|, and sum_a V_a |n_a|
+    tends to 2 pi R / 4 (the flat value above). The inward force therefore tends
+    to 2 pi sigma / 4; the normal sum approaches its limit as R/h grows, the
+    force to within the O(h/R) error of the curvature."""
+    sigma = 0.072
+    got = []
+    for R in (32.0, 128.0):
+        d = wl.circle(R, dx=1.0, layout="rings", sigma=sigma, kernel=kernel)
+        d.params.update(rho0=1000.0, h=3.5, cell_size=2.2 * 3.5)
+        d.rho[:] = 1000.0
+        d.mass[:] = 1000.0
+        r = orc.evaluate(d)
+        rr = np.hypot(d.pos[:, 0], d.pos[:, 1])
+        band = rr > R - 4 * 3.5
+        rh = d.pos[band] / rr[band, None]
+        V = (d.mass / d.rho)[band]
+        nsum = (V * np.linalg.norm(r["nrm"][band], axis=1)).sum() / (2 * math.pi * R)
+        force = (d.mass[band, None] * r["asurf"][band] * (-rh)).sum() / (2 * math.pi * sigma)
+        assert np.all((r["asurf"][band] * rh).sum(1) <= 0.0)  # inward
+        got.append((nsum, force))
+    (n32, f32), (n128, f128) = got
+    assert abs(n128 - 0.25) < abs(n32 - 0.25)
+    assert abs(n128 - 0.25) < 0.01 and abs(n32 - 0.25) < 0.02
+    assert abs(f128 - 0.25) < 0.006 and abs(f32 - 0.25) < 0.01
 
 
 def test_lattice_disc_surface_force_inward(orc):

@@ -12,7 +12,9 @@ and B = rho0 c0^2 / gamma (eq. 26); Courant number 0.2 (eq. 32).
 
 The jets are nondimensional (rho0 = D = U = 1), with sigma = 1/We and the
 artificial-viscosity coefficient set from the kinematic viscosity nu = 1/Re by
-the 2-D relation nu = alpha h c0 / 8, so the momentum equation only ever sees
+nu = alpha h c0 / 16, the shear viscosity of eq. 10 in 2-D: the term applied to
+every pair would give alpha h c0 / 8, and eq. 10 acts on approaching pairs
+only, which in a shear is half of them. The momentum equation only ever sees
 alpha (eq. 9-10). The paper feeds its jet from a particle-filled tank (Section
 3-2); here that tank is driven by a piston so that the particle count stays
 fixed, the inflow carrying a 1 % sinusoidal perturbation.
@@ -204,12 +206,12 @@ def rest_tank(dx: float = 0.02, width: float = 0.4, depth: float = 0.3, wall_lay
 def jet_params(nD: int, Re: float, We: float, kD: float = 0.7, kernel: int = WENDLAND,
                mach_inv: float = 10.0) -> Dict:
     """Nondimensional jet parameters: dx = D/nD, h = 1.3 dx, c0 = 10 U, sigma = 1/We,
-    alpha from nu = 1/Re through nu = alpha h c0 / 8, g = 0."""
+    alpha from nu = 1/Re through nu = alpha h c0 / 16 (eq. 10 in a shear), g = 0."""
     dx = 1.0 / nD
     h = 1.3 * dx
     c0 = mach_inv
     nu = 1.0 / Re
-    alpha = 8.0 * nu / (h * c0)
+    alpha = 16.0 * nu / (h * c0)
     return default_params(h, 1.0, c0, kernel=kernel, alpha=alpha, sigma=1.0 / We,
                           gravity=(0.0, 0.0), piston_omega=kD)
 
