@@ -24,7 +24,8 @@
  *   - Host arrays passed in are read during the call and never retained; the
  *     caller keeps ownership. Device memory is never allocated by the library:
  *     the caller supplies one device workspace of sph_workspace_bytes() bytes
- *     and keeps it alive, unmoved, until sph_free().
+ *     and keeps it alive, unmoved, until sph_free() (sph_init_static instead
+ *     takes it from a static device array the library holds).
  *   - Particle arrays are FP64 on the host, in the caller's order; that order
  *     defines the particle id (0 .. n-1). 2-vectors are interleaved (x0, y0,
  *     x1, y1, ...). Systems are contiguous id ranges given by offsets[n_sys+1].
@@ -178,6 +179,27 @@ sph_status sph_init(const sph_options* opt, int32_t n_sys, const sph_params* p,
                     const int64_t* offsets, const double* pos, const double* vel,
                     const double* rho, const double* mass, const int32_t* type,
                     void* d_workspace, size_t ws_bytes, void* stream, sph_ctx** out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sph_init
+ * without a workspace argument. The context is carved from a static device
+ * array of SPH_STATIC_WORKSPACE_BYTES that the library holds on every device it
+ * runs on until the process ends; this call allocates no device memory (no
+ * hipMalloc, no graph instantiation: opt->use_graph is taken as 0, so
+ * sph_step launches its kernels directly and a caller may capture them).
+ *   Arguments as for sph_init, the stream's device being the current device.
+ *   One such context per device at a time: its state lives in that device's
+ *   array until sph_free; the array keeps the last context's contents, and
+ *   sph_init_static clears what must start at zero.
+ * Errors: those of sph_init; SPH_ENOMEM if the systems need more than
+ * SPH_STATIC_WORKSPACE_BYTES (sph_workspace_bytes with use_graph = 0 tells);
+ * SPH_ESTATE if a context created by this call is still alive on the device
+ * (two such contexts would share the array and race). */
+#define SPH_STATIC_WORKSPACE_BYTES (128u << 20)
+sph_status sph_init_static(const sph_options* opt, int32_t n_sys, const sph_params* p,
+                           const int64_t* offsets, const double* pos, const double* vel,
+                           const double* rho, const double* mass, const int32_t* type,
+                           void* stream, sph_ctx** out);
 
 /* Enqueue n_steps >= 0 predictor-corrector steps; returns after enqueueing. */
 sph_status sph_step(sph_ctx* ctx, int32_t n_steps);

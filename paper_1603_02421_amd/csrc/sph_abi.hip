@@ -8,6 +8,7 @@
 #include <map>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -173,6 +174,7 @@ struct sph_ctx {
     int (*read_fn)(sph_ctx*, int, void*, size_t) = nullptr;
     int (*nbr_fn)(sph_ctx*, int64_t*, int32_t*, int64_t, int64_t*) = nullptr;
     int (*closure_fn)(sph_ctx*, const float*) = nullptr;
+    int static_dev = -1;   // device whose static workspace this context holds (sph_init_static), else -1
 };
 
 // Trainer of the closure network (see sph_mlp_* in include/sph.h).
@@ -924,6 +926,29 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
 
 }  // namespace
 
+// ------------------------------------------------------------ static workspace
+// For callers that cannot allocate device memory: one context per device is
+// carved from this array instead of a caller's workspace. Host code never
+// passes the array's name to a kernel or a copy; it uses the device address
+// that hipGetSymbolAddress returns for the current device (each device holds
+// its own copy at its own address).
+
+static __device__ __align__(256) unsigned char scratch[SPH_STATIC_WORKSPACE_BYTES];
+
+namespace {
+std::mutex g_static_mu;
+std::map<int, void*> g_static_ptr;      // device -> address of its copy of `scratch`
+std::map<int, sph_ctx*> g_static_owner; // device -> the live context carved from it
+}  // namespace
+
+static void release_static(sph_ctx* c) {
+    if (c->static_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static_owner.find(c->static_dev);
+    if (it != g_static_owner.end() && it->second == c) g_static_owner.erase(it);
+    c->static_dev = -1;
+}
+
 // ------------------------------------------------------------ C-ABI
 
 extern "C" {
@@ -979,6 +1004,43 @@ sph_status sph_init(const sph_options* opt, int32_t n_sys, const sph_params* p, 
         return (sph_status)rc;
     }
     *out = ctx.release();
+    return SPH_OK;
+}
+
+sph_status sph_init_static(const sph_options* opt, int32_t n_sys, const sph_params* p, const int64_t* offsets,
+                           const double* pos, const double* vel, const double* rho, const double* mass,
+                           const int32_t* type, void* stream, sph_ctx** out) {
+    sph_ctx* c = nullptr;
+    if (!out) return fail(c, SPH_EINVAL, "out is NULL");
+    *out = nullptr;
+    sph_options o = resolve(opt);
+    o.use_graph = 0;   // instantiating a graph may allocate device memory
+    size_t need = 0;
+    sph_status st = sph_workspace_bytes(&o, n_sys, p, offsets, &need);
+    if (st != SPH_OK) return st;
+    if (need > (size_t)SPH_STATIC_WORKSPACE_BYTES)
+        return fail(c, SPH_ENOMEM, "these systems need " + std::to_string(need) + " bytes of workspace; the static "
+                                   "workspace holds " + std::to_string((size_t)SPH_STATIC_WORKSPACE_BYTES));
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_owner.count(dev))
+        return fail(c, SPH_ESTATE, "the static workspace of device " + std::to_string(dev) +
+                                   " is held by a live context; sph_free it first");
+    void* ptr = nullptr;
+    auto it = g_static_ptr.find(dev);
+    if (it == g_static_ptr.end()) {
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(c, SPH_EDEVICE, "hipGetSymbolAddress returned a null address");
+        g_static_ptr[dev] = ptr;
+    } else {
+        ptr = it->second;
+    }
+    st = sph_init(&o, n_sys, p, offsets, pos, vel, rho, mass, type, ptr, (size_t)SPH_STATIC_WORKSPACE_BYTES, stream,
+                  out);
+    if (st != SPH_OK) return st;
+    (*out)->static_dev = dev;
+    g_static_owner[dev] = *out;
     return SPH_OK;
 }
 
@@ -1236,6 +1298,7 @@ void sph_free(sph_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     c->impl.reset();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    release_static(c);
     delete c;
 }
 

@@ -23,10 +23,11 @@ FIELDS = {
     "fallback": 21,
 }
 MLP_NPARAMS = 8515
+STATIC_WORKSPACE_BYTES = 128 << 20   # SPH_STATIC_WORKSPACE_BYTES
 
 # Exported entry points, as declared in include/sph.h.
 EXPORTS = [
-    "sph_workspace_bytes", "sph_init", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
+    "sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
     "sph_sync", "sph_profile", "sph_autotune", "sph_free", "sph_last_error", "sph_abi_version",
     "sph_set_closure", "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
     "sph_mlp_train_step", "sph_mlp_params", "sph_mlp_free",
@@ -81,6 +82,7 @@ def load():
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     L.sph_workspace_bytes.argtypes = [vp, i32, vp, vp, C.POINTER(sz)]
     L.sph_init.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, C.POINTER(vp)]
+    L.sph_init_static.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
     L.sph_step.argtypes = [vp, i32]
     L.sph_evaluate.argtypes = [vp]
     L.sph_read.argtypes = [vp, i32, vp, sz]
@@ -102,7 +104,7 @@ def load():
     L.sph_last_error.argtypes = [vp]
     L.sph_last_error.restype = C.c_char_p
     L.sph_abi_version.restype = i32
-    for name in ("sph_workspace_bytes", "sph_init", "sph_step", "sph_evaluate", "sph_read",
+    for name in ("sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read",
                  "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune", "sph_set_closure",
                  "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
                  "sph_mlp_train_step", "sph_mlp_params"):

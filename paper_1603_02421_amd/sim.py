@@ -50,12 +50,13 @@ class Simulation:
 
     systems: a workloads System, Batch or list of Systems (params dicts plus FP64
     host arrays). Options map to sph_options (dtype_bits, block_sweep,
-    block_stream, use_graph, xcd_remap).
+    block_stream, use_graph, xcd_remap). static_workspace=True creates the
+    context with sph_init_static (no device allocation; one per device).
     """
 
     def __init__(self, systems, dtype_bits: int = 32, block_sweep: int = 0, block_stream: int = 0,
                  use_graph: int = -1, xcd_remap: int = -1, graph_steps: int = 0, cell_factor: float = 0.0,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, static_workspace: bool = False):
         import torch
 
         L = native.load()
@@ -76,19 +77,26 @@ class Simulation:
         opt.use_graph, opt.xcd_remap, opt.graph_steps = use_graph, xcd_remap, graph_steps
         self._opt = opt
         self.dtype_bits = dtype_bits
-        nbytes = C.c_size_t(0)
-        native.check(L.sph_workspace_bytes(C.byref(opt), self.n_sys, P, _ptr(off), C.byref(nbytes)))
-        self.workspace_bytes = int(nbytes.value)
         self.device = torch.device(device)
-        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         handle = C.c_void_p(stream.cuda_stream)
         ctx = C.c_void_p()
-        native.check(L.sph_init(C.byref(opt), self.n_sys, P, _ptr(off), _ptr(pos), _ptr(vel), _ptr(rho),
-                                _ptr(mass), _ptr(typ), C.c_void_p(self.workspace.data_ptr()),
-                                self.workspace_bytes, handle, C.byref(ctx)))
+        if static_workspace:
+            self.workspace_bytes = native.STATIC_WORKSPACE_BYTES
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                native.check(L.sph_init_static(C.byref(opt), self.n_sys, P, _ptr(off), _ptr(pos), _ptr(vel),
+                                               _ptr(rho), _ptr(mass), _ptr(typ), handle, C.byref(ctx)))
+        else:
+            nbytes = C.c_size_t(0)
+            native.check(L.sph_workspace_bytes(C.byref(opt), self.n_sys, P, _ptr(off), C.byref(nbytes)))
+            self.workspace_bytes = int(nbytes.value)
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            native.check(L.sph_init(C.byref(opt), self.n_sys, P, _ptr(off), _ptr(pos), _ptr(vel), _ptr(rho),
+                                    _ptr(mass), _ptr(typ), C.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace_bytes, handle, C.byref(ctx)))
         self._ctx = ctx
 
     # -- stepping -------------------------------------------------------

@@ -110,3 +110,21 @@ def test_trainer_workspace_and_argument_checks_without_the_gpu():
     assert L.sph_mlp_train_step(None, None, None, 16, C.c_float(1e-3), None) == -1
     assert L.sph_mlp_forward(None, None, 16, None) == -1
     assert "bad arguments" in L.sph_last_error(None).decode()
+
+
+def test_static_init_rejects_systems_beyond_its_array_without_the_gpu():
+    """sph_init_static checks the workspace the systems need against
+    SPH_STATIC_WORKSPACE_BYTES on the host, before any device call."""
+    from paper_1603_02421_amd import native
+    L = native.load()
+    s = wl.lattice_block(1500, 1000)            # 1.5M particles: several hundred MB
+    P = (native.SphParams * 1)()
+    P[0] = native.params_struct(s.params)
+    off = np.array([0, s.n], dtype=np.int64)
+    arrs = [np.ascontiguousarray(a) for a in (s.pos, s.vel, s.rho, s.mass, s.type.astype(np.int32))]
+    out = C.c_void_p()
+    st = L.sph_init_static(None, 1, P, off.ctypes.data_as(C.c_void_p),
+                           *[a.ctypes.data_as(C.c_void_p) for a in arrs], None, C.byref(out))
+    assert st == native.SPH_ENOMEM
+    assert b"static workspace holds" in L.sph_last_error(None)
+    assert out.value is None
