@@ -33,13 +33,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per active particle and launch, FP32 storage: every
-# per-slot array the kernel needs read once and every output written once
-# (neighbour re-reads are the reuse the cell order provides and are not
-# counted). Layout: pos 16 (FP64 pair), vel 8, dens 4, mass 4, tag 4, id 4,
-# cell 4, colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, c,
-# rho, m/rho), neighbour mask 20 (one word per cell row).
-ALGO_BYTES = {
+# Algorithmic bytes of the method per active particle, FP32, 2-D: each field
+# the step needs, counted once per sweep that needs it (neighbour re-reads are
+# the reuse the cell order provides and are not counted). Colour sweep: pos 8,
+# rho 4, type 4 -> C 4. Main sweep: pos 8, v 8, rho 4, type 4, C 4 -> drho/dt 4,
+# a 8, n 8. Surface sweep: pos 8, rho 4, type 4, n 8, a 8 -> a 8. Predictor and
+# corrector: state 20 + derivatives 12 -> state 20, each. Neighbour structure
+# once per step: key 8 + 4, histogram 4, scan 1.2, scatter 8, permute 2 x 24.
+# Per step, with two evaluations: 2 x (20 + 48 + 40) + 104 + 73 = 393, used as
+# 400 B per particle-step.
+METHOD_BYTES = {"colour": 20, "colour_skin": 20, "main": 48, "surface": 40, "predict": 52, "correct": 52}
+METHOD_BYTES_PER_STEP = 400
+
+# This implementation's own bytes per active particle and launch, FP32
+# storage: every per-slot array the kernel reads once and every output written
+# once. Layout: pos 16 (FP64 pair), vel 8, dens 4, mass 4, tag 4, id 4, cell 4,
+# colour 4, drho 4, acc 8, nrm 8, kappa 4, vol 4, eos 16 (P/rho^2, C, rho,
+# m/rho), neighbour mask 20 (one word per cell row).
+IMPL_BYTES = {
     "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20,               # pos vol cell tag dens -> colour eos skin-mask
     "colour_skin": 16 + 4 + 4 + 4 + 20 + 4 + 16,          # pos vol cell dens skin-mask -> colour eos
     "main": 4 + 16 + 8 + 16 + 20 + 4 + 4 + 8 + 8,         # tag pos vel eos mask cell -> drho acc nrm
@@ -156,27 +167,40 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(batch, target_s: float = 15.0):
-    """Oracle particle-steps/s on a bounded sample: whole jets of the workload
-    (smallest first) stepped on the host cores."""
+def cpu_baseline(batch, n_jets: int = 4, steps: int = 20):
+    """Oracle particle-steps/s on a bounded sample of the workload: n_jets of its
+    jets, at the 1/8, 3/8, 5/8 and 7/8 quantiles of size, each stepped `steps`
+    times on all host cores, then the same on one core."""
     import oracle
     import workloads as wl
     oracle.build(force=False)
     systems = sorted(batch.systems, key=lambda s: s.n)
-    pick = systems[len(systems) // 2]   # a median-size jet
-    st = oracle.State(pick)
-    t0 = time.perf_counter()
-    st.step(1)
-    one = time.perf_counter() - t0
-    k = max(1, min(1000, int(target_s / max(one, 1e-6))))
-    n0 = int((st.type != wl.INACTIVE).sum())
-    t0 = time.perf_counter()
-    st.step(k)
-    el = time.perf_counter() - t0
-    n1 = int((st.type != wl.INACTIVE).sum())
-    return dict(value=(k * 0.5 * (n0 + n1)) / el, unit="particle-steps/s", cores=oracle.threads(),
-                kind="oracle", sample=f"one jet of the batch (N={pick.n}, median size), {k} steps after 1 warm-up "
-                                       f"step, FP64 C oracle with OpenMP, {el:.1f} s")
+    k = len(systems)
+    picks = [systems[min(k - 1, int((2 * i + 1) * k / (2 * n_jets)))] for i in range(n_jets)] if k > n_jets \
+        else systems
+    all_cores = oracle.threads()
+
+    def run(threads):
+        oracle.set_threads(threads)
+        total, el = 0.0, 0.0
+        for sy in picks:
+            st = oracle.State(sy)
+            n0 = int((st.type != wl.INACTIVE).sum())
+            t0 = time.perf_counter()
+            st.step(steps)
+            el += time.perf_counter() - t0
+            total += steps * 0.5 * (n0 + int((st.type != wl.INACTIVE).sum()))
+        return total / el, el
+
+    v_all, t_all = run(all_cores)
+    v_one, t_one = run(1)
+    oracle.set_threads(all_cores)
+    sizes = ", ".join(str(sy.n) for sy in picks)
+    return dict(value=v_all, unit="particle-steps/s", cores=all_cores, kind="oracle",
+                sample=f"{len(picks)} jets of the workload (N = {sizes}; the 1/8, 3/8, 5/8, 7/8 size quantiles), "
+                       f"{steps} steps each, FP64 C oracle with OpenMP: {t_all:.1f} s on {all_cores} threads, "
+                       f"{t_one:.1f} s on 1",
+                single_core=dict(value=v_one, cores=1))
 
 
 def closure_leg(sph, batch, bits, block_sweep, cell_factor, args):
@@ -300,14 +324,14 @@ def main():
     prof = sim.profile(args.profile_steps)
     n_act = int(sim.read("nactive", allow_unstable=True).sum())
     step_ms = sum(v["avg_ms"] * v["calls"] for v in prof.values()) / max(args.profile_steps, 1)
-    dom = max((k for k in prof if k in ALGO_BYTES), key=lambda k: prof[k]["avg_ms"] * prof[k]["calls"])
+    dom = max((k for k in prof if k in METHOD_BYTES), key=lambda k: prof[k]["avg_ms"] * prof[k]["calls"])
     avg = prof[dom]["avg_ms"]
-    bytes_launch = ALGO_BYTES[dom] * n_act
+    bytes_launch = METHOD_BYTES[dom] * n_act
     achieved = bytes_launch / (avg * 1e-3) / 1e9
     kernels = {k: dict(avg_ms=round(v["avg_ms"], 4), calls=v["calls"],
                        share=round(v["avg_ms"] * v["calls"] / args.profile_steps / step_ms, 4))
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"])}
-    step_bytes = sum(ALGO_BYTES.get(k, 0) * v["calls"] for k, v in prof.items()) / args.profile_steps
+    impl_step_bytes = sum(IMPL_BYTES.get(k, 0) * v["calls"] for k, v in prof.items()) / args.profile_steps
     traffic_bytes, traffic_launch = measured_traffic(args.workload, cell_factor, block_sweep, dom)
     out = {
         "metric": "particle-steps/s (plain vs learned closure, batched jets); % HBM roofline",
@@ -328,9 +352,13 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_bytes, "traffic_launch": traffic_launch,
-                     "algo_bytes_per_particle": ALGO_BYTES[dom], "avg_launch_ms": avg},
-        "step_model": {"algo_bytes_per_particle_step": step_bytes,
-                       "hbm_frac": step_bytes * value / (HBM_PEAK_GBS * 1e9)},
+                     "algo_bytes_per_particle": METHOD_BYTES[dom], "avg_launch_ms": avg,
+                     "impl_bytes_per_particle": IMPL_BYTES[dom],
+                     "impl_frac": IMPL_BYTES[dom] * n_act / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "step_model": {"algo_bytes_per_particle_step": METHOD_BYTES_PER_STEP,
+                       "hbm_frac": METHOD_BYTES_PER_STEP * value / (HBM_PEAK_GBS * 1e9),
+                       "impl_bytes_per_particle_step": impl_step_bytes,
+                       "impl_hbm_frac": impl_step_bytes * value / (HBM_PEAK_GBS * 1e9)},
         "kernels": kernels,
     }
     sim.close()

@@ -101,6 +101,8 @@ def _declare(L):
     L.orc_eval.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
     L.orc_step.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
     L.orc_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = None
     return L
 
 
@@ -227,3 +229,8 @@ class State:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads for the following oracle calls."""
+    lib().orc_set_threads(int(n))

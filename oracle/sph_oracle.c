@@ -47,6 +47,14 @@ int orc_threads(void) {
 #endif
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- kernels */
 
 /* Cubic spline, eq. 27: W = (10/(7 pi h^2)) f(q); Wendland, eq. 28:

@@ -95,8 +95,9 @@ int orc_step(int n_sys, const orc_params* p, const int64_t* off, double* pos, do
              double* rho, const double* mass, int32_t* type, double* time, int nsteps,
              double* dt_out);
 
-/* Number of OpenMP threads the oracle runs on. */
+/* Number of OpenMP threads the oracle runs on, and a way to change it. */
 int orc_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
