@@ -56,8 +56,9 @@ typedef enum {
     SPH_ENOMEM = -2,     /* workspace smaller than sph_workspace_bytes() */
     SPH_EDEVICE = -3,    /* a HIP runtime call failed (message in sph_last_error) */
     SPH_EUNSTABLE = -4,  /* the device flagged a non-finite value, a density outside
-                            [rho0/2, 2 rho0], or a particle that moved farther than the
-                            cell skin within half a step; data was still copied out */
+                            [rho0/2, 2 rho0], or a particle that moved farther within
+                            half a step than the widest rescan covers (see cell_size);
+                            data was still copied out */
     SPH_ECAPACITY = -5,  /* output buffer too small (sph_neighbors) */
     SPH_ESTATE = -6      /* call not valid in the context's current state */
 } sph_status;
@@ -95,8 +96,13 @@ typedef struct sph_params {
     double box_hi[2];      /*   the box also spans the cell grid */
     double cell_size;      /* cell edge s; must exceed h (reach 2) or 2h (reach 1).
                               The neighbour search scans (2R+1)^2 cells, R = 1 if
-                              s > 2h else 2, and needs particles to move less than
-                              (R s - 2h)/2 in half a step (checked, SPH_EUNSTABLE) */
+                              s > 2h else 2, and the half step reuses the pairs
+                              within R s found at the step's start while no particle
+                              moves more than (R s - 2h)/2 in half a step. A system
+                              in which one does scans its cells again for the half
+                              step, with the reach that covers the largest
+                              displacement (exact; FLAGS bit 8); beyond a reach of
+                              6 cells pairs may be missed (FLAGS bit 4, SPH_EUNSTABLE) */
     double piston_dir[2];  /* unit direction of the piston's motion */
     double piston_u;       /* piston speed U: U (1 + piston_amp sin(piston_omega t)) */
     double piston_amp;
@@ -151,14 +157,17 @@ enum {
     SPH_F_NACTIVE = 14,   /* n_sys, int64 */
     SPH_F_SORT_KEYS = 15, /* n, uint64, cell key of each slot of the sorted arrays */
     SPH_F_SORT_PERM = 16, /* n, int64, particle id held by each slot of the sorted arrays */
-    SPH_F_FLAGS = 17,     /* 1, int32, instability bits (1 non-finite, 2 density, 4 skin) */
+    SPH_F_FLAGS = 17,     /* 1, int32, instability bits (1 non-finite, 2 density, 4 a half-step
+                             displacement beyond the widest rescan) and 8, informational: some
+                             half step was rescanned (see cell_size); sticky until sph_restore */
     SPH_F_CURV_PLAIN = 18,/* n, curvature of eq. 23 (equals CURV unless the closure is on) */
     SPH_F_STENCIL = 19,   /* n x 64, closure input of every particle the closure saw at the last
                              evaluation (BF16 values as FP64), zeros elsewhere */
     SPH_F_CLOSURE = 20,   /* n x 4, network output (n_1, n_2, kappa h, 1) of those particles,
                              zeros elsewhere (the last entry marks the listed particles) */
     SPH_F_FALLBACK = 21,  /* n, int32, 1 where the plain curvature replaced the network's */
-    SPH_F_COUNT = 22
+    SPH_F_ALL_STATE = 22, /* sph_state_bytes() bytes: the checkpoint blob (see sph_restore) */
+    SPH_F_COUNT = 23
 };
 
 /* Bytes of device workspace a context with these systems needs.
@@ -213,11 +222,32 @@ sph_status sph_evaluate(sph_ctx* ctx);
  * Returns SPH_EUNSTABLE, after copying, if the device raised an instability flag. */
 sph_status sph_read(sph_ctx* ctx, int32_t field, void* host_dst, size_t bytes);
 
-/* Neighbour lists at the current state (waits for the stream): for every
- * particle id a, the ids b != a of its system with |r_a - r_b|^2 < (2h)^2,
- * ascending. start: n + 1 int64; nbr: cap int32. *total receives the number of
- * pairs; SPH_ECAPACITY (start still filled) if cap < *total. Debug path: uses
- * its own kernels and the sorted arrays of the last sort. */
+/* Checkpoint and resume. The state of Section 2-2 (position, velocity,
+ * density and mass of every particle) plus each system's time and last dt --
+ * everything a step starts from, the piston's phase being its time -- as one
+ * blob: sph_read(ctx, SPH_F_ALL_STATE, buf, sph_state_bytes) fills it, and
+ * sph_restore loads it into a context, which may be a different one with the
+ * same dtype, system count and particle count (for example one created with a
+ * smaller Courant number to recover from SPH_EUNSTABLE). The blob holds the
+ * stored values themselves (positions FP64; velocity, rho - rho0 and mass in
+ * the context's dtype; types), in particle-id order, after a small header, so a
+ * restored context continues bit for bit as the one it was read from. Derived
+ * fields (DRHODT .. CURV) read zero until the next sph_step or sph_evaluate;
+ * instability flags are cleared.
+ * sph_state_bytes: *bytes_out = size of the blob of this context.
+ * sph_restore: waits for the stream; SPH_EINVAL if bytes differs from
+ * sph_state_bytes or the header does not match this context. */
+sph_status sph_state_bytes(const sph_ctx* ctx, size_t* bytes_out);
+sph_status sph_restore(sph_ctx* ctx, const void* state, size_t bytes);
+
+/* Neighbour lists at the current state (Section 2-7; waits for the stream):
+ * for every particle id a, the ids b != a of its system with
+ * |r_a - r_b|^2 < (2h)^2, ascending. start: n + 1 int64; nbr: cap int32.
+ * *total receives the number of pairs; SPH_ECAPACITY (start still filled) if
+ * cap < *total. These are the pairs the sweeps visit: the call sorts the
+ * current state into cells (as sph_evaluate does), runs the colour sweep that
+ * records each particle's candidate mask, and walks those masks as the main
+ * and surface sweeps do, with the exact pair predicate. */
 sph_status sph_neighbors(sph_ctx* ctx, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total);
 
 /* Wait for all enqueued work. */

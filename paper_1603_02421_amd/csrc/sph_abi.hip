@@ -174,6 +174,7 @@ struct sph_ctx {
     int (*read_fn)(sph_ctx*, int, void*, size_t) = nullptr;
     int (*nbr_fn)(sph_ctx*, int64_t*, int32_t*, int64_t, int64_t*) = nullptr;
     int (*closure_fn)(sph_ctx*, const float*) = nullptr;
+    int (*restore_fn)(sph_ctx*, const void*, size_t) = nullptr;
     int static_dev = -1;   // device whose static workspace this context holds (sph_init_static), else -1
 };
 
@@ -231,6 +232,7 @@ struct Impl : sph_ctx_base {
     SortBufs sb{};
     unsigned long long* dtmin = nullptr;
     double* dt_wave = nullptr;
+    unsigned long long* skin_max = nullptr;
     double* dt = nullptr;
     double* time = nullptr;
     uint32_t* flags = nullptr;
@@ -318,6 +320,7 @@ struct Impl : sph_ctx_base {
         sb.chunk_base = cv.take<uint32_t>(n_sys_ + 1);
         dtmin = cv.take<unsigned long long>(2 * n_sys_);
         dt_wave = cv.take<double>(2 * surface_chunks(n_, n_sys_));
+        skin_max = cv.take<unsigned long long>(n_sys_ + 1);
         dt = cv.take<double>(n_sys_);
         time = cv.take<double>(n_sys_);
         flags = cv.take<uint32_t>(4);
@@ -370,6 +373,8 @@ struct Impl : sph_ctx_base {
             v.cl_list = cl.list;
             v.cl_capacity = cl.capacity;
         }
+        v.skin_max = half ? skin_max : nullptr;
+        v.flags = flags;
         return v;
     }
 
@@ -385,6 +390,7 @@ struct Impl : sph_ctx_base {
         const StateBuf<T>& S = buf[cur];
         IntegView<T> v{};
         v.n = n;
+        v.n_sys = n_sys;
         v.sys = sys;
         v.pos = S.pos;
         v.vel = S.vel;
@@ -401,6 +407,7 @@ struct Impl : sph_ctx_base {
         v.mass = S.mass;
         v.vol = vol;
         v.surf_count = surf_count;
+        v.skin_max = skin_max;
         return v;
     }
 
@@ -414,7 +421,7 @@ struct Impl : sph_ctx_base {
     void step(hipStream_t st, KernelTimer* kt) {
         sort(st, kt);
         evaluate(false, true, st, kt);
-        launch_dt<T>(n_sys, sys, sb.chunk_base, dt_wave, dtmin, dt, st, kt);
+        launch_dt<T>(n_sys, sys, sb.chunk_base, dt_wave, dtmin, dt, skin_max, st, kt);
         launch_predict<T>(L, integ_view(), st, kt);
         evaluate(true, false, st, kt);
         launch_correct<T>(L, integ_view(), n_sys, dt, time, st, kt);
@@ -448,7 +455,8 @@ int evaluate_impl(sph_ctx* c) {
     Impl<T>* m = impl_of<T>(c);
     m->sort(c->stream, &c->timer);
     m->evaluate(false, true, c->stream, &c->timer);
-    launch_dt<T>(m->n_sys, m->sys, m->sb.chunk_base, m->dt_wave, m->dtmin, m->dt, c->stream, &c->timer);
+    launch_dt<T>(m->n_sys, m->sys, m->sb.chunk_base, m->dt_wave, m->dtmin, m->dt, m->skin_max, c->stream,
+                 &c->timer);
     HIP_OK(hipGetLastError());
     return SPH_OK;
 }
@@ -472,6 +480,24 @@ void unpermute(const std::vector<uint32_t>& ids, const SRC* src, int comps, doub
         for (int k = 0; k < comps; ++k) dst[(size_t)ids[j] * comps + k] = (double)src[j * comps + k];
 }
 
+// The checkpoint blob of sph_read(SPH_F_ALL_STATE) and sph_restore: a header,
+// then per system time and dt (FP64), then per particle in id order the stored
+// values themselves: position (2 FP64), velocity (2 T), rho - rho0 (T), mass
+// (T) and type (int32). Restoring these bits restores the state bit for bit.
+struct StateHeader {
+    uint32_t magic;        // 'SPHS'
+    uint32_t version;
+    uint32_t dtype_bits;
+    uint32_t n_sys;
+    uint64_t n;
+};
+constexpr uint32_t STATE_MAGIC = 0x53485053u;
+
+template <typename T>
+size_t state_bytes(int64_t n, int n_sys) {
+    return sizeof(StateHeader) + (size_t)n_sys * 16 + (size_t)n * (16 + 2 * sizeof(T) + 2 * sizeof(T) + 4);
+}
+
 template <typename T>
 int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
     Impl<T>* m = impl_of<T>(c);
@@ -486,6 +512,7 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
         case SPH_F_CURV: case SPH_F_CURV_PLAIN: case SPH_F_SORT_KEYS: case SPH_F_SORT_PERM:
             want = (size_t)n * 8; break;
         case SPH_F_TYPE: case SPH_F_NFLAG: case SPH_F_FALLBACK: want = (size_t)n * 4; break;
+        case SPH_F_ALL_STATE: want = state_bytes<T>(n, ns); break;
         case SPH_F_STENCIL: want = (size_t)n * 64 * 8; break;
         case SPH_F_CLOSURE: want = (size_t)n * 4 * 8; break;
         case SPH_F_DT: case SPH_F_TIME: case SPH_F_NACTIVE: want = (size_t)ns * 8; break;
@@ -613,6 +640,37 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
             HIP_OK(fetch(m->flags, 4, tmp));
             memcpy(host, tmp.data(), 4);
             break;
+        case SPH_F_ALL_STATE: {
+            char* o = static_cast<char*>(host);
+            StateHeader hd{STATE_MAGIC, 1u, (uint32_t)(8 * sizeof(T)), (uint32_t)ns, (uint64_t)n};
+            memcpy(o, &hd, sizeof hd);
+            o += sizeof hd;
+            HIP_OK(fetch(m->time, ns * 8, tmp));
+            memcpy(o, tmp.data(), ns * 8);
+            o += ns * 8;
+            HIP_OK(fetch(m->dt, ns * 8, tmp));
+            memcpy(o, tmp.data(), ns * 8);
+            o += ns * 8;
+            // each per-slot array moved to id order as raw bytes
+            auto raw = [&](const void* dev, size_t elem) -> hipError_t {
+                hipError_t e = fetch(dev, (size_t)n * elem, tmp);
+                if (e != hipSuccess) return e;
+                for (int64_t j = 0; j < n; ++j) memcpy(o + (size_t)ids[j] * elem, tmp.data() + (size_t)j * elem, elem);
+                o += (size_t)n * elem;
+                return hipSuccess;
+            };
+            HIP_OK(raw(S.pos, 16));
+            HIP_OK(raw(S.vel, 2 * sizeof(T)));
+            HIP_OK(raw(S.dens, sizeof(T)));
+            HIP_OK(raw(S.mass, sizeof(T)));
+            HIP_OK(fetch(S.tag, n * 4, tmp));
+            const uint32_t* tg = reinterpret_cast<const uint32_t*>(tmp.data());
+            for (int64_t j = 0; j < n; ++j) {
+                const int32_t ty = (int32_t)(tg[j] & 15u);
+                memcpy(o + (size_t)ids[j] * 4, &ty, 4);
+            }
+            break;
+        }
         case SPH_F_STENCIL: case SPH_F_CLOSURE: case SPH_F_FALLBACK: {
             memset(host, 0, bytes);
             if (!m->closure) break;
@@ -656,7 +714,7 @@ int read_impl(sph_ctx* c, int field, void* host, size_t bytes) {
     uint32_t fl = 0;
     HIP_OK(hipMemcpyAsync(&fl, m->flags, 4, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    if (fl) return fail(c, SPH_EUNSTABLE, "instability flags " + std::to_string(fl));
+    if (fl & ~FLAG_RESCAN) return fail(c, SPH_EUNSTABLE, "instability flags " + std::to_string(fl));
     return SPH_OK;
 }
 
@@ -665,6 +723,9 @@ int nbr_impl(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* tot
     Impl<T>* m = impl_of<T>(c);
     const int n = m->n;
     hipStream_t st = c->stream;
+    // the current state sorted, and the skin mask the sweeps walk recorded
+    m->sort(st, &c->timer);
+    launch_colour_mask<T>(m->L, m->eval_view(false, false), st);
     EvalView<T> v = m->eval_view(false, false);
     uint32_t* cnt = m->sb.scratch;
     launch_nbr_count<T>(m->L, v, cnt, st);
@@ -720,6 +781,67 @@ int closure_impl(sph_ctx* c, const float* params) {
 }
 
 template <typename T>
+int restore_impl(sph_ctx* c, const void* blob, size_t bytes) {
+    Impl<T>* m = impl_of<T>(c);
+    const int64_t n = m->n;
+    const int ns = m->n_sys;
+    if (bytes != state_bytes<T>(n, ns))
+        return fail(c, SPH_EINVAL, "state blob needs " + std::to_string(state_bytes<T>(n, ns)) + " bytes");
+    const char* in = static_cast<const char*>(blob);
+    StateHeader hd;
+    memcpy(&hd, in, sizeof hd);
+    if (hd.magic != STATE_MAGIC || hd.version != 1u)
+        return fail(c, SPH_EINVAL, "not a state blob of this library");
+    if (hd.dtype_bits != 8 * sizeof(T) || hd.n_sys != (uint32_t)ns || hd.n != (uint64_t)n)
+        return fail(c, SPH_EINVAL, "state blob of another shape (dtype, systems or particle count)");
+    in += sizeof hd;
+    const double* time = reinterpret_cast<const double*>(in);
+    const double* dt = time + ns;
+    in += (size_t)ns * 16;
+    const char* pos = in;
+    const char* vel = pos + (size_t)n * 16;
+    const char* dens = vel + (size_t)n * 2 * sizeof(T);
+    const char* mass = dens + (size_t)n * sizeof(T);
+    const char* type = mass + (size_t)n * sizeof(T);
+    std::vector<uint32_t> tag(n), id(n);
+    for (int s = 0; s < ns; ++s) {
+        if (!(time[s] >= 0.0) || !(dt[s] >= 0.0)) return fail(c, SPH_EINVAL, "state blob holds a bad time or dt");
+        for (int64_t a = c->offsets[s]; a < c->offsets[s + 1]; ++a) {
+            int32_t ty;
+            memcpy(&ty, type + (size_t)a * 4, 4);
+            if (ty < SPH_FLUID || ty > SPH_INACTIVE)
+                return fail(c, SPH_EINVAL, "particle type out of range at id " + std::to_string(a));
+            tag[a] = ((uint32_t)s << 4) | (uint32_t)ty;
+            id[a] = (uint32_t)a;
+        }
+    }
+    hipStream_t st = c->stream;
+    HIP_OK(hipStreamSynchronize(st));
+    // the blob's arrays are in id order: slot a holds particle a until the sort
+    StateBuf<T>& X = m->buf[m->cur];
+    HIP_OK(hipMemcpyAsync(X.pos, pos, (size_t)n * 16, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.vel, vel, (size_t)n * 2 * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.dens, dens, (size_t)n * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.mass, mass, (size_t)n * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.tag, tag.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(X.id, id.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(m->time, time, (size_t)ns * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(m->dt, dt, (size_t)ns * 8, hipMemcpyHostToDevice, st));
+    // derived fields belong to the state they were evaluated at: cleared
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->colour), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->drho), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->acc), n * sizeof(V2<T>) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->nrm), n * sizeof(V2<T>) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->kappa), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->kappa_plain), n * sizeof(T) / 4, 0u, st);
+    launch_fill_u32(m->flags, 4, 0u, st);
+    m->sort(st, &c->timer);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    return SPH_OK;
+}
+
+template <typename T>
 SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     SysDev<T> s;
     memset(&s, 0, sizeof s);
@@ -731,6 +853,7 @@ SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     s.R2 = (2.0 * p.h) * (2.0 * p.h);
     double skin = g.reach * p.cell_size - 2.0 * p.h;
     s.skin2 = 0.25 * skin * skin;
+    s.cell_s = p.cell_size;
     // pairs within 2h after a half step of at most skin/2 per particle were
     // within R s = 2h + skin before it (the margin covers rounding)
     s.Rs2 = (g.reach * p.cell_size) * (g.reach * p.cell_size) * (1.0 + 1e-12);
@@ -874,6 +997,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     launch_fill_u64(reinterpret_cast<unsigned long long*>(m->dt), c->n_sys, 0ull, st);
     launch_fill_u64(reinterpret_cast<unsigned long long*>(m->time), c->n_sys, 0ull, st);
     launch_fill_u32(m->flags, 4, 0u, st);
+    launch_fill_u64(m->skin_max, c->n_sys + 1, 0ull, st);
     launch_fill_u32(m->sb.cell, n, 0u, st);
     // the padding past the last position is read (and ignored) by the candidate scan
     for (double2* p : {m->buf[0].pos, m->buf[1].pos, m->pos_h})
@@ -921,6 +1045,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     c->read_fn = read_impl<T>;
     c->nbr_fn = nbr_impl<T>;
     c->closure_fn = closure_impl<T>;
+    c->restore_fn = restore_impl<T>;
     return SPH_OK;
 }
 
@@ -1058,6 +1183,17 @@ sph_status sph_evaluate(sph_ctx* c) {
 sph_status sph_read(sph_ctx* c, int32_t field, void* host_dst, size_t bytes) {
     if (!c) return fail(c, SPH_EINVAL, "ctx is NULL");
     return (sph_status)c->read_fn(c, field, host_dst, bytes);
+}
+
+sph_status sph_state_bytes(const sph_ctx* c, size_t* bytes_out) {
+    if (!c || !bytes_out) return fail(nullptr, SPH_EINVAL, "ctx or bytes_out is NULL");
+    *bytes_out = c->opt.dtype_bits == 32 ? state_bytes<float>(c->n, c->n_sys) : state_bytes<double>(c->n, c->n_sys);
+    return SPH_OK;
+}
+
+sph_status sph_restore(sph_ctx* c, const void* state, size_t bytes) {
+    if (!c || !state) return fail(c, SPH_EINVAL, "ctx or state is NULL");
+    return (sph_status)c->restore_fn(c, state, bytes);
 }
 
 sph_status sph_neighbors(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total) {

@@ -19,7 +19,14 @@
 namespace sphjet {
 
 enum : uint32_t { T_FLUID = 0, T_WALL = 1, T_PISTON = 2, T_INACTIVE = 3 };
-enum : uint32_t { FLAG_NONFINITE = 1, FLAG_DENSITY = 2, FLAG_SKIN = 4 };
+// Instability bits of the flags word, and one informational bit: a half step
+// in which some particle moved farther than half the cell skin, so its
+// evaluation scanned the cells again instead of walking the skin mask.
+enum : uint32_t { FLAG_NONFINITE = 1, FLAG_DENSITY = 2, FLAG_SKIN = 4, FLAG_RESCAN = 8 };
+
+// Largest cell reach of such a rescan: a particle that moved farther than
+// (RESCAN_MAX_REACH s - 2h)/2 in half a step raises FLAG_SKIN.
+constexpr int RESCAN_MAX_REACH = 6;
 
 template <typename T> struct V2t;
 template <> struct V2t<float> { using type = float2; };
@@ -49,6 +56,7 @@ struct SysDev {
     // neighbour grid (FP64, so keys and the predicate are exact)
     double x0, y0, inv_s, R2;      // grid origin, 1/cell size, (2h)^2
     double skin2;                  // (half the skin)^2: allowed half-step displacement squared
+    double cell_s;                 // cell size s
     double Rs2;                    // (R s)^2: radius^2 of the skin mask kept for the half step
     int32_t nx, ny, reach, kernel;
     uint32_t cell_base, pad_;

@@ -89,6 +89,12 @@ struct EvalView {
     uint32_t* smask4;            //   R s); null in the half-step evaluation
     int skin;                    // 1: nmask is a skin mask, walkers apply the exact pair predicate
     int pad3_;
+    // half-step evaluation only (else null): per system, then over all
+    // systems, the bit pattern of the largest squared half-step displacement
+    // beyond half the skin (0: none); such a system's sweeps scan the
+    // step-start cells with a wider reach
+    const unsigned long long* skin_max;
+    uint32_t* flags;
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
     uint32_t* cl_list;
     uint32_t cl_capacity;
@@ -152,7 +158,7 @@ struct ClosureView {
 template <typename T>
 struct IntegView {
     int n;
-    int pad_;
+    int n_sys;
     const SysDev<T>* sys;
     double2* pos;          // state n (corrector updates it in place)
     V2<T>* vel;
@@ -169,6 +175,8 @@ struct IntegView {
     uint32_t* flags;
     T* vol;                // m / rho of the half-step state
     uint32_t* surf_count;  // surface-list counters, cleared for the half-step evaluation
+    unsigned long long* skin_max;  // per system, then over all: largest squared half-step displacement
+                                   // beyond half the skin (0: none)
 };
 
 struct LaunchCfg {
@@ -216,13 +224,15 @@ template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt);
 template <typename T>
 void launch_dt(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base, const double* dt_wave,
-               unsigned long long* dtmin, double* dt, hipStream_t st,
+               unsigned long long* dtmin, double* dt, unsigned long long* skin_max, hipStream_t st,
                KernelTimer* kt);
 template <typename T>
 void launch_predict(const LaunchCfg& L, const IntegView<T>& v, hipStream_t st, KernelTimer* kt);
 template <typename T>
 void launch_correct(const LaunchCfg& L, const IntegView<T>& v, int n_sys, const double* dt, double* time,
                     hipStream_t st, KernelTimer* kt);
+template <typename T>
+void launch_colour_mask(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st);
 template <typename T>
 void launch_nbr_count(const LaunchCfg& L, const EvalView<T>& v, uint32_t* count, hipStream_t st);
 template <typename T>

@@ -318,7 +318,8 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 
 // Visit every slot b != a of the (2R+1)^2 cells around slot a's cell that
 // passes the exact predicate |r_ab|^2 < rp2 (rp2 = (2h)^2 for the neighbours,
-// (R s)^2 for the skin mask of the colour sweep). Candidates are taken four at a
+// (R s)^2 for the skin mask of the colour sweep). R is the system's reach,
+// or a wider one when the half step rescans (rescan_reach). Candidates are taken four at a
 // time: their positions are loaded together, then the per-neighbour payload of
 // the accepted ones (load(b)), then compute(b, k, dx, dy, r2, payload) with k
 // the slot's place in its cell row, r_ab = r_a - r_b in the working precision
@@ -328,13 +329,12 @@ __device__ __forceinline__ void wave_atomic_min(unsigned long long* dst, double 
 template <typename T, int NB = 4, typename LoadFn, typename ComputeFn, typename RowEndFn>
 __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
                                                 uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
-                                                ComputeFn&& compute, RowEndFn&& row_end, double rp2) {
+                                                ComputeFn&& compute, RowEndFn&& row_end, double rp2, int R) {
     using P = typename std::decay<decltype(load(0u))>::type;
     const uint32_t ny = (uint32_t)S.ny;
     const uint32_t local = cell - S.cell_base;
     const int cx = (int)(local / ny);
     const int cy = (int)(local - (uint32_t)cx * ny);
-    const int R = S.reach;
     const int ylo = cy - R < 0 ? 0 : cy - R;
     const int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
     const int xlo = cx - R < 0 ? 0 : cx - R;
@@ -378,34 +378,30 @@ __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32
 template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void scan_cells(const SysDev<T>& S, const uint32_t* __restrict__ cstart, uint32_t cell,
                                            uint32_t a, double2 pa, const double2* __restrict__ pos, LoadFn&& load,
-                                           ComputeFn&& compute) {
+                                           ComputeFn&& compute, int R) {
     scan_cells_rows<T, NB>(S, cstart, cell, a, pa, pos, load,
                            [&](uint32_t b, uint32_t, T dx, T dy, double, const auto& p) { compute(b, dx, dy, p); },
-                           [](int) {}, S.R2);
+                           [](int) {}, S.R2, R);
 }
 
-// Reference-style visitor, one candidate at a time (debug neighbour lists).
-template <typename T, typename Fn>
-__device__ __forceinline__ void for_neighbours(const SysDev<T>& S, const uint32_t* cstart, uint32_t cell,
-                                               int a, double2 pa, const double2* pos, Fn&& f) {
-    uint32_t local = cell - S.cell_base;
-    int cx = (int)(local / (uint32_t)S.ny);
-    int cy = (int)(local - (uint32_t)cx * (uint32_t)S.ny);
-    int R = S.reach;
-    int ylo = cy - R < 0 ? 0 : cy - R;
-    int yhi = cy + R > S.ny - 1 ? S.ny - 1 : cy + R;
-    int xlo = cx - R < 0 ? 0 : cx - R;
-    int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
-    for (int X = xlo; X <= xhi; ++X) {
-        uint32_t row = S.cell_base + (uint32_t)X * (uint32_t)S.ny;
-        uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
-        for (uint32_t b = b0; b < b1; ++b) {
-            if ((int)b == a) continue;
-            double dx, dy;
-            double r2 = pair_r2(pa, pos[b], dx, dy);
-            if (r2 < S.R2) f((int)b, (T)dx, (T)dy);
-        }
+// Reach of a half-step rescan of system `sys`, 0 when its particles all stayed
+// within half the skin (the skin mask is complete). A pair within 2h at the
+// half step was within 2h + 2d at the step start, d the system's largest
+// half-step displacement, so its cells differ by at most ceil((2h + 2d)/s) in
+// each direction. Beyond RESCAN_MAX_REACH the scan keeps that reach and
+// FLAG_SKIN reports that pairs may be missing.
+template <typename T>
+__device__ __forceinline__ int rescan_reach(const EvalView<T>& v, const SysDev<T>& S, int sys) {
+    if (!v.skin_max) return 0;
+    const unsigned long long bits = v.skin_max[sys];
+    if (!bits) return 0;
+    const double d = sqrt(__longlong_as_double((long long)bits));
+    const double need = ceil((sqrt(S.R2) + 2.0 * d) * (1.0 + 1e-12) / S.cell_s);
+    if (!(need <= (double)RESCAN_MAX_REACH)) {
+        atomicOr(v.flags, FLAG_SKIN);
+        return RESCAN_MAX_REACH;
     }
+    return (int)need > S.reach ? (int)need : S.reach;
 }
 
 // Visit the neighbours recorded in slot a's mask words, four at a time
@@ -505,12 +501,57 @@ __device__ __forceinline__ RowMask load_mask(const uint4* nmask, const uint32_t*
 
 // The neighbours of slot a: from its mask, or by scanning its cells when it
 // had more candidates than the mask holds.
-template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
+// RESCAN: the half step of slot a's system outran the skin mask; the
+// step-start cells are scanned with reach `rescan` instead (the kernels built
+// with RESCAN run only for such systems, so the others keep their registers).
+template <typename T, int NB = 4, bool RESCAN = false, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
-                                           LoadFn&& load, ComputeFn&& compute) {
-    const RowMask M = load_mask(v.nmask, v.nmask4, a);
-    if (!(M.w[4] & MASK_OVERFLOW)) mask_neighbours<T, NB>(v, S, a, pa, M, load, compute);
-    else scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute);  // rare: keep it lean
+                                           LoadFn&& load, ComputeFn&& compute, int rescan = 0) {
+    if constexpr (RESCAN) {
+        scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute, rescan);
+    } else {
+        const RowMask M = load_mask(v.nmask, v.nmask4, a);
+        if (!(M.w[4] & MASK_OVERFLOW)) mask_neighbours<T, NB>(v, S, a, pa, M, load, compute);
+        else scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute, S.reach);  // rare: keep it lean
+    }
+}
+
+// Half step: whether system sys outran the skin mask (its sweeps then run in
+// the RESCAN kernels); false in the first evaluation of a step.
+template <typename T>
+__device__ __forceinline__ bool outran(const EvalView<T>& v, int sys) {
+    return v.skin_max != nullptr && v.skin_max[sys] != 0ull;
+}
+
+// The system of sweep chunk c (one 64-slot wave chunk of one system).
+template <typename T>
+__device__ __forceinline__ int chunk_system(const EvalView<T>& v, uint32_t c) {
+    int lo = 0, hi = v.n_sys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (v.chunk_base[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Grid of the RESCAN kernels: its waves stride over the chunks of the systems
+// that outran the skin mask; with none (skin_max[n_sys], the largest over all
+// systems, is 0) every wave returns at once.
+constexpr int RESCAN_BLOCKS = 256;
+
+template <typename T, typename Fn>
+__device__ __forceinline__ void for_outran_chunks(const EvalView<T>& v, Fn&& body) {
+    if (v.skin_max[v.n_sys] == 0ull) return;
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t waves = gridDim.x * wpb;
+    const uint32_t total = v.chunk_base[v.n_sys];
+    for (uint32_t c = blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); c < total; c += waves) {
+        const int sys = chunk_system(v, c);
+        if (v.skin_max[sys] == 0ull) continue;
+        const uint32_t a = v.sys_lo[sys] + (c - v.chunk_base[sys]) * 64u + (uint32_t)__lane_id();
+        body(sys, a, c, __builtin_amdgcn_readfirstlane(rescan_reach(v, v.sys[sys], sys)));
+    }
 }
 
 template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; uint32_t tag; };
@@ -598,9 +639,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         // mask, whose walk applies the exact predicate, so lanes do not pay for
         // each other's rejected candidates
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, [&](uint32_t) { return 0; },
-                           [&](uint32_t, uint32_t k, T, T, double, int) { Sk.mark(k); }, row_end, S.Rs2);
+                           [&](uint32_t, uint32_t k, T, T, double, int) { Sk.mark(k); }, row_end, S.Rs2, S.reach);
         if (!Sk.overflow) mask_neighbours<T>(v, S, a, pa, Sk.M, load, acc);
-        else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc);
+        else scan_cells<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load, acc, S.reach);
     } else {
         // 5 x 5 blocks (about 2.2 candidates per neighbour): one pass
         scan_cells_rows<T>(S, v.cstart, v.cell[a], a, pa, v.pos, load,
@@ -608,7 +649,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                                Sk.mark(k);
                                if (r2 < R2) wsum += vol_b * kernel_shape(K, sqrt_((T)r2));
                            },
-                           row_end, S.Rs2);
+                           row_end, S.Rs2, S.reach);
     }
     colour_finish(v, S, a, vol_a, dens_a, wsum);
     Sk.store(v.smask, v.smask4, a);
@@ -617,21 +658,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 // Sweep 1 of the half-step evaluation: the same colour sum over the skin mask
 // of the first evaluation (v.nmask), which the walk filters by the exact
 // predicate; the sweeps that follow walk the same skin mask.
-template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_colour_skin(EvalView<T> v) {
-    int sys;
-    uint32_t a;
-    if (!wave_assign(v, sys, a)) return;
+template <typename T, bool RESCAN>
+__device__ __forceinline__ void colour_skin_slot(const EvalView<T>& v, int sys, uint32_t a, int rescan) {
     const SysDev<T>& S = v.sys[sys];
-    if (a >= v.sys_hi[sys]) return;
     const KernelConsts<T> K = kconsts(S);
     const double2 pa = v.pos[a];
     const T vol_a = v.vol[a];
     const T dens_a = v.dens[a];
     T wsum = 0;
-    neighbours<T>(v, S, a, pa, [&](uint32_t b) { return v.vol[b]; },
-                  [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); });
+    neighbours<T, 4, RESCAN>(v, S, a, pa, [&](uint32_t b) { return v.vol[b]; },
+                             [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); },
+                             rescan);
     colour_finish(v, S, a, vol_a, dens_a, wsum);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_colour_skin(EvalView<T> v) {
+    int sys;
+    uint32_t a;
+    if (!wave_assign(v, sys, a)) return;
+    if (outran(v, sys)) return;   // k_colour_rescan
+    if (a >= v.sys_hi[sys]) return;
+    colour_skin_slot<T, false>(v, sys, a, 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_colour_rescan(EvalView<T> v) {
+    for_outran_chunks(v, [&](int sys, uint32_t a, uint32_t, int rescan) {
+        if (a < v.sys_hi[sys]) colour_skin_slot<T, true>(v, sys, a, rescan);
+    });
 }
 
 // Sweep 2: continuity (eq. 7) for every active particle (a boundary particle
@@ -649,11 +704,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 // region collects neighbouring chunks (its neighbours share cache lines). The wave's minima of the two dt terms go
 // to its own slot of dt_wave (plain stores); k_dt_finalize reduces them.
 // FP32: six waves per SIMD (at most 80 VGPRs) fit without spilling.
-template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) k_main(EvalView<T> v) {
-    int sys;
-    uint32_t a, chunk;
-    if (!wave_assign(v, sys, a, &chunk)) return;
+// One wave's chunk of the main sweep (every lane of the wave calls it).
+template <typename T, bool RESCAN>
+__device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32_t a, uint32_t chunk, int rescan) {
     const SysDev<T>& S = v.sys[sys];
     const bool valid = a < v.sys_hi[sys];
     // the arguments of this particle's dt terms: c_a + v_sig (eq. 31) and, when
@@ -670,7 +723,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
         const KernelConsts<T> K = kconsts(S);
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, sig_vr = 0, sig_r2 = 1;
-        neighbours<T>(v, S, a, pa,
+        neighbours<T, 4, RESCAN>(v, S, a, pa,
             [&](uint32_t b) {
                 Pay2<T> p;
                 p.vel = v.vel[b];
@@ -707,7 +760,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                     nx += cn * dx;
                     ny += cn * dy;
                 }
-            });
+            },
+            rescan);
         const T vsig = h * sig_vr / sig_r2;
         v.drho[a] = drho;
         V2<T> acc, nrm;
@@ -757,6 +811,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) k_main(EvalView<T> v) {
+    int sys;
+    uint32_t a, chunk;
+    if (!wave_assign(v, sys, a, &chunk)) return;
+    if (outran(v, sys)) return;   // k_main_rescan
+    main_chunk<T, false>(v, sys, a, chunk, 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_main_rescan(EvalView<T> v) {
+    for_outran_chunks(v, [&](int sys, uint32_t a, uint32_t chunk, int rescan) {
+        main_chunk<T, true>(v, sys, a, chunk, rescan);
+    });
+}
+
 // Sweep 3, over the surface list (fluid particles with N_a = 1): curvature
 // kappa_a = sum_b min(N_a,N_b)(m_b/rho_b)(nh_b - nh_a).grad_a W_ab /
 // sum_b min(N_a,N_b)(m_b/rho_b) W_ab (eq. 23, self in the denominator),
@@ -766,8 +836,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 // The list holds a few percent of the particles, from every system, so the
 // waves here are dense but not system-uniform: the system's constants are
 // per lane. A fixed grid strides over the regions, taken as one list.
-template <typename T>
+// RESCAN: the entries of systems whose half step outran the skin mask (and
+// only those; the plain kernel skips them).
+template <typename T, bool RESCAN>
 __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
+    if (RESCAN && v.skin_max[v.n_sys] == 0ull) return;
     __shared__ uint32_t pre[4][SURF_REGIONS];
     static_assert(SURF_REGIONS == 64, "one region per lane");
     const int lane = __lane_id(), w = (int)(threadIdx.x >> 6);
@@ -795,9 +868,10 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
         for (int step = 32; step > 0; step >>= 1)
             if (pre[w][r + step] <= idx) r += step;
         const uint32_t off = idx - pre[w][r];
-        const bool in = idx < total && off < v.surf_region;
+        bool in = idx < total && off < v.surf_region;
         const uint32_t a = in ? v.surf_list[(size_t)r * v.surf_region + off] : 0u;
         const uint32_t sys = in ? tag_sys(v.tag[a]) : 0u;
+        in = in && (RESCAN ? outran(v, (int)sys) : !outran(v, (int)sys));
         const SysDev<T>& S = v.sys[sys];
         double dtf = __builtin_inf();
         bool listed = false;
@@ -816,7 +890,7 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
             T num = 0;
             T den = v.vol[a] * S.W0;
             const double2 pa = v.pos[a];
-            neighbours<T>(v, S, a, pa,
+            neighbours<T, 4, RESCAN>(v, S, a, pa,
                 [&](uint32_t b) { return Pay3<T>{v.nrm[b], v.vol[b]}; },
                 [&](uint32_t, T dx, T dy, const Pay3<T>& p) {
                     T mb = sqrt_(p.nrm.x * p.nrm.x + p.nrm.y * p.nrm.y);
@@ -828,7 +902,8 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
                         num += p.vol * F * ((p.nrm.x * ib - hx) * dx + (p.nrm.y * ib - hy) * dy);
                         den += p.vol * W;
                     }
-                });
+                },
+                RESCAN ? rescan_reach(v, S, (int)sys) : 0);
             const T kappa = num / den;
             v.kappa_plain[a] = kappa;
             T f = listed ? T(0) : -S.sigma * rcp(rho_a) * kappa;
@@ -865,10 +940,12 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
 // dt of every system (eq. 32): the minima of h/(c + sig) (eq. 31) and
 // sqrt(h/|a|) (eq. 30) over the per-wave minima of the main sweep (dt_wave,
 // one pair per chunk of the system) and what the surface and closure kernels
-// folded into dtmin; dtmin is reset for the next step. One workgroup per system.
+// folded into dtmin; dtmin is reset for the next step, and the system's largest
+// half-step displacement for this step's predictor. One workgroup per system.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_dt_finalize(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base,
-                                                     const double* dt_wave, unsigned long long* dtmin, double* dt) {
+                                                     const double* dt_wave, unsigned long long* dtmin, double* dt,
+                                                     unsigned long long* skin_max) {
     __shared__ double red[2][16];
     const int s = blockIdx.x;
     if (s >= n_sys) return;
@@ -900,6 +977,8 @@ __global__ void __launch_bounds__(1024) k_dt_finalize(int n_sys, const SysDev<T>
         const unsigned long long inf_bits = (unsigned long long)__double_as_longlong(__builtin_inf());
         dtmin[2 * s] = inf_bits;
         dtmin[2 * s + 1] = inf_bits;
+        skin_max[s] = 0ull;   // this step's predictor records its displacements afresh
+        if (s == 0) skin_max[n_sys] = 0ull;
     }
 }
 
@@ -909,6 +988,23 @@ __device__ __forceinline__ double piston_travel(double U, double A, double w, do
 }
 __device__ __forceinline__ double piston_speed(double U, double A, double w, double t) {
     return U * (1.0 + A * sin(w * t));
+}
+
+// A half-step displacement beyond half the cell skin: the system's largest one
+// is kept (as the bit pattern of its square, whose unsigned order is the
+// numeric order), so the half-step sweeps of that system scan the cells again
+// with a reach that covers it. Rare; a NaN displacement fails the test and is
+// caught as a non-finite value by the corrector.
+template <typename T>
+__device__ __forceinline__ void note_displacement(const IntegView<T>& v, const SysDev<T>& S, uint32_t sys, double dx,
+                                                  double dy) {
+    const double d2 = dx * dx + dy * dy;
+    if (d2 > S.skin2) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
+        atomicMax(v.skin_max + sys, bits);
+        atomicMax(v.skin_max + v.n_sys, bits);   // the largest over all systems
+        atomicOr(v.flags, FLAG_RESCAN);
+    }
 }
 
 // Predictor: half-step state from state n and its derivatives.
@@ -935,8 +1031,7 @@ __global__ void k_predict(IntegView<T> v) {
         double2 q;
         q.x = p.x + hd * (double)u.x;
         q.y = p.y + hd * (double)u.y;
-        double ddx = q.x - p.x, ddy = q.y - p.y;
-        if (ddx * ddx + ddy * ddy > S.skin2) atomicOr(v.flags, FLAG_SKIN);
+        note_displacement(v, S, tag_sys(t), q.x - p.x, q.y - p.y);
         v.pos_h[a] = q;
         V2<T> w;
         w.x = u.x + hdt * acc.x;
@@ -949,6 +1044,7 @@ __global__ void k_predict(IntegView<T> v) {
         double2 q;
         q.x = p.x + S.pdx * dX;
         q.y = p.y + S.pdy * dX;
+        note_displacement(v, S, tag_sys(t), q.x - p.x, q.y - p.y);
         v.pos_h[a] = q;
         V2<T> w;
         w.x = (T)(S.pdx * U);
@@ -1014,6 +1110,11 @@ __global__ void k_advance_time(int n_sys, const double* dt, double* time) {
 }
 
 // ------------------------------------------------------------------ debug: neighbour lists
+// The neighbours the sweeps visit, read back: after a sort and the first
+// colour sweep (which records the skin mask), every slot's neighbours are
+// walked exactly as the main and surface sweeps walk them -- the mask's
+// candidates filtered by the exact pair predicate, or the cell scan where the
+// mask overflowed.
 
 template <typename T>
 __global__ void k_nbr_count(EvalView<T> v, uint32_t* count) {
@@ -1023,7 +1124,8 @@ __global__ void k_nbr_count(EvalView<T> v, uint32_t* count) {
     uint32_t c = 0;
     if (tag_type(t) != T_INACTIVE) {
         const SysDev<T>& S = v.sys[tag_sys(t)];
-        for_neighbours<T>(S, v.cstart, v.cell[a], a, v.pos[a], v.pos, [&](int, T, T) { ++c; });
+        neighbours<T, 1>(v, S, (uint32_t)a, v.pos[a], [](uint32_t) { return 0; },
+                         [&](uint32_t, T, T, int) { ++c; });
     }
     count[a] = c;
 }
@@ -1036,7 +1138,8 @@ __global__ void k_nbr_fill(EvalView<T> v, int a0, int a1, const int64_t* start, 
     if (tag_type(t) == T_INACTIVE) return;
     const SysDev<T>& S = v.sys[tag_sys(t)];
     int64_t k = start[a] - base;
-    for_neighbours<T>(S, v.cstart, v.cell[a], a, v.pos[a], v.pos, [&](int b, T, T) { out[k++] = v.id[b]; });
+    neighbours<T, 1>(v, S, (uint32_t)a, v.pos[a], [](uint32_t) { return 0; },
+                     [&](uint32_t b, T, T, int) { out[k++] = v.id[b]; });
 }
 
 // Derived per-slot quantities for sph_read.
@@ -1133,6 +1236,9 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     const int bs = L.block_sweep;
     const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
     const unsigned nb = nblk(max_waves, bs / 64);
+    // the half step (v.skin_max set) follows each sweep with its RESCAN
+    // kernel, which returns at once unless some system outran the skin mask
+    const bool half = v.skin_max != nullptr;
     if (!v.smask) {
         kt->begin("colour_skin", st);
         k_colour_skin<T><<<nb, bs, 0, st>>>(v);
@@ -1142,19 +1248,34 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
         k_colour<T><<<nb, bs, 0, st>>>(v);
     }
     kt->end(st);
+    if (half) {
+        kt->begin("rescan", st);
+        k_colour_rescan<T><<<RESCAN_BLOCKS, 256, 0, st>>>(v);
+        kt->end(st);
+    }
     kt->begin("main", st);
     k_main<T><<<nb, bs, 0, st>>>(v);
     kt->end(st);
+    if (half) {
+        kt->begin("rescan", st);
+        k_main_rescan<T><<<RESCAN_BLOCKS, 256, 0, st>>>(v);
+        kt->end(st);
+    }
     kt->begin("surface", st);
-    k_surface<T><<<surface_blocks(L.n), 256, 0, st>>>(v);
+    k_surface<T, false><<<surface_blocks(L.n), 256, 0, st>>>(v);
     kt->end(st);
+    if (half) {
+        kt->begin("rescan", st);
+        k_surface<T, true><<<RESCAN_BLOCKS, 256, 0, st>>>(v);
+        kt->end(st);
+    }
 }
 
 template <typename T>
 void launch_dt(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base, const double* dt_wave,
-               unsigned long long* dtmin, double* dt, hipStream_t st, KernelTimer* kt) {
+               unsigned long long* dtmin, double* dt, unsigned long long* skin_max, hipStream_t st, KernelTimer* kt) {
     kt->begin("dt", st);
-    k_dt_finalize<T><<<(unsigned)n_sys, 1024, 0, st>>>(n_sys, sys, chunk_base, dt_wave, dtmin, dt);
+    k_dt_finalize<T><<<(unsigned)n_sys, 1024, 0, st>>>(n_sys, sys, chunk_base, dt_wave, dtmin, dt, skin_max);
     kt->end(st);
 }
 
@@ -1174,6 +1295,14 @@ void launch_correct(const LaunchCfg& L, const IntegView<T>& v, int n_sys, const 
     kt->begin("time", st);
     k_advance_time<<<nblk(n_sys, 64), 64, 0, st>>>(n_sys, dt, time);
     kt->end(st);
+}
+
+// The first colour sweep alone: colour, neighbour record and the skin mask.
+template <typename T>
+void launch_colour_mask(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st) {
+    const int bs = L.block_sweep;
+    const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
+    k_colour<T><<<nblk(max_waves, bs / 64), bs, 0, st>>>(v);
 }
 
 template <typename T>
@@ -1197,11 +1326,12 @@ void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* 
                                  StateBuf<T>, T*, hipStream_t, KernelTimer*);                              \
     template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t, KernelTimer*);         \
     template void launch_dt<T>(int, const SysDev<T>*, const uint32_t*, const double*, unsigned long long*, \
-                               double*, hipStream_t,                                                       \
+                               double*, unsigned long long*, hipStream_t,                                  \
                                KernelTimer*);                                                              \
     template void launch_predict<T>(const LaunchCfg&, const IntegView<T>&, hipStream_t, KernelTimer*);     \
     template void launch_correct<T>(const LaunchCfg&, const IntegView<T>&, int, const double*, double*,    \
                                     hipStream_t, KernelTimer*);                                            \
+    template void launch_colour_mask<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t);               \
     template void launch_nbr_count<T>(const LaunchCfg&, const EvalView<T>&, uint32_t*, hipStream_t);       \
     template void launch_nbr_fill<T>(const EvalView<T>&, int, int, const int64_t*, int64_t, uint32_t*,    \
                                      hipStream_t);                                                         \

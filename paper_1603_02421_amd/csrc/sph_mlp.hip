@@ -660,7 +660,12 @@ __device__ __forceinline__ ApplyIn<T> closure_apply_load(const EvalView<T>& v, u
     in.rho = v.eos[a].z;
     in.n_a = v.nrm[a];
     in.acc = v.acc[a];
-    in.overflow = (v.nmask4[a] & MASK_OVERFLOW) != 0u;
+    // the plain estimate is used where the stencil may be incomplete: the mask
+    // overflowed, it holds more candidates than a stencil group takes (128), or
+    // the half step of this system outran the skin mask the stencil walks
+    const RowMask M = closure_mask(v.nmask, v.nmask4, a);
+    in.overflow = (M.w[4] & MASK_OVERFLOW) != 0u || stencil_candidates(M) > 128 ||
+                  (v.skin_max && v.skin_max[in.sys] != 0ull);
     return in;
 }
 

@@ -20,7 +20,7 @@ FIELDS = {
     "pos": 0, "vel": 1, "rho": 2, "pressure": 3, "mass": 4, "type": 5, "drhodt": 6, "accel": 7,
     "colour": 8, "normal": 9, "curv": 10, "nflag": 11, "dt": 12, "time": 13, "nactive": 14,
     "sort_keys": 15, "sort_perm": 16, "flags": 17, "curv_plain": 18, "stencil": 19, "closure": 20,
-    "fallback": 21,
+    "fallback": 21, "all_state": 22,
 }
 MLP_NPARAMS = 8515
 STATIC_WORKSPACE_BYTES = 128 << 20   # SPH_STATIC_WORKSPACE_BYTES
@@ -28,7 +28,7 @@ STATIC_WORKSPACE_BYTES = 128 << 20   # SPH_STATIC_WORKSPACE_BYTES
 # Exported entry points, as declared in include/sph.h.
 EXPORTS = [
     "sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
-    "sph_sync", "sph_profile", "sph_autotune", "sph_free", "sph_last_error", "sph_abi_version",
+    "sph_sync", "sph_profile", "sph_autotune", "sph_state_bytes", "sph_restore", "sph_free", "sph_last_error", "sph_abi_version",
     "sph_set_closure", "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
     "sph_mlp_train_step", "sph_mlp_params", "sph_mlp_free",
 ]
@@ -88,6 +88,8 @@ def load():
     L.sph_read.argtypes = [vp, i32, vp, sz]
     L.sph_neighbors.argtypes = [vp, vp, vp, i64, C.POINTER(i64)]
     L.sph_sync.argtypes = [vp]
+    L.sph_state_bytes.argtypes = [vp, C.POINTER(sz)]
+    L.sph_restore.argtypes = [vp, vp, sz]
     L.sph_profile.argtypes = [vp, i32, i32, C.POINTER(C.c_char_p), vp, vp, C.POINTER(i32)]
     L.sph_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, i32, vp]
     L.sph_free.argtypes = [vp]
@@ -106,6 +108,7 @@ def load():
     L.sph_abi_version.restype = i32
     for name in ("sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read",
                  "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune", "sph_set_closure",
+                 "sph_state_bytes", "sph_restore",
                  "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
                  "sph_mlp_train_step", "sph_mlp_params"):
         getattr(L, name).restype = i32

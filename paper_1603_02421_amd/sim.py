@@ -137,6 +137,22 @@ class Simulation:
             native.check(st, self._ctx)
         return out
 
+    def checkpoint(self, allow_unstable: bool = False) -> bytes:
+        """The state blob (sph_read of SPH_F_ALL_STATE)."""
+        nbytes = C.c_size_t(0)
+        native.check(self._L.sph_state_bytes(self._ctx, C.byref(nbytes)), self._ctx)
+        buf = np.zeros(int(nbytes.value), dtype=np.uint8)
+        st = self._L.sph_read(self._ctx, native.FIELDS["all_state"], _ptr(buf), buf.nbytes)
+        if not (allow_unstable and st == native.SPH_EUNSTABLE):
+            native.check(st, self._ctx)
+        return buf.tobytes()
+
+    def restore(self, blob: bytes) -> "Simulation":
+        """Load a state blob from checkpoint() (sph_restore)."""
+        buf = np.frombuffer(blob, dtype=np.uint8)
+        native.check(self._L.sph_restore(self._ctx, _ptr(buf), buf.nbytes), self._ctx)
+        return self
+
     def read_all(self, fields: Sequence[str] = ("pos", "vel", "rho", "type")) -> Dict[str, np.ndarray]:
         return {f: self.read(f) for f in fields}
 
