@@ -271,16 +271,20 @@ def test_fast_particles_within_the_cell_skin(gpu, orc):
 
 
 def test_trajectory_fp64_dam_break(gpu, orc):
+    """The dam break with its obstacle in FP64 over the configured 500 steps,
+    checked every 100."""
     obj = wl.dam_break()
     say(f"[trajectory fp64] dam_break n={obj.n}")
     st = orc.State(obj)
     with _sim(gpu, obj, bits=64) as sim:
-        sim.step(50)
-        st.step(50)
-        ep, er, ev = _traj_errors(sim, st, 0.01, 1000.0)
-        say(f"   50 steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
-        assert ep <= 1e-9 and er <= 1e-9 and ev <= 1e-9
-        assert np.allclose(sim.read("time"), st.time, rtol=1e-12)
+        for k in range(5):
+            sim.step(100)
+            st.step(100)
+            ep, er, ev = _traj_errors(sim, st, 0.01, 1000.0)
+            say(f"   {100 * (k + 1)} steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
+            assert ep <= 1e-9 and er <= 1e-9 and ev <= 1e-9
+            assert np.allclose(sim.read("time"), st.time, rtol=1e-12)
+            assert np.array_equal(sim.read("type"), st.type)
 
 
 def test_run_to_run_bit_identical(gpu):
