@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 1
+#define SPH_ABI_VERSION 2
 
 typedef enum {
     SPH_OK = 0,
@@ -109,6 +109,17 @@ typedef struct sph_params {
     double piston_omega;
     double closure_tol;    /* closure only: relative deviation from the plain
                               curvature above which the plain value is used (0.2) */
+    int32_t density;       /* 0: density from the continuity equation (eq. 7);
+                              1: density summation (eq. 6) for fluid particles --
+                              at every evaluation rho_a = sum_b m_b W_ab over every
+                              active particle of the system, itself included,
+                              before the pressure; the integrator keeps the density
+                              of the latest evaluation; the density check then has
+                              no lower bound (a lone particle has m W(0)) */
+    int32_t boundary;      /* 0: dynamic boundary particles (see the particle types);
+                              1: repulsive-force walls (eq. 29, see sph_set_wall_normals) */
+    double wall_spacing;   /* repulsive walls: spacing of the wall particles along
+                              the wall (0: h / 1.3) */
 } sph_params;
 
 /* Per-context options. Zero-initialised options select the defaults. */

@@ -58,7 +58,7 @@ def using(path: str):
 
 class Params(C.Structure):
     _fields_ = [
-        ("kernel", C.c_int32), ("pad_", C.c_int32),
+        ("kernel", C.c_int32), ("density", C.c_int32),
         ("h", C.c_double), ("rho0", C.c_double), ("c0", C.c_double), ("gamma", C.c_double),
         ("alpha", C.c_double), ("eta2_h2", C.c_double), ("sigma", C.c_double), ("eps_h", C.c_double),
         ("gravity", C.c_double * 2), ("courant", C.c_double), ("dt_fixed", C.c_double),
@@ -71,12 +71,13 @@ class Params(C.Structure):
 class EvalOut(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in (
         "colour", "drho", "apv", "nrm", "nflag", "kappa", "asurf", "acc", "vsig", "nnb",
-        "s_drho", "s_acc", "s_nrm", "dt_f", "dt_cv", "dt")]
+        "s_drho", "s_acc", "s_nrm", "dt_f", "dt_cv", "dt", "rho")]
 
 
 def _params(d: Dict) -> Params:
     p = Params()
     p.kernel = int(d["kernel"])
+    p.density = int(d.get("density", 0))
     for k in ("h", "rho0", "c0", "gamma", "alpha", "eta2_h2", "sigma", "eps_h", "courant",
               "dt_fixed", "cell_size", "piston_u", "piston_amp", "piston_omega"):
         setattr(p, k, float(d[k]))
@@ -202,7 +203,7 @@ def evaluate(obj) -> Dict[str, np.ndarray]:
         nflag=np.zeros(n, dtype=np.int32), kappa=np.zeros(n), asurf=np.zeros((n, 2)),
         acc=np.zeros((n, 2)), vsig=np.zeros(n), nnb=np.zeros(n, dtype=np.int32),
         s_drho=np.zeros(n), s_acc=np.zeros(n), s_nrm=np.zeros(n),
-        dt_f=np.zeros(ns), dt_cv=np.zeros(ns), dt=np.zeros(ns))
+        dt_f=np.zeros(ns), dt_cv=np.zeros(ns), dt=np.zeros(ns), rho=np.zeros(n))
     out = EvalOut(**{k: _ptr(v).value if v is not None else None for k, v in res.items()})
     lib().orc_eval(ns, _param_array(plist), _ptr(off), _ptr(pos), _ptr(vel), _ptr(rho),
                    _ptr(mass), _ptr(typ), C.byref(out))

@@ -23,6 +23,12 @@
  *    wall of Section 2-6 is a purely repulsive force); walls stay fixed, the
  *    piston follows its prescribed motion, and boundaries carry no normal
  *    (N = 0) or surface force.
+ *  - Density summation (eq. 6), a per-system option: at every evaluation a
+ *    fluid particle's density is rho_a = sum_b m_b W_ab over every active
+ *    particle of its system, itself included, from the positions alone; it
+ *    replaces the continuity equation for that particle (the integrator keeps
+ *    the density of the latest evaluation). Boundary particles keep the rule
+ *    above.
  *  - The predictor-corrector (Section 2-8 cites it without equations):
  *    half step phi_1/2 = phi_n + dt/2 D_n; full step rho_{n+1} = rho_n + dt Drho_1/2,
  *    v_{n+1} = v_n + dt a_1/2, r_{n+1} = r_n + dt (v_n + dt/2 a_1/2); dt from
@@ -284,7 +290,7 @@ void orc_sort(int n_sys, const orc_params* p, const int64_t* off, const double* 
 static double dot2(double ax, double ay, double bx, double by) { return ax * bx + ay * by; }
 
 int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double* pos,
-             const double* vel, const double* rho, const double* mass, const int32_t* type,
+             const double* vel, const double* rho_in, const double* mass, const int32_t* type,
              const orc_eval_out* out) {
     int64_t n = off[n_sys];
     int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
@@ -307,6 +313,8 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
     double* vs = (double*)calloc((size_t)n, sizeof(double));
     double* sdr = (double*)calloc((size_t)n, sizeof(double));
     double* sacc = (double*)calloc((size_t)n, sizeof(double));
+    double* rho = (double*)malloc(sizeof(double) * (size_t)n);
+    memcpy(rho, rho_in, sizeof(double) * (size_t)n);
 
     for (int s = 0; s < n_sys; ++s) {
         const orc_params* p = &prm[s];
@@ -316,6 +324,22 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
         double eps = p->eps_h / h;                 /* eq. 20 threshold eps = 0.01/h */
         double eta2 = p->eta2_h2 * h * h;          /* eq. 10 */
         double W0 = orc_kernel_w(K, 0.0, h);
+
+        /* Density summation (eq. 6) over every active particle, self included,
+         * for the fluid particles of a system that uses it. */
+        if (p->density == 1) {
+#pragma omp parallel for schedule(dynamic, 128)
+            for (int64_t a = o0; a < o1; ++a) {
+                if (type[a] != ORC_FLUID) continue;
+                double sum = mass[a] * W0;
+                for (int64_t k = start[a]; k < start[a + 1]; ++k) {
+                    int64_t b = nbr[k];
+                    double rx = pos[2 * a] - pos[2 * b], ry = pos[2 * a + 1] - pos[2 * b + 1];
+                    sum += mass[b] * orc_kernel_w(K, sqrt(rx * rx + ry * ry), h);
+                }
+                rho[a] = sum;
+            }
+        }
 
         /* Tait pressure and sound speed (eq. 26). */
         for (int64_t a = o0; a < o1; ++a) { P[a] = tait_p(p, rho[a]); c[a] = tait_c(p, rho[a]); }
@@ -463,7 +487,9 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
     if (out->s_nrm) memcpy(out->s_nrm, snrm, sizeof(double) * (size_t)n);
     if (out->nnb)
         for (int64_t a = 0; a < n; ++a) out->nnb[a] = (int32_t)(start[a + 1] - start[a]);
+    if (out->rho) memcpy(out->rho, rho, sizeof(double) * (size_t)n);
 
+    free(rho);
     free(start); free(nbr); free(P); free(c); free(C); free(nv); free(snrm); free(nhat);
     free(N); free(kap); free(as); free(apv); free(acc); free(dr); free(vs); free(sdr); free(sacc);
     return 0;
@@ -493,11 +519,13 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
     double* a1 = (double*)malloc(sizeof(double) * (size_t)(2 * n));
     double* dt = (double*)malloc(sizeof(double) * (size_t)n_sys);
     double* dt_unused = (double*)malloc(sizeof(double) * (size_t)n_sys);
+    double* re0 = (double*)malloc(sizeof(double) * (size_t)n);   /* densities of the two evaluations */
+    double* re1 = (double*)malloc(sizeof(double) * (size_t)n);
 
     for (int step = 0; step < nsteps; ++step) {
         orc_eval_out o0;
         memset(&o0, 0, sizeof o0);
-        o0.drho = d0; o0.acc = a0; o0.dt = dt;
+        o0.drho = d0; o0.acc = a0; o0.dt = dt; o0.rho = re0;
         orc_eval(n_sys, prm, off, pos, vel, rho, mass, type, &o0);
 
         /* predictor: half step */
@@ -511,7 +539,9 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
                 vh[2 * a] = vel[2 * a]; vh[2 * a + 1] = vel[2 * a + 1];
                 rh[a] = rho[a];
                 if (type[a] == ORC_INACTIVE) continue;
-                rh[a] = rho[a] + hdt * d0[a];
+                /* a summed density is recomputed by the next evaluation */
+                if (p->density == 1 && type[a] == ORC_FLUID) rh[a] = re0[a];
+                else rh[a] = rho[a] + hdt * d0[a];
                 if (type[a] != ORC_FLUID && rh[a] < p->rho0) rh[a] = p->rho0;  /* walls only repel */
                 if (type[a] == ORC_FLUID) {
                     ph[2 * a] = pos[2 * a] + hdt * vel[2 * a];
@@ -529,7 +559,7 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
 
         orc_eval_out o1;
         memset(&o1, 0, sizeof o1);
-        o1.drho = d1; o1.acc = a1; o1.dt = dt_unused;
+        o1.drho = d1; o1.acc = a1; o1.dt = dt_unused; o1.rho = re1;
         orc_eval(n_sys, prm, off, ph, vh, rh, mass, type, &o1);
 
         /* corrector: full step from state n with the half-step derivatives */
@@ -540,7 +570,9 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
             double U = piston_speed(p, time[s] + T);
             for (int64_t a = off[s]; a < off[s + 1]; ++a) {
                 if (type[a] == ORC_INACTIVE) continue;
-                rho[a] = rho[a] + T * d1[a];
+                /* summation: the density of the latest (half-step) evaluation */
+                if (p->density == 1 && type[a] == ORC_FLUID) rho[a] = re1[a];
+                else rho[a] = rho[a] + T * d1[a];
                 if (type[a] != ORC_FLUID && rho[a] < p->rho0) rho[a] = p->rho0;  /* walls only repel */
                 if (type[a] == ORC_FLUID) {
                     double vx = vel[2 * a], vy = vel[2 * a + 1];
@@ -563,5 +595,6 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
         }
     }
     free(ph); free(vh); free(rh); free(d0); free(a0); free(d1); free(a1); free(dt); free(dt_unused);
+    free(re0); free(re1);
     return 0;
 }

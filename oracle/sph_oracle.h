@@ -24,7 +24,7 @@ extern "C" {
 
 typedef struct {
     int32_t kernel;        /* 0 Wendland (eq. 28), 1 cubic spline (eq. 27) */
-    int32_t pad_;
+    int32_t density;       /* 0 continuity (eq. 7), 1 summation (eq. 6) for fluid particles */
     double h;              /* smoothing length */
     double rho0, c0, gamma;/* Tait reference density, sound speed, exponent (eq. 26) */
     double alpha;          /* artificial-viscosity coefficient (eq. 10) */
@@ -59,6 +59,7 @@ typedef struct {
     double *s_acc;
     double *s_nrm;
     double *dt_f, *dt_cv, *dt;  /* per system, eq. 30-32 */
+    double *rho;       /* density used by this evaluation (eq. 6 where summed) */
 } orc_eval_out;
 
 /* Kernel value W(r,h) and F(r,h) with grad_a W = F r_ab (2-D). */

@@ -111,6 +111,9 @@ const char* check_params(const sph_params& p) {
     if (!(p.dt_fixed >= 0)) return "dt_fixed must be >= 0";
     if (p.kernel != SPH_WENDLAND && p.kernel != SPH_CUBIC) return "kernel must be SPH_WENDLAND or SPH_CUBIC";
     if (p.closure != 0 && p.closure != 1) return "closure must be 0 or 1";
+    if (p.density != 0 && p.density != 1) return "density must be 0 or 1";
+    if (p.boundary != 0 && p.boundary != 1) return "boundary must be 0 or 1";
+    if (!(p.wall_spacing >= 0)) return "wall_spacing must be >= 0";
     if (!(p.box_hi[0] > p.box_lo[0] && p.box_hi[1] > p.box_lo[1])) return "box_hi must exceed box_lo";
     if (!(p.cell_size > p.h)) return "cell_size must exceed h";
     if (!isfinite(p.gravity[0]) || !isfinite(p.gravity[1])) return "gravity must be finite";
@@ -223,6 +226,7 @@ struct Impl : sph_ctx_base {
     uint32_t surf_region = 0;
     uint32_t* surf_count = nullptr;
     uint32_t* surf_list = nullptr;
+    bool density_sum = false;   // some system uses the density summation (eq. 6)
     // learned closure (only when some system uses it)
     bool closure = false;
     ClosureView cl{};
@@ -375,6 +379,9 @@ struct Impl : sph_ctx_base {
         }
         v.skin_max = half ? skin_max : nullptr;
         v.flags = flags;
+        v.dens_out = half ? dens_h : S.dens;
+        v.vol_out = vol;
+        v.density_sum = density_sum ? 1 : 0;
         return v;
     }
 
@@ -884,6 +891,11 @@ SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     s.gy = (T)p.gravity[1];
     s.gamma7 = p.gamma == 7.0 ? 1 : 0;
     s.closure = p.closure;
+    s.density_sum = p.density;
+    s.boundary = p.boundary;
+    s.h64 = h;
+    s.wnorm64 = wn;
+    s.rho0_64 = p.rho0;
     s.closure_tol = (T)(p.closure_tol > 0 ? p.closure_tol : 0.2);
     s.courant = p.courant;
     s.dt_fixed = p.dt_fixed;
@@ -938,7 +950,10 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     m->L.xcd = c->opt.xcd_remap;
     const uint32_t trash = c->cell_base[c->n_sys];
     bool with_closure = false;
-    for (int s2 = 0; s2 < c->n_sys; ++s2) with_closure = with_closure || c->params[s2].closure != 0;
+    for (int s2 = 0; s2 < c->n_sys; ++s2) {
+        with_closure = with_closure || c->params[s2].closure != 0;
+        m->density_sum = m->density_sum || c->params[s2].density != 0;
+    }
     size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream, with_closure);
     if (ws_bytes < need)
         return fail(c, SPH_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");

@@ -70,6 +70,9 @@ struct SysDev {
     T gx, gy;
     int32_t gamma7, closure;
     T closure_tol;
+    int32_t density_sum;           // 1: eq. 6 for fluid particles
+    int32_t boundary;              // 1: repulsive-force walls (eq. 29)
+    double h64, wnorm64, rho0_64;  // FP64 copies for the density summation
     // time stepping (FP64)
     double courant, dt_fixed;
     double box_lo_x, box_lo_y, box_hi_x, box_hi_y;
@@ -155,6 +158,18 @@ __device__ __forceinline__ T kernel_shape(const KernelConsts<T>& K, T r) {
     if (q <= T(1)) return T(1) + q * q * (T(-1.5) + T(0.75) * q);
     T u = T(2) - q;
     return T(0.25) * u * u * u;
+}
+
+// W / wnorm in FP64, at q = r / h (the density summation's terms).
+__device__ __forceinline__ double kernel_shape64(int kernel, double q) {
+    if (kernel == 0) {
+        const double u = 1.0 - 0.5 * q;
+        const double u2 = u * u;
+        return u2 * u2 * (1.0 + 2.0 * q);
+    }
+    if (q <= 1.0) return 1.0 + q * q * (-1.5 + 0.75 * q);
+    const double u = 2.0 - q;
+    return 0.25 * u * u * u;
 }
 
 template <typename T>

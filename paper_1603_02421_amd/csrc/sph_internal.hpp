@@ -95,6 +95,10 @@ struct EvalView {
     // step-start cells with a wider reach
     const unsigned long long* skin_max;
     uint32_t* flags;
+    T* dens_out;                 // the evaluation's density (= dens), written by the density summation
+    T* vol_out;                  // its m / rho (= vol)
+    int density_sum;             // some system uses the density summation (eq. 6)
+    int pad4_;
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
     uint32_t* cl_list;
     uint32_t cl_capacity;

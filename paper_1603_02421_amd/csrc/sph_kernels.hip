@@ -557,6 +557,37 @@ __device__ __forceinline__ void for_outran_chunks(const EvalView<T>& v, Fn&& bod
 template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; uint32_t tag; };
 template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 
+// Density summation (eq. 6) for the fluid particles of systems that use it:
+// rho_a = sum_b m_b W_ab over every active particle of the system, itself
+// included, summed in FP64 whatever the storage type -- the stored rho - rho0
+// keeps the Tait pressure's precision only if the sum is exact to well below
+// an FP32 ulp of rho0 -- and written, with m / rho, to the evaluation's
+// state before the colour sweep reads m_b / rho_b. The cells are scanned with
+// the exact pair predicate: the step-start cells in the half step too, with
+// the rescan reach where the system outran the skin.
+template <typename T>
+__global__ void __launch_bounds__(256) k_density(EvalView<T> v) {
+    int sys;
+    uint32_t a;
+    if (!wave_assign(v, sys, a)) return;
+    const SysDev<T>& S = v.sys[sys];
+    if (!S.density_sum) return;
+    const int rr = v.skin_max ? rescan_reach(v, S, sys) : 0;
+    const int R = __builtin_amdgcn_readfirstlane(rr ? rr : S.reach);
+    if (a >= v.sys_hi[sys] || tag_type(v.tag[a]) != T_FLUID) return;
+    const double inv_h = 1.0 / S.h64;
+    const double m_a = (double)v.mass[a];
+    double sum = m_a;   // the self term m_a W(0), W(0) = wnorm
+    scan_cells_rows<T>(S, v.cstart, v.cell[a], a, v.pos[a], v.pos, [&](uint32_t b) { return v.mass[b]; },
+                       [&](uint32_t, uint32_t, T, T, double r2, T m_b) {
+                           sum += (double)m_b * kernel_shape64(S.kernel, sqrt(r2) * inv_h);
+                       },
+                       [](int) {}, S.R2, R);
+    const double rho = S.wnorm64 * sum;
+    v.dens_out[a] = (T)(rho - S.rho0_64);
+    v.vol_out[a] = (T)(m_a / rho);
+}
+
 // Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included
 // (eq. 14). The Tait equation (eq. 26) is evaluated here once per particle:
 // the record (P / rho^2, C, rho, m / rho) is everything the main sweep
@@ -1022,7 +1053,8 @@ __global__ void k_predict(IntegView<T> v) {
     T hdt = (T)hd;
     double2 p = v.pos[a];
     V2<T> u = v.vel[a];
-    T dh = v.dens[a] + hdt * v.drho[a];
+    // a summed density (eq. 6) is recomputed by the half-step evaluation
+    T dh = (ty == T_FLUID && S.density_sum) ? v.dens[a] : v.dens[a] + hdt * v.drho[a];
     if (ty != T_FLUID && dh < T(0)) dh = T(0);   // boundaries never below rho0: they only repel
     v.dens_h[a] = dh;
     v.vol[a] = particle_vol(S, dh, v.mass[a]);
@@ -1073,12 +1105,14 @@ __global__ void k_correct(IntegView<T> v) {
     const SysDev<T>& S = v.sys[tag_sys(t)];
     double dt = v.dt[tag_sys(t)];
     T tdt = (T)dt;
-    T dens = dens0 + tdt * drho;
+    // eq. 6: the density of the half-step evaluation; eq. 7 otherwise
+    const bool summed = ty == T_FLUID && S.density_sum;
+    T dens = summed ? v.dens_h[a] : dens0 + tdt * drho;
     if (ty != T_FLUID && dens < T(0)) dens = T(0);   // boundaries never below rho0
     v.dens[a] = dens;
     uint32_t flags = 0;
     if (!isfinite(dens)) flags |= FLAG_NONFINITE;
-    else if (dens < T(-0.5) * S.rho0 || dens > S.rho0) flags |= FLAG_DENSITY;
+    else if ((!summed && dens < T(-0.5) * S.rho0) || dens > S.rho0) flags |= FLAG_DENSITY;
     if (ty == T_FLUID) {
         p.x = p.x + dt * ((double)u.x + 0.5 * dt * (double)acc.x);
         p.y = p.y + dt * ((double)u.y + 0.5 * dt * (double)acc.y);
@@ -1239,6 +1273,11 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     // the half step (v.skin_max set) follows each sweep with its RESCAN
     // kernel, which returns at once unless some system outran the skin mask
     const bool half = v.skin_max != nullptr;
+    if (v.density_sum) {
+        kt->begin("density", st);
+        k_density<T><<<nb, bs, 0, st>>>(v);
+        kt->end(st);
+    }
     if (!v.smask) {
         kt->begin("colour_skin", st);
         k_colour_skin<T><<<nb, bs, 0, st>>>(v);

@@ -43,6 +43,7 @@ class SphParams(C.Structure):
         ("box_lo", C.c_double * 2), ("box_hi", C.c_double * 2), ("cell_size", C.c_double),
         ("piston_dir", C.c_double * 2), ("piston_u", C.c_double), ("piston_amp", C.c_double),
         ("piston_omega", C.c_double), ("closure_tol", C.c_double),
+        ("density", C.c_int32), ("boundary", C.c_int32), ("wall_spacing", C.c_double),
     ]
 
 
@@ -130,6 +131,9 @@ def params_struct(d) -> SphParams:
               "dt_fixed", "cell_size", "piston_u", "piston_amp", "piston_omega"):
         setattr(p, k, float(d[k]))
     p.closure_tol = float(d.get("closure_tol", 0.2))
+    p.density = int(d.get("density", 0))
+    p.boundary = int(d.get("boundary", 0))
+    p.wall_spacing = float(d.get("wall_spacing", 0.0))
     for k in ("gravity", "box_lo", "box_hi", "piston_dir"):
         arr = getattr(p, k)
         arr[0], arr[1] = float(d[k][0]), float(d[k][1])

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     L = native.load()
     for name in _declared():
         assert hasattr(L, name), name
-    assert L.sph_abi_version() == 1
+    assert L.sph_abi_version() == 2
 
 
 def _ws(params_list, n_list, **opt):

@@ -44,6 +44,12 @@ MUTANTS = {
                     [(pins.test_signal_term_uniform_compression, dict(wall_fraction=0.0, rho_factor=1.0))]),
     "eq31_c0_for_c_a": ("double v = h / (c[a] + vs[a]);", "double v = h / (p->c0 + vs[a]);",
                         [(pins.test_signal_term_uniform_compression, dict(wall_fraction=0.0, rho_factor=1.01))]),
+    # eq. 6: density summation
+    "eq6_no_self": ("double sum = mass[a] * W0;", "double sum = 0.0;",
+                    [(pins.test_density_summation_lone_particle, dict(kernel=wl.WENDLAND, w0=7.0 / (4.0 * 3.141592653589793)))]),
+    "eq6_volume_for_mass": ("sum += mass[b] * orc_kernel_w(K, sqrt(rx * rx + ry * ry), h);",
+                            "sum += mass[b] / rho[b] * orc_kernel_w(K, sqrt(rx * rx + ry * ry), h);",
+                            [(pins.test_density_summation_lattice_interior, {})]),
     # eq. 14, 18, 23, 24: colour, normal, curvature, surface force
     "eq14_no_self": ("double sum = mass[a] / rho[a] * W0;", "double sum = 0.0;",
                      [(pins.test_colour_bulk_and_surface, {})]),

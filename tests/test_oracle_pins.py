@@ -319,6 +319,57 @@ def test_viscosity_acts_on_approaching_pairs_only(orc, approach):
         assert np.all(a == 0.0)
 
 
+@pytest.mark.parametrize("kernel,w0", [(wl.WENDLAND, 7.0 / (4.0 * math.pi)), (wl.CUBIC, 10.0 / (7.0 * math.pi))])
+def test_density_summation_lone_particle(orc, kernel, w0):
+    """Eq. 6 with the self term: a particle without neighbours has
+    rho = m W(0) = m w0 / h^2, w0 the unit-integral constant of the kernel."""
+    s = wl.lattice_block(1, 1, dx=0.02, kernel=kernel)
+    s.params.update(density=1, rho0=1000.0)
+    s.mass[:] = 0.4
+    r = orc.evaluate(s)
+    h = s.params["h"]
+    assert math.isclose(r["rho"][0], 0.4 * w0 / h ** 2, rel_tol=1e-14)
+
+
+def test_density_summation_lattice_interior(orc):
+    """Eq. 6 on a lattice of spacing dx with m = rho0 dx^2: the interior density
+    is rho0 dx^2 sum_lattice W, which tends to rho0 int W dA = rho0 as h/dx grows;
+    walls keep their continuity density (eq. 7) and the continuity rate is
+    still reported."""
+    got = []
+    for hf in (1.3, 2.0, 3.0):
+        dx = 0.01
+        s = wl.lattice_block(40, 40, dx=dx)
+        s.params.update(h=hf * dx, cell_size=2.2 * hf * dx, density=1, rho0=1000.0)
+        s.mass[:] = 1000.0 * dx * dx
+        s.rho[:] = 1003.0                 # ignored for fluid: the sum replaces it
+        s.type[:40] = wl.WALL             # the bottom row
+        r = orc.evaluate(s)
+        ctr = s.pos.mean(0)
+        inner = np.all(np.abs(s.pos - ctr) < 0.2 - 2.2 * hf * dx, axis=1)
+        assert np.ptp(r["rho"][inner]) < 1e-9
+        got.append(r["rho"][inner].mean() / 1000.0)
+        assert np.all(r["rho"][s.type == wl.WALL] == 1003.0)
+    assert abs(got[0] - 1.0105) < 5e-4                 # the lattice Shepard sum at h = 1.3 dx (Wendland)
+    assert abs(got[2] - 1.0) < 2e-3 and abs(got[2] - 1.0) < abs(got[0] - 1.0)
+
+
+def test_density_summation_in_the_time_loop(orc):
+    """Under eq. 6 the stored fluid density after a step is the sum at the
+    half-step positions, whatever the continuity rate. On a uniformly moving
+    lattice the half-step positions are the start positions translated by
+    dt/2 v (the predictor moves them with v alone), so the stored densities
+    equal the sums at the start -- while continuity (zero rate for a
+    translation) would have kept the input density 1."""
+    s = wl.lattice_block(12, 12, dx=1.0, vel=(0.3, -0.2))
+    s.params.update(density=1, dt_fixed=0.05, sigma=0.0)
+    r0 = orc.evaluate(s)
+    assert np.all(r0["drho"] == 0.0) and np.abs(r0["rho"] - 1.0).max() > 0.1
+    st = orc.State(s)
+    st.step(1)
+    assert np.allclose(st.rho, r0["rho"], rtol=0, atol=1e-13)
+
+
 def test_uniform_translation_keeps_density(orc):
     s = wl.lattice_block(25, 25, vel=(0.3, -0.2))
     r = orc.evaluate(s)
