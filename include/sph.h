@@ -120,6 +120,12 @@ typedef struct sph_params {
                               1: repulsive-force walls (eq. 29, see sph_set_wall_normals) */
     double wall_spacing;   /* repulsive walls: spacing of the wall particles along
                               the wall (0: h / 1.3) */
+    int32_t gravity_plane; /* 0: g acts on every fluid particle; 1: only on those whose
+                              coordinate along g, r . g/|g|, is at least gravity_from
+                              (a jet whose nozzle imposes its inflow speed, with g
+                              acting on the free jet beyond the nozzle exit) */
+    int32_t pad_;
+    double gravity_from;
 } sph_params;
 
 /* Per-context options. Zero-initialised options select the defaults. */
@@ -260,6 +266,23 @@ sph_status sph_restore(sph_ctx* ctx, const void* state, size_t bytes);
  * records each particle's candidate mask, and walks those masks as the main
  * and surface sweeps do, with the exact pair predicate. */
 sph_status sph_neighbors(sph_ctx* ctx, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total);
+
+/* Breakup length of every system at the current state (Section 3-2: the jet
+ * is broken where two particles consecutive along it are more than 1.5 h
+ * apart). The fluid particles whose coordinate along `axis` (2 FP64,
+ * xi = x axis[0] + y axis[1], no FMA) is at least xi_start[s] (the nozzle exit)
+ * are taken in order of xi; system s is broken where two consecutive ones are
+ * more than gap_h * h apart: length[s] is then the coordinate of the nearer one
+ * minus xi_start[s] and broken[s] = 1. Otherwise length[s] reaches the
+ * farthest such particle (0 if there is none) and broken[s] = 0.
+ *   axis: 2 doubles, a unit vector; xi_start, length: n_sys doubles; broken:
+ *   n_sys int32; gap_h >= 1 (the paper: 1.5).
+ * Waits for the stream; uses workspace of its own (bins of gap_h h / 2 along
+ * each system's box). Errors: SPH_EINVAL (NULL, an axis that is not a finite
+ * unit vector, a start that is not finite, gap_h < 1), SPH_ECAPACITY (fluid
+ * outside its box, which a step deactivates, reaching past the bins). */
+sph_status sph_breakup(sph_ctx* ctx, const double* axis, const double* xi_start, double gap_h,
+                       double* length, int32_t* broken);
 
 /* Wait for all enqueued work. */
 sph_status sph_sync(sph_ctx* ctx);

@@ -65,6 +65,8 @@ class Params(C.Structure):
         ("box_lo", C.c_double * 2), ("box_hi", C.c_double * 2), ("cell_size", C.c_double),
         ("piston_dir", C.c_double * 2), ("piston_u", C.c_double), ("piston_amp", C.c_double),
         ("piston_omega", C.c_double),
+        ("boundary", C.c_int32), ("gravity_plane", C.c_int32), ("wall_spacing", C.c_double),
+        ("gravity_from", C.c_double),
     ]
 
 
@@ -78,6 +80,10 @@ def _params(d: Dict) -> Params:
     p = Params()
     p.kernel = int(d["kernel"])
     p.density = int(d.get("density", 0))
+    p.boundary = int(d.get("boundary", 0))
+    p.gravity_plane = int(d.get("gravity_plane", 0))
+    p.wall_spacing = float(d.get("wall_spacing", 0.0))
+    p.gravity_from = float(d.get("gravity_from", 0.0))
     for k in ("h", "rho0", "c0", "gamma", "alpha", "eta2_h2", "sigma", "eps_h", "courant",
               "dt_fixed", "cell_size", "piston_u", "piston_amp", "piston_omega"):
         setattr(p, k, float(d[k]))
@@ -101,6 +107,7 @@ def _declare(L):
     L.orc_sort.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp]
     L.orc_eval.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
     L.orc_step.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+    L.orc_breakup.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
     L.orc_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_set_threads.restype = None
@@ -208,6 +215,21 @@ def evaluate(obj) -> Dict[str, np.ndarray]:
     lib().orc_eval(ns, _param_array(plist), _ptr(off), _ptr(pos), _ptr(vel), _ptr(rho),
                    _ptr(mass), _ptr(typ), C.byref(out))
     return res
+
+
+def breakup(obj, xi_start, axis=(1.0, 0.0), gap_h: float = 1.5):
+    """(length, broken) per system: the breakup criterion of Section 3-2 (see
+    orc_breakup in sph_oracle.h). xi_start: the start coordinate along the axis
+    (the nozzle exit), one per system or one for all."""
+    plist, off, (pos, vel, rho, mass, typ) = _unpack(obj)
+    ns = len(plist)
+    ax = np.ascontiguousarray(axis, dtype=np.float64)
+    xs = np.ascontiguousarray(np.broadcast_to(np.asarray(xi_start, dtype=np.float64), (ns,)))
+    length = np.zeros(ns)
+    broken = np.zeros(ns, dtype=np.int32)
+    lib().orc_breakup(ns, _param_array(plist), _ptr(off), _ptr(pos), _ptr(typ), _ptr(ax), _ptr(xs),
+                      float(gap_h), _ptr(length), _ptr(broken))
+    return length, broken
 
 
 class State:

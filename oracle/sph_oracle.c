@@ -446,9 +446,15 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
             }
             kap[a] = k_a;
             as[2 * a] = sx; as[2 * a + 1] = sy;
-            acc[2 * a] = apv[2 * a] + sx + p->gravity[0];
-            acc[2 * a + 1] = apv[2 * a + 1] + sy + p->gravity[1];
-            sacc[a] += scale_k + sqrt(p->gravity[0] * p->gravity[0] + p->gravity[1] * p->gravity[1]);
+            /* gravity everywhere, or beyond a plane normal to g */
+            double gx = p->gravity[0], gy = p->gravity[1];
+            if (p->gravity_plane) {
+                double gn = hypot(gx, gy);
+                if (!(pos[2 * a] * (gx / gn) + pos[2 * a + 1] * (gy / gn) >= p->gravity_from)) gx = gy = 0.0;
+            }
+            acc[2 * a] = apv[2 * a] + sx + gx;
+            acc[2 * a + 1] = apv[2 * a + 1] + sy + gy;
+            sacc[a] += scale_k + sqrt(gx * gx + gy * gy);
         }
 
         /* Time-step limits, eq. 30-32. */
@@ -597,4 +603,40 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
     free(ph); free(vh); free(rh); free(d0); free(a0); free(d1); free(a1); free(dt); free(dt_unused);
     free(re0); free(re1);
     return 0;
+}
+
+/* ------------------------------------------------------------ breakup */
+
+static int cmp_f64(const void* x, const void* y) {
+    double a = *(const double*)x, b = *(const double*)y;
+    return (a > b) - (a < b);
+}
+
+/* The breakup criterion of Section 3-2: two particles consecutive along the
+ * jet farther apart than the gap (1.5 h in the paper). Plain definition: sort
+ * the coordinates and look at consecutive differences. */
+void orc_breakup(int n_sys, const orc_params* prm, const int64_t* off, const double* pos,
+                 const int32_t* type, const double* axis, const double* xi_start, double gap_h,
+                 double* length, int32_t* broken) {
+    for (int s = 0; s < n_sys; ++s) {
+        int64_t o0 = off[s], o1 = off[s + 1], m = 0;
+        double* xi = (double*)malloc(sizeof(double) * (size_t)(o1 - o0 + 1));
+        for (int64_t a = o0; a < o1; ++a) {
+            if (type[a] != ORC_FLUID) continue;
+            double t = pos[2 * a] * axis[0] + pos[2 * a + 1] * axis[1];
+            if (t >= xi_start[s]) xi[m++] = t;
+        }
+        qsort(xi, (size_t)m, sizeof(double), cmp_f64);
+        double gap = gap_h * prm[s].h;
+        length[s] = m ? xi[m - 1] - xi_start[s] : 0.0;
+        broken[s] = 0;
+        for (int64_t i = 0; i + 1 < m; ++i) {
+            if (xi[i + 1] - xi[i] > gap) {
+                length[s] = xi[i] - xi_start[s];
+                broken[s] = 1;
+                break;
+            }
+        }
+        free(xi);
+    }
 }

@@ -37,6 +37,10 @@ typedef struct {
     double box_lo[2], box_hi[2];   /* fluid leaving this box becomes inactive */
     double cell_size;      /* cell edge of the linked-list grid */
     double piston_dir[2], piston_u, piston_amp, piston_omega;
+    int32_t boundary;      /* 0 dynamic boundary particles, 1 repulsive-force walls (eq. 29) */
+    int32_t gravity_plane; /* 1: g acts only on fluid with r . g/|g| >= gravity_from */
+    double wall_spacing;   /* spacing of the wall particles (repulsive walls) */
+    double gravity_from;
 } orc_params;
 
 enum { ORC_FLUID = 0, ORC_WALL = 1, ORC_PISTON = 2, ORC_INACTIVE = 3 };
@@ -95,6 +99,17 @@ int orc_eval(int n_sys, const orc_params* p, const int64_t* off, const double* p
 int orc_step(int n_sys, const orc_params* p, const int64_t* off, double* pos, double* vel,
              double* rho, const double* mass, int32_t* type, double* time, int nsteps,
              double* dt_out);
+
+/* Breakup length (Section 3-2): per system, the fluid particles whose
+ * coordinate along `axis`, xi = x axis_x + y axis_y (no FMA), is at least
+ * xi_start[s] are taken in order of xi; the jet is broken at the first pair of
+ * consecutive particles more than gap_h * h apart, and length[s] is the
+ * coordinate of the nearer one minus xi_start[s] (broken[s] = 1). Without such
+ * a gap, length[s] is that of the farthest particle (broken[s] = 0); without
+ * any such particle 0. */
+void orc_breakup(int n_sys, const orc_params* p, const int64_t* off, const double* pos,
+                 const int32_t* type, const double* axis, const double* xi_start, double gap_h,
+                 double* length, int32_t* broken);
 
 /* Number of OpenMP threads the oracle runs on, and a way to change it. */
 int orc_threads(void);

@@ -117,6 +117,9 @@ const char* check_params(const sph_params& p) {
     if (!(p.box_hi[0] > p.box_lo[0] && p.box_hi[1] > p.box_lo[1])) return "box_hi must exceed box_lo";
     if (!(p.cell_size > p.h)) return "cell_size must exceed h";
     if (!isfinite(p.gravity[0]) || !isfinite(p.gravity[1])) return "gravity must be finite";
+    if (p.gravity_plane != 0 && p.gravity_plane != 1) return "gravity_plane must be 0 or 1";
+    if (p.gravity_plane && !(p.gravity[0] != 0.0 || p.gravity[1] != 0.0)) return "gravity_plane needs a non-zero g";
+    if (p.gravity_plane && isnan(p.gravity_from)) return "gravity_from must not be NaN";
     return nullptr;
 }
 
@@ -127,6 +130,16 @@ Grid grid_of(const sph_params& p) {
     g.ny = (int64_t)floor((p.box_hi[1] - p.box_lo[1]) * inv) + 1;
     g.reach = p.cell_size > 2.0 * p.h ? 1 : 2;
     return g;
+}
+
+// Bins the breakup detector may need: per system, its box's diagonal in bins of
+// h/2 (the bins are half the gap, and the gap is at least h), plus a margin.
+uint64_t breakup_bins(int n_sys, const sph_params* p) {
+    uint64_t total = 0;
+    for (int s = 0; s < n_sys; ++s)
+        total += (uint64_t)ceil(hypot(p[s].box_hi[0] - p[s].box_lo[0], p[s].box_hi[1] - p[s].box_lo[1]) /
+                                (0.5 * p[s].h)) + 4;
+    return total;
 }
 
 sph_options resolve(const sph_options* o) {
@@ -178,6 +191,7 @@ struct sph_ctx {
     int (*nbr_fn)(sph_ctx*, int64_t*, int32_t*, int64_t, int64_t*) = nullptr;
     int (*closure_fn)(sph_ctx*, const float*) = nullptr;
     int (*restore_fn)(sph_ctx*, const void*, size_t) = nullptr;
+    int (*breakup_fn)(sph_ctx*, const double*, const double*, double, double*, int32_t*) = nullptr;
     int static_dev = -1;   // device whose static workspace this context holds (sph_init_static), else -1
 };
 
@@ -241,6 +255,9 @@ struct Impl : sph_ctx_base {
     double* time = nullptr;
     uint32_t* flags = nullptr;
     int64_t* dbg_start = nullptr;
+    unsigned long long* brk_sys = nullptr;    // breakup detector: per-system arrays
+    unsigned long long* brk_bins = nullptr;   // and its bins (minima, then maxima)
+    uint64_t brk_capacity = 0;
     int cur = 0;
     bool graphs = false;
     int graph_steps = 0;
@@ -259,7 +276,8 @@ struct Impl : sph_ctx_base {
     }
 
     // Lays out every buffer in the workspace (base == nullptr: size only).
-    size_t carve(char* base, int64_t n_, int n_sys_, uint32_t trash, int block_stream, bool with_closure) {
+    size_t carve(char* base, int64_t n_, int n_sys_, uint32_t trash, int block_stream, bool with_closure,
+                 uint64_t bins) {
         Carver cv{base};
         closure = with_closure;
         if (with_closure) {
@@ -329,6 +347,9 @@ struct Impl : sph_ctx_base {
         time = cv.take<double>(n_sys_);
         flags = cv.take<uint32_t>(4);
         dbg_start = cv.take<int64_t>(n_ + 1);
+        brk_sys = cv.take<unsigned long long>((size_t)8 * n_sys_ + 2);
+        brk_bins = cv.take<unsigned long long>(2 * bins);
+        brk_capacity = bins;
         return cv.off + 256;
     }
 
@@ -848,6 +869,72 @@ int restore_impl(sph_ctx* c, const void* blob, size_t bytes) {
     return SPH_OK;
 }
 
+// Host twin of the order-preserving map of FP64 values to 64-bit integers.
+static double from_ordered_host(unsigned long long k) {
+    const unsigned long long u = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    double x;
+    memcpy(&x, &u, 8);
+    return x;
+}
+
+template <typename T>
+int breakup_impl(sph_ctx* c, const double* axis, const double* xi_start, double gap_h, double* length,
+                 int32_t* broken) {
+    Impl<T>* m = impl_of<T>(c);
+    const int64_t n = m->n;
+    const int ns = m->n_sys;
+    unsigned long long* extent = m->brk_sys;
+    double* start = reinterpret_cast<double*>(extent + ns);
+    double* anchor = start + ns;
+    double* half_gap = anchor + ns;
+    double* gap = half_gap + ns;
+    double* len = gap + ns;
+    int32_t* brk = reinterpret_cast<int32_t*>(len + ns);
+    uint32_t* base = reinterpret_cast<uint32_t*>(brk + ns + (ns & 1));
+    // bins start at the nozzle exit or at the near edge of the box, whichever
+    // is farther along the axis: active fluid lies inside the box
+    std::vector<double> hs(xi_start, xi_start + ns), ha(ns), hg(ns), hh(ns);
+    for (int s = 0; s < ns; ++s) {
+        if (!isfinite(hs[s])) return fail(c, SPH_EINVAL, "xi_start must be finite");
+        const sph_params& q = c->params[s];
+        const double x0 = axis[0] >= 0 ? q.box_lo[0] : q.box_hi[0], y0 = axis[1] >= 0 ? q.box_lo[1] : q.box_hi[1];
+        ha[s] = std::max(hs[s], x0 * axis[0] + y0 * axis[1]);
+        hg[s] = gap_h * q.h;
+        hh[s] = 0.5 * hg[s];
+    }
+    hipStream_t st = c->stream;
+    const StateBuf<T>& S = m->buf[m->cur];
+    HIP_OK(hipMemcpyAsync(start, hs.data(), ns * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(anchor, ha.data(), ns * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(gap, hg.data(), ns * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(half_gap, hh.data(), ns * 8, hipMemcpyHostToDevice, st));
+    launch_breakup((int)n, ns, S.tag, S.pos, axis[0], axis[1], start, extent, st);
+    std::vector<unsigned long long> ext(ns);
+    HIP_OK(hipMemcpyAsync(ext.data(), extent, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    // bins of half the gap from each anchor to the system's farthest particle
+    std::vector<uint32_t> hb(ns + 1);
+    uint64_t total = 0;
+    for (int s = 0; s < ns; ++s) {
+        hb[s] = (uint32_t)total;
+        if (ext[s]) {
+            const double u = floor((from_ordered_host(ext[s]) - ha[s]) / hh[s]);
+            total += (u > 0.0 ? (uint64_t)u : 0ull) + 2;
+        }
+        if (total > m->brk_capacity)
+            return fail(c, SPH_ECAPACITY, "fluid beyond its box along the axis: more breakup bins than the workspace holds");
+    }
+    hb[ns] = (uint32_t)total;
+    HIP_OK(hipMemcpyAsync(base, hb.data(), (ns + 1) * 4, hipMemcpyHostToDevice, st));
+    launch_breakup_bins((int)n, ns, S.tag, S.pos, axis[0], axis[1], start, anchor, half_gap, gap, base,
+                        (uint32_t)total, m->brk_bins, m->brk_bins + total, len, brk, st);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(length, len, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(broken, brk, ns * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return SPH_OK;
+}
+
 template <typename T>
 SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     SysDev<T> s;
@@ -892,6 +979,13 @@ SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     s.gamma7 = p.gamma == 7.0 ? 1 : 0;
     s.closure = p.closure;
     s.density_sum = p.density;
+    s.g_plane = p.gravity_plane;
+    if (p.gravity_plane) {
+        const double gn = hypot(p.gravity[0], p.gravity[1]);
+        s.ghx = p.gravity[0] / gn;
+        s.ghy = p.gravity[1] / gn;
+        s.g_from = p.gravity_from;
+    }
     s.boundary = p.boundary;
     s.h64 = h;
     s.wnorm64 = wn;
@@ -954,11 +1048,12 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
         with_closure = with_closure || c->params[s2].closure != 0;
         m->density_sum = m->density_sum || c->params[s2].density != 0;
     }
-    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream, with_closure);
+    const uint64_t bins = breakup_bins(c->n_sys, c->params.data());
+    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream, with_closure, bins);
     if (ws_bytes < need)
         return fail(c, SPH_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws) & 255) return fail(c, SPH_EINVAL, "workspace must be 256-byte aligned");
-    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream, with_closure);
+    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream, with_closure, bins);
     if (with_closure) {
         // the stencil kernel builds four stencils per wave once two per wave
         // would more than fill the chip's wave slots (8 per SIMD, 4 SIMDs per CU)
@@ -1061,6 +1156,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     c->nbr_fn = nbr_impl<T>;
     c->closure_fn = closure_impl<T>;
     c->restore_fn = restore_impl<T>;
+    c->breakup_fn = breakup_impl<T>;
     return SPH_OK;
 }
 
@@ -1109,10 +1205,10 @@ sph_status sph_workspace_bytes(const sph_options* opt, int32_t n_sys, const sph_
     for (int s = 0; s < n_sys; ++s) with_closure = with_closure || p[s].closure != 0;
     if (o.dtype_bits == 32) {
         Impl<float> m;
-        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure);
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure, breakup_bins(n_sys, p));
     } else {
         Impl<double> m;
-        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure);
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure, breakup_bins(n_sys, p));
     }
     return SPH_OK;
 }
@@ -1209,6 +1305,15 @@ sph_status sph_state_bytes(const sph_ctx* c, size_t* bytes_out) {
 sph_status sph_restore(sph_ctx* c, const void* state, size_t bytes) {
     if (!c || !state) return fail(c, SPH_EINVAL, "ctx or state is NULL");
     return (sph_status)c->restore_fn(c, state, bytes);
+}
+
+sph_status sph_breakup(sph_ctx* c, const double* axis, const double* xi_start, double gap_h, double* length,
+                       int32_t* broken) {
+    if (!c || !axis || !xi_start || !length || !broken) return fail(c, SPH_EINVAL, "NULL argument");
+    if (!isfinite(axis[0]) || !isfinite(axis[1])) return fail(c, SPH_EINVAL, "axis must be finite");
+    if (fabs(axis[0] * axis[0] + axis[1] * axis[1] - 1.0) > 1e-12) return fail(c, SPH_EINVAL, "axis must be a unit vector");
+    if (!(gap_h >= 1.0) || !isfinite(gap_h)) return fail(c, SPH_EINVAL, "gap_h must be at least 1");
+    return (sph_status)c->breakup_fn(c, axis, xi_start, gap_h, length, broken);
 }
 
 sph_status sph_neighbors(sph_ctx* c, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total) {

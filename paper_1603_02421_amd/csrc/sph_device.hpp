@@ -72,6 +72,8 @@ struct SysDev {
     T closure_tol;
     int32_t density_sum;           // 1: eq. 6 for fluid particles
     int32_t boundary;              // 1: repulsive-force walls (eq. 29)
+    int32_t g_plane, pad2_;        // 1: g acts only where r . g_hat >= g_from
+    double ghx, ghy, g_from;
     double h64, wnorm64, rho0_64;  // FP64 copies for the density summation
     // time stepping (FP64)
     double courant, dt_fixed;
@@ -222,6 +224,14 @@ __device__ __forceinline__ T tait_pressure(const SysDev<T>& S, T dens) {
     T rho, pr;
     tait(S, dens, rho, pr);
     return pr * rho * rho;
+}
+
+// Whether gravity acts on a fluid particle at pa (everywhere, or beyond a plane
+// normal to g: r . g_hat >= g_from, formed without FMA as the oracle forms it).
+template <typename T>
+__device__ __forceinline__ bool gravity_on(const SysDev<T>& S, double2 pa) {
+#pragma clang fp contract(off)
+    return !S.g_plane || pa.x * S.ghx + pa.y * S.ghy >= S.g_from;
 }
 
 // ---------------------------------------------------------------- reductions

@@ -244,6 +244,13 @@ void launch_nbr_fill(const EvalView<T>& v, int a0, int a1, const int64_t* start,
                      hipStream_t st);
 template <typename T>
 void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* dens, T* out, hipStream_t st);
+// Breakup length: per-system extent along the axis, then the binned gap search.
+void launch_breakup(int n, int n_sys, const uint32_t* tag, const double2* pos, double ax, double ay,
+                    const double* start, unsigned long long* extent, hipStream_t st);
+void launch_breakup_bins(int n, int n_sys, const uint32_t* tag, const double2* pos, double ax, double ay,
+                         const double* start, const double* anchor, const double* half_gap, const double* gap,
+                         const uint32_t* bin_base, uint32_t n_bins, unsigned long long* bmin, unsigned long long* bmax,
+                         double* length, int32_t* broken, hipStream_t st);
 
 void launch_mlp_forward(const MlpView& W, const uint16_t* X, int64_t m, float* Y, int ystride, hipStream_t st);
 constexpr int MLP_GRAD_WAVES = 1024;

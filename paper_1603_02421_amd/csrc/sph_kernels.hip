@@ -804,8 +804,9 @@ __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32
         surf = fluid && mag > S.eps;
         if (fluid && !surf) {
             // no surface force: acceleration and curvature are final here
-            acc.x = ax + S.gx;
-            acc.y = ay + S.gy;
+            const bool gon = gravity_on(S, pa);
+            acc.x = ax + (gon ? S.gx : T(0));
+            acc.y = ay + (gon ? S.gy : T(0));
             const T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
             amf = am;
         } else {
@@ -938,8 +939,9 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
             const T kappa = num / den;
             v.kappa_plain[a] = kappa;
             T f = listed ? T(0) : -S.sigma * rcp(rho_a) * kappa;
-            acc.x += f * n_a.x + S.gx;
-            acc.y += f * n_a.y + S.gy;
+            const bool gon = gravity_on(S, pa);
+            acc.x += f * n_a.x + (gon ? S.gx : T(0));
+            acc.y += f * n_a.y + (gon ? S.gy : T(0));
             v.acc[a] = acc;
             v.kappa[a] = kappa;
             T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
@@ -1174,6 +1176,133 @@ __global__ void k_nbr_fill(EvalView<T> v, int a0, int a1, const int64_t* start, 
     int64_t k = start[a] - base;
     neighbours<T, 1>(v, S, (uint32_t)a, v.pos[a], [](uint32_t) { return 0; },
                      [&](uint32_t b, T, T, int) { out[k++] = v.id[b]; });
+}
+
+// ------------------------------------------------------------------ breakup length
+// The breakup criterion of Section 3-2: the jet is broken where two fluid
+// particles consecutive along its axis, beyond the nozzle exit, are more than
+// the gap (1.5 h) apart. The coordinates xi = p . axis are binned in bins of
+// half the gap: a larger gap always leaves a bin empty between its two ends,
+// and no gap inside a bin can exceed it, so the consecutive pairs that matter
+// are the maximum of a non-empty bin and the minimum of the next non-empty
+// one -- the same values a sort would put side by side. FP64 coordinates go
+// through an order-preserving map to 64-bit integers for the atomic extrema.
+
+__device__ __forceinline__ unsigned long long ordered_bits(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered(unsigned long long k) {
+    const unsigned long long u = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double((long long)u);
+}
+
+// The coordinate along the axis (no FMA, as the oracle forms it).
+__device__ __forceinline__ double axis_coord(double2 p, double ax, double ay) {
+#pragma clang fp contract(off)
+    return p.x * ax + p.y * ay;
+}
+
+// Per system: the largest coordinate of its fluid particles at or beyond the start.
+template <typename T>
+__global__ void k_breakup_extent(int n, const uint32_t* tag, const double2* pos, double ax, double ay,
+                                 const double* start, unsigned long long* extent) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const uint32_t t = tag[a];
+    if (tag_type(t) != T_FLUID) return;
+    const double xi = axis_coord(pos[a], ax, ay);
+    if (xi >= start[tag_sys(t)]) atomicMax(extent + tag_sys(t), ordered_bits(xi));
+}
+
+// Per bin of half the gap: the smallest and largest coordinate in it.
+template <typename T>
+__global__ void k_breakup_bins(int n, const uint32_t* tag, const double2* pos, double ax, double ay, const double* start,
+                               const double* anchor, const double* half_gap, const uint32_t* bin_base,
+                               unsigned long long* bmin, unsigned long long* bmax) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const uint32_t t = tag[a];
+    if (tag_type(t) != T_FLUID) return;
+    const uint32_t s = tag_sys(t);
+    const double xi = axis_coord(pos[a], ax, ay);
+    if (!(xi >= start[s])) return;
+    // bins counted from the anchor (the start, or the box's near edge beyond it)
+    const double u = floor((xi - anchor[s]) / half_gap[s]);
+    const uint32_t b = bin_base[s] + (uint32_t)(u > 0.0 ? u : 0.0);
+    atomicMin(bmin + b, ordered_bits(xi));
+    atomicMax(bmax + b, ordered_bits(xi));
+}
+
+// One workgroup per system: the first non-empty bin whose minimum lies more
+// than the gap beyond the maximum of the previous non-empty bin.
+__global__ void __launch_bounds__(1024) k_breakup_scan(const uint32_t* bin_base, const unsigned long long* bmin,
+                                                      const unsigned long long* bmax, const double* start,
+                                                      const double* gap, double* length, int32_t* broken) {
+    __shared__ int last_ne[1024];
+    __shared__ int found;
+    __shared__ unsigned long long tip;
+    const int s = blockIdx.x;
+    const int b0 = (int)bin_base[s], b1 = (int)bin_base[s + 1];
+    const int nt = (int)blockDim.x, t = (int)threadIdx.x;
+    const int chunk = (b1 - b0 + nt - 1) / nt;
+    const int i0 = b0 + t * chunk, i1 = min(i0 + chunk, b1);
+    if (t == 0) {
+        found = 0x7FFFFFFF;
+        tip = 0ull;
+    }
+    // the last non-empty bin of this thread's run of bins
+    int last = -1;
+    unsigned long long hi = 0ull;
+    for (int i = i0; i < i1; ++i) {
+        const unsigned long long m = bmax[i];
+        if (m != 0ull) {
+            last = i;
+            hi = m > hi ? m : hi;
+        }
+    }
+    last_ne[t] = last;
+    __syncthreads();
+    if (hi) atomicMax(&tip, hi);
+    // the last non-empty bin before this run: a maximum over the runs below
+    int prev = -1;
+    for (int k = 0; k < t; ++k) prev = last_ne[k] > prev ? last_ne[k] : prev;
+    const double g = gap[s];
+    for (int i = i0; i < i1; ++i) {
+        if (bmax[i] == 0ull) continue;
+        if (prev >= 0 && from_ordered(bmin[i]) - from_ordered(bmax[prev]) > g) {
+            atomicMin(&found, prev);
+            break;
+        }
+        prev = i;
+    }
+    __syncthreads();
+    if (t == 0) {
+        if (found != 0x7FFFFFFF) {
+            length[s] = from_ordered(bmax[found]) - start[s];
+            broken[s] = 1;
+        } else {
+            length[s] = tip ? from_ordered(tip) - start[s] : 0.0;
+            broken[s] = 0;
+        }
+    }
+}
+
+void launch_breakup(int n, int n_sys, const uint32_t* tag, const double2* pos, double ax, double ay,
+                    const double* start, unsigned long long* extent, hipStream_t st) {
+    launch_fill_u64(extent, (size_t)n_sys, 0ull, st);
+    k_breakup_extent<float><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, tag, pos, ax, ay, start, extent);
+}
+
+void launch_breakup_bins(int n, int n_sys, const uint32_t* tag, const double2* pos, double ax, double ay,
+                         const double* start, const double* anchor, const double* half_gap, const double* gap,
+                         const uint32_t* bin_base, uint32_t n_bins, unsigned long long* bmin, unsigned long long* bmax,
+                         double* length, int32_t* broken, hipStream_t st) {
+    launch_fill_u64(bmin, n_bins, ~0ull, st);
+    launch_fill_u64(bmax, n_bins, 0ull, st);
+    k_breakup_bins<float><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, tag, pos, ax, ay, start, anchor, half_gap,
+                                                                       bin_base, bmin, bmax);
+    k_breakup_scan<<<(unsigned)n_sys, 1024, 0, st>>>(bin_base, bmin, bmax, start, gap, length, broken);
 }
 
 // Derived per-slot quantities for sph_read.

@@ -28,7 +28,7 @@ STATIC_WORKSPACE_BYTES = 128 << 20   # SPH_STATIC_WORKSPACE_BYTES
 # Exported entry points, as declared in include/sph.h.
 EXPORTS = [
     "sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
-    "sph_sync", "sph_profile", "sph_autotune", "sph_state_bytes", "sph_restore", "sph_free", "sph_last_error", "sph_abi_version",
+    "sph_sync", "sph_profile", "sph_autotune", "sph_state_bytes", "sph_restore", "sph_breakup", "sph_free", "sph_last_error", "sph_abi_version",
     "sph_set_closure", "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
     "sph_mlp_train_step", "sph_mlp_params", "sph_mlp_free",
 ]
@@ -44,6 +44,7 @@ class SphParams(C.Structure):
         ("piston_dir", C.c_double * 2), ("piston_u", C.c_double), ("piston_amp", C.c_double),
         ("piston_omega", C.c_double), ("closure_tol", C.c_double),
         ("density", C.c_int32), ("boundary", C.c_int32), ("wall_spacing", C.c_double),
+        ("gravity_plane", C.c_int32), ("pad_", C.c_int32), ("gravity_from", C.c_double),
     ]
 
 
@@ -91,6 +92,7 @@ def load():
     L.sph_sync.argtypes = [vp]
     L.sph_state_bytes.argtypes = [vp, C.POINTER(sz)]
     L.sph_restore.argtypes = [vp, vp, sz]
+    L.sph_breakup.argtypes = [vp, vp, vp, C.c_double, vp, vp]
     L.sph_profile.argtypes = [vp, i32, i32, C.POINTER(C.c_char_p), vp, vp, C.POINTER(i32)]
     L.sph_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, i32, vp]
     L.sph_free.argtypes = [vp]
@@ -109,7 +111,7 @@ def load():
     L.sph_abi_version.restype = i32
     for name in ("sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read",
                  "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune", "sph_set_closure",
-                 "sph_state_bytes", "sph_restore",
+                 "sph_state_bytes", "sph_restore", "sph_breakup",
                  "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
                  "sph_mlp_train_step", "sph_mlp_params"):
         getattr(L, name).restype = i32
@@ -134,6 +136,8 @@ def params_struct(d) -> SphParams:
     p.density = int(d.get("density", 0))
     p.boundary = int(d.get("boundary", 0))
     p.wall_spacing = float(d.get("wall_spacing", 0.0))
+    p.gravity_plane = int(d.get("gravity_plane", 0))
+    p.gravity_from = float(d.get("gravity_from", 0.0))
     for k in ("gravity", "box_lo", "box_hi", "piston_dir"):
         arr = getattr(p, k)
         arr[0], arr[1] = float(d[k][0]), float(d[k][1])

@@ -153,6 +153,16 @@ class Simulation:
         native.check(self._L.sph_restore(self._ctx, _ptr(buf), buf.nbytes), self._ctx)
         return self
 
+    def breakup(self, xi_start, axis=(1.0, 0.0), gap_h: float = 1.5):
+        """(length, broken) per system: the breakup criterion (sph_breakup)."""
+        ax = np.ascontiguousarray(axis, dtype=np.float64)
+        xs = np.ascontiguousarray(np.broadcast_to(np.asarray(xi_start, dtype=np.float64), (self.n_sys,)))
+        length = np.zeros(self.n_sys)
+        broken = np.zeros(self.n_sys, dtype=np.int32)
+        native.check(self._L.sph_breakup(self._ctx, _ptr(ax), _ptr(xs), float(gap_h), _ptr(length), _ptr(broken)),
+                     self._ctx)
+        return length, broken
+
     def read_all(self, fields: Sequence[str] = ("pos", "vel", "rho", "type")) -> Dict[str, np.ndarray]:
         return {f: self.read(f) for f in fields}
 

@@ -637,6 +637,20 @@ def test_dt_quiescent_closed_form(orc):
     assert math.isclose(r["dt"][0], 0.2 * min(math.sqrt(h / 9.81), h / 3.0), rel_tol=1e-15)
 
 
+def test_gravity_beyond_a_plane(orc):
+    """With gravity_plane, g acts on the fluid particles whose coordinate along
+    g is at least gravity_from (the free jet beyond a nozzle whose inflow is
+    imposed) and on no other; at rho0 with alpha = sigma = 0 nothing else
+    accelerates a lattice."""
+    s = wl.lattice_block(20, 6, dx=1.0)
+    s.params.update(alpha=0.0, sigma=0.0, gravity=(0.0, -2.0), gravity_plane=1, gravity_from=-3.5)
+    r = orc.evaluate(s)
+    beyond = -s.pos[:, 1] >= -3.5          # y <= 3.5
+    assert beyond.sum() == 80
+    assert np.all(r["acc"][beyond] == [0.0, -2.0])
+    assert np.all(r["acc"][~beyond] == 0.0)
+
+
 def test_free_fall_is_exact(orc):
     """A lone fluid particle under gravity: the scheme is exact for constant
     acceleration, r = r0 + v0 t + g t^2 / 2."""

@@ -17,6 +17,7 @@ from .scenarios import (  # noqa: F401
     dam_break,
     rest_tank,
     jet,
+    paper_jet,
     batch_sweep,
     circle,
     sinusoid,

@@ -53,6 +53,11 @@ def default_params(h: float, rho0: float, c0: float, **kw) -> Dict:
         piston_u=0.0,
         piston_amp=0.0,
         piston_omega=0.0,
+        density=0,
+        boundary=0,
+        wall_spacing=0.0,
+        gravity_plane=0,
+        gravity_from=0.0,
     )
     p.update(kw)
     return p
@@ -280,7 +285,34 @@ def jet(n_target: int = 300_000, nD: int = 20, Re: float = 500.0, We: float = 20
         (pre, (1.0, 0.0), 1.0, FLUID),
         (walls, (0.0, 0.0), 1.0, WALL),
         (piston, (Up, 0.0), 1.0, PISTON),
-    ], name="jet", meta=dict(nD=nD, Re=Re, We=We, kD=kD, seed=seed, W=W, Lt=Lt, dx=dx))
+    ], name="jet", meta=dict(nD=nD, Re=Re, We=We, kD=kD, seed=seed, W=W, Lt=Lt, dx=dx, exit=t_plate))
+
+
+def paper_jet(u0: float, kernel: int = WENDLAND, nD: int = 20, seed: int = 0, n_target: int = 40_000,
+              free_length: float = 45.0, prefill: float = 1.0, D0: float = 0.01, kD: float = 0.7) -> System:
+    """A jet of the breakup study (Section 3-2) in the paper's units: orifice
+    D0 = 0.01 m resolved by nD particles (h = 1.3 dx), water (rho0 = 1000 kg/m^3,
+    sigma = 0.072 N/m), c0 = 10 m/s, alpha = 0.3, inflow speed u0 imposed by the
+    piston-driven tank of jet() (with its 1 % perturbation at k D0 = kD) and
+    g = 9.81 m/s^2 along the jet (+x), acting on the fluid beyond the orifice
+    exit, where the free jet starts (gravity_plane). The tank, the orifice and a
+    short pre-formed column of `prefill` D0 come from jet() scaled by D0 and u0."""
+    base = jet(n_target=n_target, nD=nD, Re=1.0, We=1.0, kD=kD, kernel=kernel, seed=seed,
+               free_length=free_length, prefill=prefill)
+    bp = base.params
+    dx = D0 / nD
+    h = 1.3 * dx
+    rho0 = 1000.0
+    exit_x = base.meta["exit"] * D0
+    p = default_params(h, rho0, 10.0, kernel=kernel, alpha=0.3, sigma=0.072, gravity=(9.81, 0.0),
+                       box_lo=(bp["box_lo"][0] * D0, bp["box_lo"][1] * D0),
+                       box_hi=(bp["box_hi"][0] * D0, bp["box_hi"][1] * D0), cell_size=2.2 * h,
+                       piston_dir=(1.0, 0.0), piston_u=bp["piston_u"] * u0, piston_amp=bp["piston_amp"],
+                       piston_omega=bp["piston_omega"] * u0 / D0, gravity_plane=1, gravity_from=exit_x)
+    n = base.n
+    mass = np.full(n, rho0 * dx * dx)
+    return System(p, base.pos * D0, base.vel * u0, np.full(n, rho0), mass, base.type.copy(), name="paper_jet",
+                  meta=dict(u0=u0, D0=D0, dx=dx, nD=nD, exit=exit_x, kernel=kernel, seed=seed))
 
 
 def batch_sweep(n_jets: int = 64, seed: int = 1234, n_range=(20_000, 400_000),
