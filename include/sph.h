@@ -117,7 +117,9 @@ typedef struct sph_params {
                               of the latest evaluation; the density check then has
                               no lower bound (a lone particle has m W(0)) */
     int32_t boundary;      /* 0: dynamic boundary particles (see the particle types);
-                              1: repulsive-force walls (eq. 29, see sph_set_wall_normals) */
+                              1: repulsive-force walls (eq. 29, see sph_set_wall_normals):
+                              boundary particles stay out of the cells and sums, and
+                              the system's NACTIVE counts its fluid only */
     double wall_spacing;   /* repulsive walls: spacing of the wall particles along
                               the wall (0: h / 1.3) */
     int32_t gravity_plane; /* 0: g acts on every fluid particle; 1: only on those whose
@@ -266,6 +268,28 @@ sph_status sph_restore(sph_ctx* ctx, const void* state, size_t bytes);
  * records each particle's candidate mask, and walks those masks as the main
  * and surface sweeps do, with the exact pair predicate. */
 sph_status sph_neighbors(sph_ctx* ctx, int64_t* start, int32_t* nbr, int64_t cap, int64_t* total);
+
+/* Repulsive-force walls (Section 2-6, eq. 29) for the systems with
+ * boundary = 1: the unit normal, pointing into the fluid, of every wall and
+ * piston particle (normals: 2n FP64 in particle-id order; entries of other
+ * particles are ignored; a boundary particle with a zero normal exerts no
+ * force). In such a system the boundary particles stay out of every SPH sum
+ * and exert on each fluid particle within 2h the force per unit mass
+ * f = n R(psi) P(xi) eps(z, u_perp) of eq. 29, whose functions the paper names
+ * without defining; they are taken from the published form of the method it
+ * cites (psi = (r_a - r_k) . n_k, xi the distance along the wall, c_a the
+ * fluid particle's sound speed, db = wall_spacing):
+ *   R = 0.01 c_a^2 / h (1 - q) / sqrt(q), q = psi / (2h), for 0 < psi < 2h;
+ *   P = (1 + cos(pi xi / db)) / 2 for xi < db (they sum to 1 along a straight
+ *       wall of spacing db);
+ *   eps = 1 + min(|20 u_perp| / c0, 1) for an approaching particle,
+ *       u_perp = (v_a - v_k) . n_k < 0, else 1.
+ * Wall densities do not evolve. The call records the boundary particles'
+ * current positions (pistons keep their prescribed motion); until it is made
+ * the walls exert no force. Waits for the stream. Errors: SPH_ESTATE (no
+ * system with boundary = 1), SPH_EINVAL (NULL, a non-zero normal that is not
+ * a unit vector). */
+sph_status sph_set_wall_normals(sph_ctx* ctx, const double* normals);
 
 /* Breakup length of every system at the current state (Section 3-2: the jet
  * is broken where two particles consecutive along it are more than 1.5 h

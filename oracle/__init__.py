@@ -105,8 +105,8 @@ def _declare(L):
     L.orc_neighbors.restype = C.c_int64
     L.orc_neighbors.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, vp, vp, C.c_int64]
     L.orc_sort.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp]
-    L.orc_eval.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.orc_step.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+    L.orc_eval.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_step.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
     L.orc_breakup.argtypes = [C.c_int, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
     L.orc_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
@@ -125,6 +125,16 @@ def lib():
 
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _wall_normals(obj):
+    """The boundary particles' unit normals (meta["wall_normal"], n x 2) of a
+    System or of every System of a Batch, or None if none carries them."""
+    systems = obj.systems if hasattr(obj, "systems") else [obj]
+    if not any("wall_normal" in s.meta for s in systems):
+        return None
+    return np.ascontiguousarray(np.concatenate(
+        [s.meta.get("wall_normal", np.zeros((s.n, 2))) for s in systems]), dtype=np.float64)
 
 
 def _unpack(obj):
@@ -212,8 +222,9 @@ def evaluate(obj) -> Dict[str, np.ndarray]:
         s_drho=np.zeros(n), s_acc=np.zeros(n), s_nrm=np.zeros(n),
         dt_f=np.zeros(ns), dt_cv=np.zeros(ns), dt=np.zeros(ns), rho=np.zeros(n))
     out = EvalOut(**{k: _ptr(v).value if v is not None else None for k, v in res.items()})
+    wn = _wall_normals(obj)
     lib().orc_eval(ns, _param_array(plist), _ptr(off), _ptr(pos), _ptr(vel), _ptr(rho),
-                   _ptr(mass), _ptr(typ), C.byref(out))
+                   _ptr(mass), _ptr(typ), _ptr(wn), C.byref(out))
     return res
 
 
@@ -242,11 +253,12 @@ class State:
         self.time = np.zeros(len(self.plist))
         self.dt = np.zeros(len(self.plist))
         self._P = _param_array(self.plist)
+        self.wall_normal = _wall_normals(obj)
 
     def step(self, nsteps: int = 1):
         lib().orc_step(len(self.plist), self._P, _ptr(self.off), _ptr(self.pos), _ptr(self.vel),
-                       _ptr(self.rho), _ptr(self.mass), _ptr(self.type), _ptr(self.time),
-                       int(nsteps), _ptr(self.dt))
+                       _ptr(self.rho), _ptr(self.mass), _ptr(self.type), _ptr(self.wall_normal),
+                       _ptr(self.time), int(nsteps), _ptr(self.dt))
         return self
 
 

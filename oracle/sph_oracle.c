@@ -138,7 +138,12 @@ static int64_t cell_coord(double x, double lo, double inv, int64_t ncell) {
     return (int64_t)t;
 }
 
-static int is_active(int32_t t) { return t != ORC_INACTIVE; }
+/* Whether a particle enters the SPH sums of its system: every active one, but
+ * for repulsive-force walls (eq. 29) only the fluid -- walls act on the fluid
+ * through the wall force alone. */
+static int in_sums(const orc_params* p, int32_t t) {
+    return t != ORC_INACTIVE && !(p->boundary == 1 && t != ORC_FLUID);
+}
 
 /* The pair predicate: r_ab^2 < (2h)^2 in FP64, squares summed left to right. */
 static int within(const double* pos, int64_t a, int64_t b, double R2) {
@@ -164,10 +169,10 @@ static void system_neighbors(const orc_params* p, int64_t o0, int64_t o1, const 
     if (brute) {
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t a = o0; a < o1; ++a) {
-            if (!is_active(type[a])) { if (!fill) count_or_start[a] = 0; continue; }
+            if (!in_sums(p, type[a])) { if (!fill) count_or_start[a] = 0; continue; }
             int64_t k = fill ? count_or_start[a] : 0;
             for (int64_t b = o0; b < o1; ++b) {
-                if (b == a || !is_active(type[b])) continue;
+                if (b == a || !in_sums(p, type[b])) continue;
                 if (within(pos, a, b, R2)) {
                     if (fill) nbr[k] = (int32_t)b;
                     ++k;
@@ -192,7 +197,7 @@ static void system_neighbors(const orc_params* p, int64_t o0, int64_t o1, const 
         int64_t i = a - o0;
         cx[i] = cell_coord(pos[2 * a], p->box_lo[0], inv, nx);
         cy[i] = cell_coord(pos[2 * a + 1], p->box_lo[1], inv, ny);
-        if (!is_active(type[a])) { next[i] = -2; continue; }
+        if (!in_sums(p, type[a])) { next[i] = -2; continue; }
         int64_t c = cx[i] * ny + cy[i];
         next[i] = head[c];
         head[c] = i;
@@ -200,7 +205,7 @@ static void system_neighbors(const orc_params* p, int64_t o0, int64_t o1, const 
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t a = o0; a < o1; ++a) {
         int64_t i = a - o0;
-        if (!is_active(type[a])) { if (!fill) count_or_start[a] = 0; continue; }
+        if (!in_sums(p, type[a])) { if (!fill) count_or_start[a] = 0; continue; }
         int64_t k0 = fill ? count_or_start[a] : 0, k = k0;
         for (int64_t X = cx[i] - reach; X <= cx[i] + reach; ++X) {
             if (X < 0 || X >= nx) continue;
@@ -270,7 +275,7 @@ void orc_sort(int n_sys, const orc_params* p, const int64_t* off, const double* 
         double inv = 1.0 / p[s].cell_size;
         for (int64_t a = off[s]; a < off[s + 1]; ++a) {
             kv[a].id = a;
-            if (!is_active(type[a])) { kv[a].key = trash; continue; }
+            if (!in_sums(&p[s], type[a])) { kv[a].key = trash; continue; }
             int64_t X = cell_coord(pos[2 * a], p[s].box_lo[0], inv, nx);
             int64_t Y = cell_coord(pos[2 * a + 1], p[s].box_lo[1], inv, ny);
             kv[a].key = sys_base[s] + (uint64_t)(X * ny + Y);
@@ -285,13 +290,53 @@ void orc_sort(int n_sys, const orc_params* p, const int64_t* off, const double* 
     free(sys_base);
 }
 
+/* ------------------------------------------------------------ repulsive walls */
+
+/* Force per unit mass on fluid particle a from the repulsive-force walls of its
+ * system (eq. 29, f = n R(psi) P(xi) eps(z, u_perp)). The paper names the three
+ * functions without defining them (its references are missing); they are read
+ * as the published forms of those references:
+ *   psi = (r_a - r_k) . n_k (normal distance), xi = |(r_a - r_k) - psi n_k|;
+ *   R(psi) = A (1 - q) / sqrt(q), q = psi / (2h), A = 0.01 c_a^2 / h, for 0 < psi < 2h;
+ *   P(xi) = (1 + cos(pi xi / db)) / 2 for xi < db, db the wall-particle spacing, so
+ *   that the P of equally spaced wall particles sum to 1 wherever the fluid
+ *   particle is along a straight wall (the force does not ripple along it);
+ *   eps = eps(z) + eps(u_perp), eps(z) = 1 (no still-water depth in these runs),
+ *   eps(u_perp) = 0 for u_perp = (v_a - v_k) . n_k >= 0, else min(|20 u_perp| / c0, 1).
+ * sf receives the sum of the magnitudes (error scale). */
+static void wall_force(const orc_params* p, int64_t o0, int64_t o1, int64_t a, const double* pos,
+                       const double* vel, const int32_t* type, const double* wn, double c_a,
+                       double* fx, double* fy, double* sf) {
+    double h = p->h, db = p->wall_spacing > 0.0 ? p->wall_spacing : h / 1.3;
+    double A = 0.01 * c_a * c_a / h;
+    for (int64_t k = o0; k < o1; ++k) {
+        if (type[k] != ORC_WALL && type[k] != ORC_PISTON) continue;
+        double nx = wn[2 * k], ny = wn[2 * k + 1];
+        double dx = pos[2 * a] - pos[2 * k], dy = pos[2 * a + 1] - pos[2 * k + 1];
+        double psi = dx * nx + dy * ny;
+        if (!(psi > 0.0 && psi < 2.0 * h)) continue;
+        double tx = dx - psi * nx, ty = dy - psi * ny;
+        double xi = sqrt(tx * tx + ty * ty);
+        if (!(xi < db)) continue;
+        double q = psi / (2.0 * h);
+        double R = A * (1.0 - q) / sqrt(q);
+        double P = 0.5 * (1.0 + cos(PI * xi / db));
+        double up = (vel[2 * a] - vel[2 * k]) * nx + (vel[2 * a + 1] - vel[2 * k + 1]) * ny;
+        double eu = up >= 0.0 ? 0.0 : fmin(fabs(20.0 * up) / p->c0, 1.0);
+        double f = R * P * (1.0 + eu);
+        *fx += f * nx;
+        *fy += f * ny;
+        *sf += fabs(f);
+    }
+}
+
 /* ------------------------------------------------------------ evaluation */
 
 static double dot2(double ax, double ay, double bx, double by) { return ax * bx + ay * by; }
 
 int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double* pos,
              const double* vel, const double* rho_in, const double* mass, const int32_t* type,
-             const orc_eval_out* out) {
+             const double* wall_normal, const orc_eval_out* out) {
     int64_t n = off[n_sys];
     int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
     int64_t total = orc_neighbors(n_sys, prm, off, pos, type, 0, start, NULL, 0);
@@ -347,7 +392,7 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
         /* Colour function, eq. 14, over every active particle, self included. */
 #pragma omp parallel for schedule(dynamic, 128)
         for (int64_t a = o0; a < o1; ++a) {
-            if (!is_active(type[a])) { C[a] = 0.0; continue; }
+            if (!in_sums(p, type[a])) { C[a] = 0.0; continue; }
             double sum = mass[a] / rho[a] * W0;
             for (int64_t k = start[a]; k < start[a + 1]; ++k) {
                 int64_t b = nbr[k];
@@ -362,7 +407,7 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
          * interface normal (eq. 18) and the signal term of eq. 31. */
 #pragma omp parallel for schedule(dynamic, 128)
         for (int64_t a = o0; a < o1; ++a) {
-            if (!is_active(type[a])) continue;
+            if (!in_sums(p, type[a])) continue;
             int fluid = type[a] == ORC_FLUID;
             double d = 0.0, sd = 0.0, ax = 0.0, ay = 0.0, sa = 0.0;
             double nx = 0.0, ny = 0.0, sn = 0.0, vmax = 0.0;
@@ -446,21 +491,24 @@ int orc_eval(int n_sys, const orc_params* prm, const int64_t* off, const double*
             }
             kap[a] = k_a;
             as[2 * a] = sx; as[2 * a + 1] = sy;
+            /* repulsive-force walls (eq. 29) */
+            double fx = 0.0, fy = 0.0, sf = 0.0;
+            if (p->boundary == 1 && wall_normal) wall_force(p, o0, o1, a, pos, vel, type, wall_normal, c[a], &fx, &fy, &sf);
             /* gravity everywhere, or beyond a plane normal to g */
             double gx = p->gravity[0], gy = p->gravity[1];
             if (p->gravity_plane) {
                 double gn = hypot(gx, gy);
                 if (!(pos[2 * a] * (gx / gn) + pos[2 * a + 1] * (gy / gn) >= p->gravity_from)) gx = gy = 0.0;
             }
-            acc[2 * a] = apv[2 * a] + sx + gx;
-            acc[2 * a + 1] = apv[2 * a + 1] + sy + gy;
-            sacc[a] += scale_k + sqrt(gx * gx + gy * gy);
+            acc[2 * a] = apv[2 * a] + sx + gx + fx;
+            acc[2 * a + 1] = apv[2 * a + 1] + sy + gy + fy;
+            sacc[a] += scale_k + sqrt(gx * gx + gy * gy) + sf;
         }
 
         /* Time-step limits, eq. 30-32. */
         double dtf = INFINITY, dtcv = INFINITY;
         for (int64_t a = o0; a < o1; ++a) {
-            if (!is_active(type[a])) continue;
+            if (!in_sums(p, type[a])) continue;
             double v = h / (c[a] + vs[a]);
             if (v < dtcv) dtcv = v;
             if (type[a] != ORC_FLUID) continue;
@@ -513,8 +561,8 @@ static double piston_speed(const orc_params* p, double t) {
 }
 
 int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, double* vel,
-             double* rho, const double* mass, int32_t* type, double* time, int nsteps,
-             double* dt_out) {
+             double* rho, const double* mass, int32_t* type, const double* wall_normal, double* time,
+             int nsteps, double* dt_out) {
     int64_t n = off[n_sys];
     double* ph = (double*)malloc(sizeof(double) * (size_t)(2 * n));
     double* vh = (double*)malloc(sizeof(double) * (size_t)(2 * n));
@@ -532,7 +580,7 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
         orc_eval_out o0;
         memset(&o0, 0, sizeof o0);
         o0.drho = d0; o0.acc = a0; o0.dt = dt; o0.rho = re0;
-        orc_eval(n_sys, prm, off, pos, vel, rho, mass, type, &o0);
+        orc_eval(n_sys, prm, off, pos, vel, rho, mass, type, wall_normal, &o0);
 
         /* predictor: half step */
         for (int s = 0; s < n_sys; ++s) {
@@ -545,8 +593,10 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
                 vh[2 * a] = vel[2 * a]; vh[2 * a + 1] = vel[2 * a + 1];
                 rh[a] = rho[a];
                 if (type[a] == ORC_INACTIVE) continue;
-                /* a summed density is recomputed by the next evaluation */
+                /* a summed density is recomputed by the next evaluation; a
+                 * repulsive wall's density does not evolve */
                 if (p->density == 1 && type[a] == ORC_FLUID) rh[a] = re0[a];
+                else if (p->boundary == 1 && type[a] != ORC_FLUID) rh[a] = rho[a];
                 else rh[a] = rho[a] + hdt * d0[a];
                 if (type[a] != ORC_FLUID && rh[a] < p->rho0) rh[a] = p->rho0;  /* walls only repel */
                 if (type[a] == ORC_FLUID) {
@@ -566,7 +616,7 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
         orc_eval_out o1;
         memset(&o1, 0, sizeof o1);
         o1.drho = d1; o1.acc = a1; o1.dt = dt_unused; o1.rho = re1;
-        orc_eval(n_sys, prm, off, ph, vh, rh, mass, type, &o1);
+        orc_eval(n_sys, prm, off, ph, vh, rh, mass, type, wall_normal, &o1);
 
         /* corrector: full step from state n with the half-step derivatives */
         for (int s = 0; s < n_sys; ++s) {
@@ -578,6 +628,7 @@ int orc_step(int n_sys, const orc_params* prm, const int64_t* off, double* pos, 
                 if (type[a] == ORC_INACTIVE) continue;
                 /* summation: the density of the latest (half-step) evaluation */
                 if (p->density == 1 && type[a] == ORC_FLUID) rho[a] = re1[a];
+                else if (p->boundary == 1 && type[a] != ORC_FLUID) rho[a] = rho[a];
                 else rho[a] = rho[a] + T * d1[a];
                 if (type[a] != ORC_FLUID && rho[a] < p->rho0) rho[a] = p->rho0;  /* walls only repel */
                 if (type[a] == ORC_FLUID) {

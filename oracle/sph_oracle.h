@@ -89,16 +89,18 @@ int64_t orc_neighbors(int n_sys, const orc_params* p, const int64_t* off, const 
 void orc_sort(int n_sys, const orc_params* p, const int64_t* off, const double* pos,
               const int32_t* type, uint64_t* keys_sorted, int64_t* perm);
 
-/* One evaluation of every right-hand side at the given state. */
+/* One evaluation of every right-hand side at the given state. wall_normal
+ * (2n, may be NULL): the unit normal, into the fluid, of every boundary
+ * particle of a system with repulsive-force walls (boundary = 1). */
 int orc_eval(int n_sys, const orc_params* p, const int64_t* off, const double* pos,
              const double* vel, const double* rho, const double* mass, const int32_t* type,
-             const orc_eval_out* out);
+             const double* wall_normal, const orc_eval_out* out);
 
 /* nsteps predictor-corrector steps in place (time per system advanced). dt_out
  * (n_sys, may be NULL) receives the last step's dt. */
 int orc_step(int n_sys, const orc_params* p, const int64_t* off, double* pos, double* vel,
-             double* rho, const double* mass, int32_t* type, double* time, int nsteps,
-             double* dt_out);
+             double* rho, const double* mass, int32_t* type, const double* wall_normal,
+             double* time, int nsteps, double* dt_out);
 
 /* Breakup length (Section 3-2): per system, the fluid particles whose
  * coordinate along `axis`, xi = x axis_x + y axis_y (no FMA), is at least

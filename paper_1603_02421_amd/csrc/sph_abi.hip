@@ -142,6 +142,38 @@ uint64_t breakup_bins(int n_sys, const sph_params* p) {
     return total;
 }
 
+// Workspace of the repulsive-force walls (systems with boundary = 1): per
+// such system two grids of cells of 2h + db over its box with a margin of a
+// cell, and room for a record per particle of the system.
+struct WallPlan {
+    uint64_t cells = 0, records = 0;
+    bool any = false;
+};
+
+double wall_db(const sph_params& p) { return p.wall_spacing > 0 ? p.wall_spacing : p.h / 1.3; }
+
+void wall_grid(const sph_params& p, double& x0, double& y0, double& cs, int32_t& nx, int32_t& ny) {
+    cs = 2.0 * p.h + wall_db(p);
+    x0 = p.box_lo[0] - cs;
+    y0 = p.box_lo[1] - cs;
+    nx = (int32_t)ceil((p.box_hi[0] - p.box_lo[0]) / cs) + 3;
+    ny = (int32_t)ceil((p.box_hi[1] - p.box_lo[1]) / cs) + 3;
+}
+
+WallPlan wall_plan(int n_sys, const sph_params* p, const int64_t* off) {
+    WallPlan w;
+    for (int s = 0; s < n_sys; ++s) {
+        if (p[s].boundary != 1) continue;
+        double x0, y0, cs;
+        int32_t nx, ny;
+        wall_grid(p[s], x0, y0, cs, nx, ny);
+        w.cells += 2ull * (uint64_t)nx * (uint64_t)ny;
+        w.records += (uint64_t)(off[s + 1] - off[s]);
+        w.any = true;
+    }
+    return w;
+}
+
 sph_options resolve(const sph_options* o) {
     sph_options r;
     memset(&r, 0, sizeof r);
@@ -192,6 +224,7 @@ struct sph_ctx {
     int (*closure_fn)(sph_ctx*, const float*) = nullptr;
     int (*restore_fn)(sph_ctx*, const void*, size_t) = nullptr;
     int (*breakup_fn)(sph_ctx*, const double*, const double*, double, double*, int32_t*) = nullptr;
+    int (*walls_fn)(sph_ctx*, const double*) = nullptr;
     int static_dev = -1;   // device whose static workspace this context holds (sph_init_static), else -1
 };
 
@@ -255,6 +288,13 @@ struct Impl : sph_ctx_base {
     double* time = nullptr;
     uint32_t* flags = nullptr;
     int64_t* dbg_start = nullptr;
+    // repulsive-force walls (some system has boundary = 1)
+    bool repulsive = false;
+    WallSys* wall_sys = nullptr;
+    uint32_t* wall_cstart = nullptr;
+    double4* wall_rec = nullptr;
+    V2<T>* fwall = nullptr;
+    uint64_t wall_cells = 0;
     unsigned long long* brk_sys = nullptr;    // breakup detector: per-system arrays
     unsigned long long* brk_bins = nullptr;   // and its bins (minima, then maxima)
     uint64_t brk_capacity = 0;
@@ -277,7 +317,7 @@ struct Impl : sph_ctx_base {
 
     // Lays out every buffer in the workspace (base == nullptr: size only).
     size_t carve(char* base, int64_t n_, int n_sys_, uint32_t trash, int block_stream, bool with_closure,
-                 uint64_t bins) {
+                 uint64_t bins, const WallPlan& wp) {
         Carver cv{base};
         closure = with_closure;
         if (with_closure) {
@@ -350,6 +390,14 @@ struct Impl : sph_ctx_base {
         brk_sys = cv.take<unsigned long long>((size_t)8 * n_sys_ + 2);
         brk_bins = cv.take<unsigned long long>(2 * bins);
         brk_capacity = bins;
+        repulsive = wp.any;
+        if (wp.any) {
+            wall_sys = cv.take<WallSys>(n_sys_);
+            wall_cstart = cv.take<uint32_t>(wp.cells + 1);
+            wall_rec = cv.take<double4>(wp.records ? wp.records : 1);
+            fwall = cv.take<V2<T>>(n_);
+            wall_cells = wp.cells;
+        }
         return cv.off + 256;
     }
 
@@ -403,6 +451,7 @@ struct Impl : sph_ctx_base {
         v.dens_out = half ? dens_h : S.dens;
         v.vol_out = vol;
         v.density_sum = density_sum ? 1 : 0;
+        v.fwall = fwall;
         return v;
     }
 
@@ -410,7 +459,11 @@ struct Impl : sph_ctx_base {
     void evaluate(bool half, bool do_dt, hipStream_t st, KernelTimer* kt) {
         if (closure) launch_fill_u32(cl.count, 1, 0u, st);
         EvalView<T> v = eval_view(half, do_dt);
-        launch_eval<T>(L, v, st, kt);
+        // the wall force runs whenever some system has repulsive walls: the step
+        // graphs are captured before sph_set_wall_normals fills the grids,
+        // which are empty (no force) until then
+        WallView W{wall_sys, wall_cstart, wall_rec, time, dt, half ? 1 : 0, 0};
+        launch_eval<T>(L, v, repulsive ? &W : nullptr, st, kt);
         if (closure) launch_closure<T>(v, cl, net.view(), cl.capacity, st, kt);
     }
 
@@ -869,6 +922,88 @@ int restore_impl(sph_ctx* c, const void* blob, size_t bytes) {
     return SPH_OK;
 }
 
+// The repulsive-force walls' grids from the boundary particles' current
+// positions (pistons at their travel now) and the caller's normals.
+template <typename T>
+int walls_impl(sph_ctx* c, const double* normals) {
+    Impl<T>* m = impl_of<T>(c);
+    if (!m->repulsive) return fail(c, SPH_ESTATE, "no system of this context has repulsive-force walls");
+    const int64_t n = m->n;
+    const int ns = m->n_sys;
+    hipStream_t st = c->stream;
+    const StateBuf<T>& S = m->buf[m->cur];
+    std::vector<uint32_t> ids(n), tags(n);
+    std::vector<double2> pos(n);
+    std::vector<double> time(ns);
+    HIP_OK(hipMemcpyAsync(ids.data(), S.id, n * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(tags.data(), S.tag, n * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(pos.data(), S.pos, n * 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(time.data(), m->time, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    std::vector<WallSys> ws(ns);
+    std::vector<uint32_t> cstart(m->wall_cells + 1, 0);
+    std::vector<double4> rec;
+    uint32_t cell_off = 0;
+    // slots of every system's boundary particles with a normal, by grid
+    std::vector<std::vector<uint32_t>> members(2 * ns);
+    for (int64_t j = 0; j < n; ++j) {
+        const uint32_t ty = tags[j] & 15u, s = tags[j] >> 4;
+        if ((ty != SPH_WALL && ty != SPH_PISTON) || c->params[s].boundary != 1) continue;
+        const double nx = normals[2 * (size_t)ids[j]], ny = normals[2 * (size_t)ids[j] + 1];
+        if (nx == 0.0 && ny == 0.0) continue;
+        if (!isfinite(nx) || !isfinite(ny) || fabs(nx * nx + ny * ny - 1.0) > 1e-6)
+            return fail(c, SPH_EINVAL, "wall normal of particle " + std::to_string(ids[j]) + " is not a unit vector");
+        members[2 * s + (ty == SPH_PISTON ? 1 : 0)].push_back((uint32_t)j);
+    }
+    for (int s = 0; s < ns; ++s) {
+        const sph_params& p = c->params[s];
+        WallSys& G = ws[s];
+        memset(&G, 0, sizeof G);
+        if (p.boundary != 1) continue;
+        double cs;
+        wall_grid(p, G.x0, G.y0, cs, G.nx, G.ny);
+        G.inv_cs = 1.0 / cs;
+        G.db = wall_db(p);
+        const double tm = time[s];
+        G.x_ref = p.piston_omega == 0.0 ? p.piston_u * tm
+                                         : p.piston_u * (tm + p.piston_amp * (1.0 - cos(p.piston_omega * tm)) / p.piston_omega);
+        const uint32_t cells = (uint32_t)G.nx * (uint32_t)G.ny;
+        for (int g = 0; g < 2; ++g) {
+            G.cell_base[g] = cell_off;
+            // counting sort of the grid's records by cell
+            std::vector<uint32_t> cell_of;
+            for (uint32_t j : members[2 * s + g]) {
+                int cx = (int)floor((pos[j].x - G.x0) * G.inv_cs), cy = (int)floor((pos[j].y - G.y0) * G.inv_cs);
+                cx = std::min(std::max(cx, 0), G.nx - 1);
+                cy = std::min(std::max(cy, 0), G.ny - 1);
+                cell_of.push_back((uint32_t)cx * (uint32_t)G.ny + (uint32_t)cy);
+            }
+            std::vector<uint32_t> count(cells + 1, 0);
+            for (uint32_t k : cell_of) ++count[k + 1];
+            for (uint32_t k = 0; k < cells; ++k) count[k + 1] += count[k];
+            const uint32_t r0 = (uint32_t)rec.size();
+            rec.resize(rec.size() + cell_of.size());
+            std::vector<uint32_t> fillp(count.begin(), count.end() - 1);
+            for (size_t i = 0; i < cell_of.size(); ++i) {
+                const uint32_t j = members[2 * s + g][i];
+                double4 r;
+                r.x = pos[j].x;
+                r.y = pos[j].y;
+                r.z = normals[2 * (size_t)ids[j]];
+                r.w = normals[2 * (size_t)ids[j] + 1];
+                rec[r0 + fillp[cell_of[i]]++] = r;
+            }
+            for (uint32_t k = 0; k <= cells; ++k) cstart[cell_off + k] = r0 + count[k];
+            cell_off += cells;
+        }
+    }
+    HIP_OK(hipMemcpyAsync(m->wall_sys, ws.data(), ns * sizeof(WallSys), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(m->wall_cstart, cstart.data(), cstart.size() * 4, hipMemcpyHostToDevice, st));
+    if (!rec.empty()) HIP_OK(hipMemcpyAsync(m->wall_rec, rec.data(), rec.size() * sizeof(double4), hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return SPH_OK;
+}
+
 // Host twin of the order-preserving map of FP64 values to 64-bit integers.
 static double from_ordered_host(unsigned long long k) {
     const unsigned long long u = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
@@ -1049,11 +1184,12 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
         m->density_sum = m->density_sum || c->params[s2].density != 0;
     }
     const uint64_t bins = breakup_bins(c->n_sys, c->params.data());
-    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream, with_closure, bins);
+    const WallPlan wp = wall_plan(c->n_sys, c->params.data(), c->offsets.data());
+    size_t need = m->carve(nullptr, c->n, c->n_sys, trash, c->opt.block_stream, with_closure, bins, wp);
     if (ws_bytes < need)
         return fail(c, SPH_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws) & 255) return fail(c, SPH_EINVAL, "workspace must be 256-byte aligned");
-    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream, with_closure, bins);
+    m->carve(static_cast<char*>(ws), c->n, c->n_sys, trash, c->opt.block_stream, with_closure, bins, wp);
     if (with_closure) {
         // the stencil kernel builds four stencils per wave once two per wave
         // would more than fill the chip's wave slots (8 per SIMD, 4 SIMDs per CU)
@@ -1108,6 +1244,11 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     launch_fill_u64(reinterpret_cast<unsigned long long*>(m->time), c->n_sys, 0ull, st);
     launch_fill_u32(m->flags, 4, 0u, st);
     launch_fill_u64(m->skin_max, c->n_sys + 1, 0ull, st);
+    if (m->repulsive) {   // no wall records until sph_set_wall_normals
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->fwall), n * sizeof(V2<T>) / 4, 0u, st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(m->wall_sys), c->n_sys * sizeof(WallSys) / 4, 0u, st);
+        launch_fill_u32(m->wall_cstart, m->wall_cells + 1, 0u, st);
+    }
     launch_fill_u32(m->sb.cell, n, 0u, st);
     // the padding past the last position is read (and ignored) by the candidate scan
     for (double2* p : {m->buf[0].pos, m->buf[1].pos, m->pos_h})
@@ -1157,6 +1298,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     c->closure_fn = closure_impl<T>;
     c->restore_fn = restore_impl<T>;
     c->breakup_fn = breakup_impl<T>;
+    c->walls_fn = walls_impl<T>;
     return SPH_OK;
 }
 
@@ -1205,10 +1347,12 @@ sph_status sph_workspace_bytes(const sph_options* opt, int32_t n_sys, const sph_
     for (int s = 0; s < n_sys; ++s) with_closure = with_closure || p[s].closure != 0;
     if (o.dtype_bits == 32) {
         Impl<float> m;
-        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure, breakup_bins(n_sys, p));
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure, breakup_bins(n_sys, p),
+                             wall_plan(n_sys, p, offsets));
     } else {
         Impl<double> m;
-        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure, breakup_bins(n_sys, p));
+        *bytes_out = m.carve(nullptr, n, n_sys, base[n_sys], o.block_stream, with_closure, breakup_bins(n_sys, p),
+                             wall_plan(n_sys, p, offsets));
     }
     return SPH_OK;
 }
@@ -1305,6 +1449,11 @@ sph_status sph_state_bytes(const sph_ctx* c, size_t* bytes_out) {
 sph_status sph_restore(sph_ctx* c, const void* state, size_t bytes) {
     if (!c || !state) return fail(c, SPH_EINVAL, "ctx or state is NULL");
     return (sph_status)c->restore_fn(c, state, bytes);
+}
+
+sph_status sph_set_wall_normals(sph_ctx* c, const double* normals) {
+    if (!c || !normals) return fail(c, SPH_EINVAL, "ctx or normals is NULL");
+    return (sph_status)c->walls_fn(c, normals);
 }
 
 sph_status sph_breakup(sph_ctx* c, const double* axis, const double* xi_start, double gap_h, double* length,

@@ -54,6 +54,25 @@ struct SortBufs {
     uint32_t* surf_count;     // SURF_REGIONS surface-list counters (cleared with the wave table)
 };
 
+// Repulsive-force walls of one system: two static cell grids (fixed walls,
+// then pistons) of the boundary particles' positions (pistons at their travel
+// x_ref) and normals, built on the host by sph_set_wall_normals.
+struct WallSys {
+    double x0, y0, inv_cs, db, x_ref;
+    int32_t nx, ny;
+    uint32_t cell_base[2];   // first cell-start entry of each grid
+};
+
+struct WallView {
+    const WallSys* sys;
+    const uint32_t* cstart;  // per cell of every grid: first record (+ one past the last)
+    const double4* rec;      // x, y, n_x, n_y
+    const double* time;      // the systems' time and last dt: the evaluation's time
+    const double* dt;
+    int half;                // 1 in the half-step evaluation
+    int pad_;
+};
+
 // What the three sweeps read and write.
 template <typename T>
 struct EvalView {
@@ -99,6 +118,7 @@ struct EvalView {
     T* vol_out;                  // its m / rho (= vol)
     int density_sum;             // some system uses the density summation (eq. 6)
     int pad4_;
+    V2<T>* fwall;                // repulsive-force walls: force per unit mass on each fluid slot
     uint32_t* cl_count;          // closure list (null when no system uses the closure)
     uint32_t* cl_list;
     uint32_t cl_capacity;
@@ -225,7 +245,7 @@ template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
                  T* vol, hipStream_t st, KernelTimer* kt);
 template <typename T>
-void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt);
+void launch_eval(const LaunchCfg& L, const EvalView<T>& v, const WallView* W, hipStream_t st, KernelTimer* kt);
 template <typename T>
 void launch_dt(int n_sys, const SysDev<T>* sys, const uint32_t* chunk_base, const double* dt_wave,
                unsigned long long* dtmin, double* dt, unsigned long long* skin_max, hipStream_t st,

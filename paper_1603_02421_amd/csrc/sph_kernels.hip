@@ -162,8 +162,9 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(uint32_t* in, uint3
 // ------------------------------------------------------------------ sort
 // Cell key of every slot, slot within its cell (atomic counter: only a place
 // for the particle's id, the order inside a cell is fixed by k_permute), and
-// per-workgroup counts of inactive particles (their order comes from a stable
-// compaction).
+// per-workgroup counts of particles outside the cells -- inactive ones and the
+// walls of repulsive-force systems -- whose order comes from a stable
+// compaction.
 
 template <typename T>
 __global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uint32_t* tag,
@@ -174,7 +175,9 @@ __global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uin
     uint32_t k = trash;
     if (i < n) {
         uint32_t t = tag[i];
-        if (tag_type(t) != T_INACTIVE) {
+        // repulsive-force walls stay out of the cells, like inactive particles:
+        // they act on the fluid only through the wall force (eq. 29)
+        if (tag_type(t) != T_INACTIVE && !(sys[tag_sys(t)].boundary && tag_type(t) != T_FLUID)) {
             const SysDev<T>& S = sys[tag_sys(t)];
             double2 p = pos[i];
             int cx = cell_coord(p.x, S.x0, S.inv_s, S.nx);
@@ -557,6 +560,78 @@ __device__ __forceinline__ void for_outran_chunks(const EvalView<T>& v, Fn&& bod
 template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; uint32_t tag; };
 template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 
+// Repulsive-force walls (eq. 29): the force per unit mass on every fluid
+// particle of a system with boundary = 1, f = n R(psi) P(xi) eps(z, u_perp)
+// summed over the system's wall and piston particles within reach, in FP64.
+// The paper names R, P and eps without defining them; the published forms of
+// the references it cites are used (psi = (r_a - r_k) . n_k, xi the distance
+// along the wall):
+//   R = 0.01 c_a^2 / h (1 - q) / sqrt(q), q = psi / (2h), for 0 < psi < 2h;
+//   P = (1 + cos(pi xi / db)) / 2 for xi < db, db the wall-particle spacing (the
+//       P of equally spaced wall particles sum to 1 along a straight wall);
+//   eps = 1 + min(|20 u_perp| / c0, 1) when u_perp = (v_a - v_k) . n_k < 0, else 1
+//       (no still-water depth: the depth term is taken as 1).
+// Walls and pistons sit in two static cell grids per system (cells of
+// 2h + db, so a 3 x 3 block covers the reach); a piston moves rigidly, so its
+// records are looked up at the fluid particle's position less the piston's
+// travel since the grids were built.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wall_force(EvalView<T> v, WallView W) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= v.n) return;
+    const uint32_t t = v.tag[a];
+    if (tag_type(t) != T_FLUID) return;
+    const int sys = (int)tag_sys(t);
+    const SysDev<T>& S = v.sys[sys];
+    if (!S.boundary) return;
+    const WallSys& G = W.sys[sys];
+    const double2 pa = v.pos[a];
+    const V2<T> va = v.vel[a];
+    const double rho = S.rho0_64 + (double)v.dens[a];
+    const double r3 = rho / S.rho0_64;
+    const double c = S.gamma7 ? (double)S.c0 * r3 * r3 * r3 : (double)S.c0 * pow(r3, (double)S.half_gm1);
+    const double A = 0.01 * c * c / S.h64;
+    const double two_h = 2.0 * S.h64;
+    // the evaluation's time: the piston's travel and speed at it
+    const double tm = W.time[sys] + (W.half ? 0.5 * W.dt[sys] : 0.0);
+    const double X = S.pomega == 0.0 ? S.pu * tm : S.pu * (tm + S.pamp * (1.0 - cos(S.pomega * tm)) / S.pomega);
+    const double U = S.pu * (1.0 + S.pamp * sin(S.pomega * tm));
+    double fx = 0.0, fy = 0.0;
+    for (int g = 0; g < 2; ++g) {
+        const double sx = g ? (X - G.x_ref) * S.pdx : 0.0, sy = g ? (X - G.x_ref) * S.pdy : 0.0;
+        const double ux = g ? U * S.pdx : 0.0, uy = g ? U * S.pdy : 0.0;
+        const double qx = pa.x - sx, qy = pa.y - sy;   // in the grid's frame
+        const int cx = (int)floor((qx - G.x0) * G.inv_cs), cy = (int)floor((qy - G.y0) * G.inv_cs);
+        for (int X2 = cx - 1; X2 <= cx + 1; ++X2) {
+            if (X2 < 0 || X2 >= G.nx) continue;
+            const uint32_t row = G.cell_base[g] + (uint32_t)X2 * (uint32_t)G.ny;
+            const int y0 = cy - 1 < 0 ? 0 : cy - 1, y1 = cy + 1 > G.ny - 1 ? G.ny - 1 : cy + 1;
+            if (y0 > y1) continue;
+            for (uint32_t k = W.cstart[row + y0]; k < W.cstart[row + y1 + 1]; ++k) {
+                const double4 w = W.rec[k];   // position in the grid's frame, unit normal
+                const double dx = qx - w.x, dy = qy - w.y;
+                const double psi = dx * w.z + dy * w.w;
+                if (!(psi > 0.0 && psi < two_h)) continue;
+                const double tx = dx - psi * w.z, ty = dy - psi * w.w;
+                const double xi = sqrt(tx * tx + ty * ty);
+                if (!(xi < G.db)) continue;
+                const double q = psi / two_h;
+                const double R = A * (1.0 - q) / sqrt(q);
+                const double P = 0.5 * (1.0 + cos(3.14159265358979323846 * xi / G.db));
+                const double up = ((double)va.x - ux) * w.z + ((double)va.y - uy) * w.w;
+                const double eu = up >= 0.0 ? 0.0 : fmin(fabs(20.0 * up) / (double)S.c0, 1.0);
+                const double f = R * P * (1.0 + eu);
+                fx += f * w.z;
+                fy += f * w.w;
+            }
+        }
+    }
+    V2<T> out;
+    out.x = (T)fx;
+    out.y = (T)fy;
+    v.fwall[a] = out;
+}
+
 // Density summation (eq. 6) for the fluid particles of systems that use it:
 // rho_a = sum_b m_b W_ab over every active particle of the system, itself
 // included, summed in FP64 whatever the storage type -- the stored rho - rho0
@@ -802,6 +877,11 @@ __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32
         cvs = c_a + vsig;
         const T mag = sqrt_(nx * nx + ny * ny);
         surf = fluid && mag > S.eps;
+        if (S.boundary && fluid) {   // repulsive-force walls (eq. 29), from k_wall_force
+            const V2<T> fw = v.fwall[a];
+            ax += fw.x;
+            ay += fw.y;
+        }
         if (fluid && !surf) {
             // no surface force: acceleration and curvature are final here
             const bool gon = gravity_on(S, pa);
@@ -1055,8 +1135,10 @@ __global__ void k_predict(IntegView<T> v) {
     T hdt = (T)hd;
     double2 p = v.pos[a];
     V2<T> u = v.vel[a];
-    // a summed density (eq. 6) is recomputed by the half-step evaluation
-    T dh = (ty == T_FLUID && S.density_sum) ? v.dens[a] : v.dens[a] + hdt * v.drho[a];
+    // a summed density (eq. 6) is recomputed by the half-step evaluation; a
+    // repulsive-force wall's density does not evolve
+    const bool frozen = (ty == T_FLUID && S.density_sum) || (ty != T_FLUID && S.boundary);
+    T dh = frozen ? v.dens[a] : v.dens[a] + hdt * v.drho[a];
     if (ty != T_FLUID && dh < T(0)) dh = T(0);   // boundaries never below rho0: they only repel
     v.dens_h[a] = dh;
     v.vol[a] = particle_vol(S, dh, v.mass[a]);
@@ -1109,12 +1191,13 @@ __global__ void k_correct(IntegView<T> v) {
     T tdt = (T)dt;
     // eq. 6: the density of the half-step evaluation; eq. 7 otherwise
     const bool summed = ty == T_FLUID && S.density_sum;
-    T dens = summed ? v.dens_h[a] : dens0 + tdt * drho;
+    const bool wall_f = ty != T_FLUID && S.boundary;   // repulsive-force wall: density fixed
+    T dens = summed ? v.dens_h[a] : (wall_f ? dens0 : dens0 + tdt * drho);
     if (ty != T_FLUID && dens < T(0)) dens = T(0);   // boundaries never below rho0
     v.dens[a] = dens;
     uint32_t flags = 0;
     if (!isfinite(dens)) flags |= FLAG_NONFINITE;
-    else if ((!summed && dens < T(-0.5) * S.rho0) || dens > S.rho0) flags |= FLAG_DENSITY;
+    else if (!wall_f && ((!summed && dens < T(-0.5) * S.rho0) || dens > S.rho0)) flags |= FLAG_DENSITY;
     if (ty == T_FLUID) {
         p.x = p.x + dt * ((double)u.x + 0.5 * dt * (double)acc.x);
         p.y = p.y + dt * ((double)u.y + 0.5 * dt * (double)acc.y);
@@ -1395,7 +1478,7 @@ static unsigned surface_blocks(int64_t n) {
 }
 
 template <typename T>
-void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, KernelTimer* kt) {
+void launch_eval(const LaunchCfg& L, const EvalView<T>& v, const WallView* W, hipStream_t st, KernelTimer* kt) {
     const int bs = L.block_sweep;
     const int64_t max_waves = ((int64_t)L.n + 63) / 64 + v.n_sys;
     const unsigned nb = nblk(max_waves, bs / 64);
@@ -1405,6 +1488,11 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, hipStream_t st, Kerne
     if (v.density_sum) {
         kt->begin("density", st);
         k_density<T><<<nb, bs, 0, st>>>(v);
+        kt->end(st);
+    }
+    if (W) {   // repulsive-force walls: their force, from this evaluation's state
+        kt->begin("wall_force", st);
+        k_wall_force<T><<<nblk(L.n, 256), 256, 0, st>>>(v, *W);
         kt->end(st);
     }
     if (!v.smask) {
@@ -1492,7 +1580,8 @@ void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* 
 #define SPHJET_INSTANTIATE(T)                                                                               \
     template void launch_sort<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,        \
                                  StateBuf<T>, T*, hipStream_t, KernelTimer*);                              \
-    template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, hipStream_t, KernelTimer*);         \
+    template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, const WallView*, hipStream_t,      \
+                                 KernelTimer*);                                                            \
     template void launch_dt<T>(int, const SysDev<T>*, const uint32_t*, const double*, unsigned long long*, \
                                double*, unsigned long long*, hipStream_t,                                  \
                                KernelTimer*);                                                              \

@@ -28,7 +28,8 @@ STATIC_WORKSPACE_BYTES = 128 << 20   # SPH_STATIC_WORKSPACE_BYTES
 # Exported entry points, as declared in include/sph.h.
 EXPORTS = [
     "sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read", "sph_neighbors",
-    "sph_sync", "sph_profile", "sph_autotune", "sph_state_bytes", "sph_restore", "sph_breakup", "sph_free", "sph_last_error", "sph_abi_version",
+    "sph_sync", "sph_profile", "sph_autotune", "sph_state_bytes", "sph_restore", "sph_breakup",
+    "sph_set_wall_normals", "sph_free", "sph_last_error", "sph_abi_version",
     "sph_set_closure", "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
     "sph_mlp_train_step", "sph_mlp_params", "sph_mlp_free",
 ]
@@ -93,6 +94,7 @@ def load():
     L.sph_state_bytes.argtypes = [vp, C.POINTER(sz)]
     L.sph_restore.argtypes = [vp, vp, sz]
     L.sph_breakup.argtypes = [vp, vp, vp, C.c_double, vp, vp]
+    L.sph_set_wall_normals.argtypes = [vp, vp]
     L.sph_profile.argtypes = [vp, i32, i32, C.POINTER(C.c_char_p), vp, vp, C.POINTER(i32)]
     L.sph_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, i32, vp]
     L.sph_free.argtypes = [vp]
@@ -111,7 +113,7 @@ def load():
     L.sph_abi_version.restype = i32
     for name in ("sph_workspace_bytes", "sph_init", "sph_init_static", "sph_step", "sph_evaluate", "sph_read",
                  "sph_neighbors", "sph_sync", "sph_profile", "sph_autotune", "sph_set_closure",
-                 "sph_state_bytes", "sph_restore", "sph_breakup",
+                 "sph_state_bytes", "sph_restore", "sph_breakup", "sph_set_wall_normals",
                  "sph_mlp_workspace_bytes", "sph_mlp_create", "sph_mlp_forward", "sph_mlp_gradient",
                  "sph_mlp_train_step", "sph_mlp_params"):
         getattr(L, name).restype = i32

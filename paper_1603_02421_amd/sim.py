@@ -41,6 +41,14 @@ def _unpack(obj):
             np.ascontiguousarray(typ, dtype=np.int32))
 
 
+def _wall_normals(obj):
+    """meta["wall_normal"] (n x 2) of a System, or of a Batch's systems."""
+    systems = obj.systems if hasattr(obj, "systems") else (list(obj) if isinstance(obj, (list, tuple)) else [obj])
+    if not any("wall_normal" in getattr(s, "meta", {}) for s in systems):
+        return None
+    return np.concatenate([s.meta.get("wall_normal", np.zeros((s.n, 2))) for s in systems])
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
@@ -98,6 +106,16 @@ class Simulation:
                                     _ptr(mass), _ptr(typ), C.c_void_p(self.workspace.data_ptr()),
                                     self.workspace_bytes, handle, C.byref(ctx)))
         self._ctx = ctx
+        normals = _wall_normals(systems)
+        if normals is not None and any(int(d.get("boundary", 0)) == 1 for d in plist):
+            self.set_wall_normals(normals)
+
+    def set_wall_normals(self, normals: np.ndarray) -> "Simulation":
+        """Unit normals of the boundary particles of repulsive-force systems (n x 2)."""
+        w = np.ascontiguousarray(normals, dtype=np.float64)
+        assert w.shape == (self.n, 2)
+        native.check(self._L.sph_set_wall_normals(self._ctx, _ptr(w)), self._ctx)
+        return self
 
     # -- stepping -------------------------------------------------------
     def step(self, n: int = 1) -> "Simulation":

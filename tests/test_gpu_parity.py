@@ -244,6 +244,73 @@ def test_density_summation_trajectory(gpu, orc, name):
     assert ep <= tol and er <= tol and ev <= tol
 
 
+@pytest.mark.parametrize("bits", [64, 32])
+def test_repulsive_wall_force_closed_form(gpu, bits):
+    """Eq. 29 through the C-ABI on a lone particle by a straight wall (the
+    oracle's pin case): R(psi) (1 + eps(u_perp)) along the normal, whatever the
+    offset along the wall; walls stay out of the SPH sums."""
+    import test_oracle_pins as pins
+    h = 1.3 * 0.01
+    tol = 1e-12 if bits == 64 else 2e-6
+    for psi_h, xi_frac, u_perp in ((0.1, 0.0, 0.0), (0.5, 0.3, -0.05), (1.0, 0.5, 0.05), (1.7, 0.25, -2.0)):
+        s = pins.wall_case(psi_h * h, xi_frac, u_perp)
+        s = wl.round_for_dtype(s, bits)
+        with _sim(gpu, s, bits=bits) as sim:
+            sim.evaluate()
+            acc = sim.read("accel")
+        eps = 0.0 if u_perp >= 0 else min(20 * abs(u_perp) / 10.0, 1.0)
+        want = pins.wall_R(psi_h * h) * (1.0 + eps)
+        say(f"[wall force] bits={bits} psi={psi_h}h xi={xi_frac}db u={u_perp}: {acc[0]} vs {want}")
+        assert abs(acc[0, 1] - want) <= tol * want and abs(acc[0, 0]) <= tol * want
+
+
+def _piston_box():
+    """A lattice of fluid pushed along x by a piston of force particles (eq. 29)."""
+    dx = 1.0
+    fluid = wl.scenarios._lattice(0.0, 0.0, 12, 8, dx)
+    piston = np.stack([np.full(12, -0.5 * dx), (np.arange(12) - 2 + 0.5) * dx], axis=1)
+    p = wl.scenarios.default_params(1.3 * dx, 1.0, 10.0, alpha=0.1, sigma=0.0, boundary=1, wall_spacing=dx,
+                                    piston_u=0.8, piston_dir=(1.0, 0.0), box_lo=(-10.0, -10.0),
+                                    box_hi=(40.0, 20.0))
+    s = wl.scenarios._assemble(p, [(fluid, (0.0, 0.0), 1.0, wl.FLUID), (piston, (0.8, 0.0), 1.0, wl.PISTON)])
+    nrm = np.zeros((s.n, 2))
+    nrm[s.type == wl.PISTON] = [1.0, 0.0]
+    s.meta["wall_normal"] = nrm
+    return s
+
+
+@pytest.mark.parametrize("case", ["dam_break", "piston_box"])
+def test_repulsive_walls_evaluation_and_trajectory(gpu, orc, case):
+    obj = wl.dam_break(repulsive=True) if case == "dam_break" else _piston_box()
+    say(f"[repulsive walls] case={case} n={obj.n}")
+    with _sim(gpu, obj, bits=64) as sim:
+        g = gpu_eval(sim)
+    o = orc.evaluate(obj)
+    start, nbr = orc.neighbors(obj)
+    rep = compare_eval(g, o, _eps_per_particle(obj), start, nbr, 1e-10, obj.type == wl.FLUID)
+    say("  ", rep)
+    fl = obj.type == wl.FLUID
+    assert np.abs(o["acc"][fl]).max() > 0
+    st = orc.State(obj)
+    steps = 100
+    with _sim(gpu, obj, bits=64) as sim:
+        sim.step(steps)
+        st.step(steps)
+        ep, er, ev = _traj_errors(sim, st, obj.meta.get("dx", 1.0), obj.params["rho0"])
+        assert np.array_equal(sim.read("type"), st.type)
+    say(f"   {steps} steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
+    assert ep <= 1e-9 and er <= 1e-9 and ev <= 1e-9
+
+
+def test_repulsive_dam_break_fp32(gpu, orc):
+    obj = wl.round_for_dtype(wl.dam_break(repulsive=True), 32)
+    with _sim(gpu, obj, bits=32) as sim:
+        g = gpu_eval(sim)
+    o = orc.evaluate(obj)
+    start, nbr = orc.neighbors(obj)
+    say("  ", compare_eval(g, o, _eps_per_particle(obj), start, nbr, 1e-5, obj.type == wl.FLUID))
+
+
 def _traj_errors(sim, st, dx, rho0):
     pos, vel, rho = sim.read("pos"), sim.read("vel"), sim.read("rho")
     act = st.type != wl.INACTIVE

@@ -50,6 +50,13 @@ MUTANTS = {
     "eq6_volume_for_mass": ("sum += mass[b] * orc_kernel_w(K, sqrt(rx * rx + ry * ry), h);",
                             "sum += mass[b] / rho[b] * orc_kernel_w(K, sqrt(rx * rx + ry * ry), h);",
                             [(pins.test_density_summation_lattice_interior, {})]),
+    # eq. 29: repulsive-force walls
+    "eq29_P_period": ("double P = 0.5 * (1.0 + cos(PI * xi / db));", "double P = 0.5 * (1.0 + cos(2.0 * PI * xi / db));",
+                      [(pins.test_wall_force_closed_form, dict(psi_h=0.5, xi_frac=0.3, u_perp=0.0))]),
+    "eq29_R_without_sqrt": ("double R = A * (1.0 - q) / sqrt(q);", "double R = A * (1.0 - q) / q;",
+                            [(pins.test_wall_force_closed_form, dict(psi_h=0.5, xi_frac=0.0, u_perp=0.0))]),
+    "eq29_eps_when_receding": ("double eu = up >= 0.0 ? 0.0", "double eu = up <= 0.0 ? 0.0",
+                               [(pins.test_wall_force_closed_form, dict(psi_h=0.5, xi_frac=0.0, u_perp=-0.05))]),
     # eq. 14, 18, 23, 24: colour, normal, curvature, surface force
     "eq14_no_self": ("double sum = mass[a] / rho[a] * W0;", "double sum = 0.0;",
                      [(pins.test_colour_bulk_and_surface, {})]),

@@ -622,6 +622,72 @@ def test_sinusoid_curvature(orc, A, lam):
     assert 0.8 < slope < 1.1
 
 
+# ------------------------------------------------- repulsive-force walls
+
+def wall_case(psi, xi_frac, u_perp, vertical=False, db_factor=1.0):
+    """One fluid particle at distance psi from a straight wall of particles
+    spaced db (= dx), offset xi_frac db along it from the nearest one, moving
+    with u_perp along the wall's normal; SI-like units. vertical: the wall is
+    the line x = 0 with normal +x instead of y = 0 with normal +y."""
+    dx = 0.01
+    k = np.arange(-20, 21) * dx * db_factor
+    wall = np.stack([k, np.zeros_like(k)], axis=1)
+    fluid = np.array([[xi_frac * dx * db_factor, psi]])
+    vel = np.array([0.0, u_perp])
+    if vertical:
+        wall, fluid, vel = wall[:, ::-1].copy(), fluid[:, ::-1].copy(), vel[::-1].copy()
+    p = wl.scenarios.default_params(1.3 * dx, 1000.0, 10.0, alpha=0.3, sigma=0.0, boundary=1,
+                                    wall_spacing=dx * db_factor, box_lo=(-1.0, -1.0), box_hi=(1.0, 1.0))
+    s = wl.scenarios._assemble(p, [(fluid, vel, 1000.0, wl.FLUID), (wall, (0.0, 0.0), 1000.0, wl.WALL)])
+    nrm = np.zeros((s.n, 2))
+    nrm[1:] = [1.0, 0.0] if vertical else [0.0, 1.0]
+    s.meta["wall_normal"] = nrm
+    return s
+
+
+def wall_R(psi, h=1.3 * 0.01, c=10.0):
+    q = psi / (2 * h)
+    return 0.01 * c * c / h * (1 - q) / math.sqrt(q) if 0 < q < 1 else 0.0
+
+
+@pytest.mark.parametrize("psi_h", [0.1, 0.5, 1.0, 1.7])
+@pytest.mark.parametrize("xi_frac", [0.0, 0.3, 0.5])
+@pytest.mark.parametrize("u_perp", [0.0, 0.05, -0.05, -2.0])
+def test_wall_force_closed_form(orc, psi_h, xi_frac, u_perp):
+    """The repulsive force of eq. 29 on a lone particle by a straight wall (no
+    other force acts: walls leave the SPH sums, P = 0 at rho0): along the
+    normal, R(psi) (1 + eps(u_perp)) with R = 0.01 c^2/h (1 - q)/sqrt(q),
+    whatever the offset along the wall (the P of the wall particles sum to 1),
+    eps = 0 receding and min(20 |u_perp| / c0, 1) approaching."""
+    h = 1.3 * 0.01
+    s = wall_case(psi_h * h, xi_frac, u_perp)
+    r = orc.evaluate(s)
+    eps = 0.0 if u_perp >= 0 else min(20 * abs(u_perp) / 10.0, 1.0)
+    want = wall_R(psi_h * h) * (1.0 + eps)
+    assert r["acc"][0, 0] == pytest.approx(0.0, abs=1e-9 * want)
+    assert r["acc"][0, 1] == pytest.approx(want, rel=1e-12)
+    # the walls are outside the SPH sums: the colour is the particle's own term
+    assert r["colour"][0] == pytest.approx(7 / (4 * math.pi * h * h) * 0.1 * 0.1 * 1e-2, rel=1e-12)
+    assert np.all(r["acc"][1:] == 0.0) and np.all(r["drho"] == 0.0)
+
+
+def test_wall_force_range_and_orientation(orc):
+    h = 1.3 * 0.01
+    for psi in (2.0 * h, 2.5 * h, -0.3 * h):        # beyond the range, or behind the wall
+        r = orc.evaluate(wall_case(psi, 0.2, 0.0))
+        assert np.all(r["acc"][0] == 0.0)
+    r = orc.evaluate(wall_case(0.6 * h, 0.25, -0.1, vertical=True))
+    want = wall_R(0.6 * h) * (1.0 + 0.2)
+    assert r["acc"][0, 0] == pytest.approx(want, rel=1e-12) and abs(r["acc"][0, 1]) <= 1e-9 * want
+
+
+def test_repulsive_walls_are_outside_the_cell_sort(orc):
+    s = wall_case(0.5 * 1.3 * 0.01, 0.0, 0.0)
+    keys, perm = orc.sort(s)
+    nx, ny = orc.grid(s.params)
+    assert perm[0] == 0 and np.all(keys[1:] == nx * ny)   # the walls go where inactive particles go
+
+
 # ----------------------------------------------------------- time stepping
 
 def test_dt_quiescent_closed_form(orc):

@@ -147,14 +147,16 @@ def hydrostatic_density(y: np.ndarray, surface_y: float, rho0: float, c0: float,
 
 def dam_break(dx: float = 0.01, column=(0.4, 0.4), tank=(1.6, 0.6), obstacle=(1.0, 0.1, 0.1),
               wall_layers: int = 2, kernel: int = WENDLAND, alpha: float = 0.3,
-              sigma: float = 0.072) -> System:
+              sigma: float = 0.072, repulsive: bool = False) -> System:
     """Water column in a tank with a square obstacle on the floor.
 
     Fluid on ((i+1/2)dx, (j+1/2)dx); `wall_layers` layers of fixed boundary
     particles below the floor and outside both side walls; the obstacle is filled
     on the same lattice. At dx = 0.01 this gives 1,600 fluid and 668 boundary
     particles. c0 = 10 sqrt(g H), hydrostatic initial density, alpha = 0.3 and
-    sigma = 0.072 N/m (the paper's water values).
+    sigma = 0.072 N/m (the paper's water values). repulsive: the walls exert
+    the repulsive force of eq. 29 instead of acting as dynamic particles
+    (meta["wall_normal"] holds their normals).
     """
     W, Hc = column
     L, Ht = tank
@@ -177,8 +179,27 @@ def dam_break(dx: float = 0.01, column=(0.4, 0.4), tank=(1.6, 0.6), obstacle=(1.
     rho_w = hydrostatic_density(walls[:, 1], Hc, rho0, c0, g)
     params = default_params(h, rho0, c0, kernel=kernel, alpha=alpha, sigma=sigma,
                             gravity=(0.0, -g), box_lo=(-0.1, -0.1), box_hi=(L + 0.1, 1.2))
-    return _assemble(params, [(fluid, (0.0, 0.0), rho_f, FLUID), (walls, (0.0, 0.0), rho_w, WALL)],
-                     name="dam_break", meta=dict(dx=dx, H=Hc))
+    s = _assemble(params, [(fluid, (0.0, 0.0), rho_f, FLUID), (walls, (0.0, 0.0), rho_w, WALL)],
+                  name="dam_break", meta=dict(dx=dx, H=Hc))
+    if repulsive:
+        # walls of force particles (eq. 29): one layer on each face, normals
+        # into the fluid; the obstacle's top and sides likewise
+        s.params.update(boundary=1, wall_spacing=dx)
+        s.rho[s.type == WALL] = rho0
+        nrm = np.zeros((s.n, 2))
+        wp = s.pos
+        w = s.type == WALL
+        near = lambda x, v: np.abs(x - v) < 0.25 * dx
+        floor = w & near(wp[:, 1], -0.5 * dx)                        # the inner layer of each face
+        nrm[floor] = [0.0, 1.0]
+        nrm[w & near(wp[:, 0], -0.5 * dx) & (wp[:, 1] > 0)] = [1.0, 0.0]
+        nrm[w & near(wp[:, 0], L + 0.5 * dx) & (wp[:, 1] > 0)] = [-1.0, 0.0]
+        o = w & (wp[:, 0] > 0) & (wp[:, 0] < L) & (wp[:, 1] > 0)    # the obstacle: its outer particles
+        nrm[o & near(wp[:, 0], ox + 0.5 * dx)] = [-1.0, 0.0]
+        nrm[o & near(wp[:, 0], ox + ow - 0.5 * dx)] = [1.0, 0.0]
+        nrm[o & near(wp[:, 1], oh - 0.5 * dx)] = [0.0, 1.0]
+        s.meta["wall_normal"] = nrm
+    return s
 
 
 def rest_tank(dx: float = 0.02, width: float = 0.4, depth: float = 0.3, wall_layers: int = 3,
