@@ -50,6 +50,10 @@ extern "C" {
 
 #define SPH_ABI_VERSION 2
 
+/* Largest total particle count of a context: every per-particle array is
+ * addressed with 32-bit byte offsets (16-byte records, a few padding slots). */
+#define SPH_MAX_PARTICLES ((int64_t)(1 << 28) - 4096)
+
 typedef enum {
     SPH_OK = 0,
     SPH_EINVAL = -1,     /* bad argument: NULL pointer, size, parameter out of range */
@@ -191,7 +195,8 @@ enum {
 
 /* Bytes of device workspace a context with these systems needs.
  *   opt: options (NULL = defaults); n_sys >= 1; p: n_sys parameter records;
- *   offsets: n_sys + 1 ascending particle offsets, offsets[0] = 0.
+ *   offsets: n_sys + 1 ascending particle offsets, offsets[0] = 0, total in
+ *            [1, SPH_MAX_PARTICLES].
  * Errors: SPH_EINVAL for invalid parameters (see sph_params). */
 sph_status sph_workspace_bytes(const sph_options* opt, int32_t n_sys, const sph_params* p,
                                const int64_t* offsets, size_t* bytes_out);

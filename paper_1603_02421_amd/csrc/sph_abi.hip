@@ -433,7 +433,6 @@ struct Impl : sph_ctx_base {
         // the first evaluation of a step scans the cells and writes the skin
         // mask (pairs within R s); both evaluations walk it with the exact pair
         // predicate
-        v.skin = 1;
         v.nmask = smask;
         v.nmask4 = smask4;
         v.smask = half ? nullptr : smask;
@@ -1080,6 +1079,9 @@ SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     s.y0 = p.box_lo[1];
     s.inv_s = 1.0 / p.cell_size;
     s.R2 = (2.0 * p.h) * (2.0 * p.h);
+    // FP32 band of the pair predicate: 2^-19 of (2h)^2 either side, rounded outwards
+    s.r2_in = std::nextafter((float)(s.R2 * (1.0 - 0x1p-19)), 0.0f);
+    s.r2_out = std::nextafter((float)(s.R2 * (1.0 + 0x1p-19)), INFINITY);
     double skin = g.reach * p.cell_size - 2.0 * p.h;
     s.skin2 = 0.25 * skin * skin;
     s.cell_s = p.cell_size;
@@ -1150,7 +1152,7 @@ const char* plan(const sph_options& o, int n_sys, const sph_params* p, const int
     if (off[0] != 0) return "offsets[0] must be 0";
     for (int s = 0; s < n_sys; ++s)
         if (off[s + 1] < off[s]) return "offsets must be non-decreasing";
-    if (off[n_sys] < 1 || off[n_sys] > ((int64_t)1 << 30)) return "particle count must be in [1, 2^30]";
+    if (off[n_sys] < 1 || off[n_sys] > SPH_MAX_PARTICLES) return "particle count must be in [1, SPH_MAX_PARTICLES]";
     base.assign(n_sys + 1, 0);
     uint64_t acc = 0;
     for (int s = 0; s < n_sys; ++s) {

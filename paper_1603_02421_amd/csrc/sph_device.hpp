@@ -60,6 +60,7 @@ struct SysDev {
     double Rs2;                    // (R s)^2: radius^2 of the skin mask kept for the half step
     int32_t nx, ny, reach, kernel;
     uint32_t cell_base, pad_;
+    float r2_in, r2_out;           // FP32 band around (2h)^2 outside which FP32 decides the predicate
     // physics in the working precision
     T h, inv_h, wnorm, gnorm;      // W = wnorm * w(q); grad_a W = gnorm * g(q) * r_ab
     T W0;                          // W(0)
@@ -101,6 +102,30 @@ __device__ __forceinline__ double pair_r2(double2 pa, double2 pb, double& dx, do
     dx = pa.x - pb.x;
     dy = pa.y - pb.y;
     return dx * dx + dy * dy;
+}
+
+// The same predicate |r_ab|^2 < (2h)^2, decided mostly in FP32. fx, fy are
+// the FP64 components ex, ey rounded to FP32 and r2f = fx^2 + fy^2 in FP32
+// (contracted or not): each component carries one rounding, each square and
+// the sum one more, so r2f is within 2^-21 of the FP64 |r_ab|^2 (itself within
+// 2^-52 of the exact value). r2_in and r2_out sit 2^-19 of (2h)^2 either side
+// of it, so below r2_in (above r2_out) the FP64 verdict is certainly "inside"
+// ("outside"); in the band between, the FP64 sum decides, formed as above.
+// The band is so thin (a few in 10^6 of the candidates) that the FP64 branch
+// is almost never taken by any lane of a wave.
+__device__ __forceinline__ bool pair_within(double ex, double ey, float r2f, float r2_in, float r2_out, double R2) {
+    if (r2f < r2_in) return true;
+    if (__builtin_expect(r2f > r2_out, 1)) return false;
+    double fx, fy;
+    return pair_r2(make_double2(ex, ey), make_double2(0.0, 0.0), fx, fy) < R2;
+}
+
+// Element i of a particle array through a 32-bit byte offset (the particle
+// count is limited so that every array's byte offsets fit): the loads then take
+// the array's base from scalar registers and one 32-bit offset per lane.
+template <typename U>
+__device__ __forceinline__ const U& at(const U* base, uint32_t i) {
+    return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(U));
 }
 
 template <typename T> __device__ __forceinline__ T rcp(T x);

@@ -106,7 +106,6 @@ struct EvalView {
     uint32_t* nmask4;            // n: word of row 4 (+ overflow bit 31)
     uint4* smask;                // n: where the first colour sweep writes the skin mask (pairs within
     uint32_t* smask4;            //   R s); null in the half-step evaluation
-    int skin;                    // 1: nmask is a skin mask, walkers apply the exact pair predicate
     int pad3_;
     // half-step evaluation only (else null): per system, then over all
     // systems, the bit pattern of the largest squared half-step displacement

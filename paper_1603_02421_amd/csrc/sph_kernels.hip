@@ -410,8 +410,9 @@ __device__ __forceinline__ int rescan_reach(const EvalView<T>& v, const SysDev<T
 // Visit the neighbours recorded in slot a's mask words, four at a time
 // (positions and payloads, then compute). Bit k of word r is the k-th slot of
 // cell row r of the block; r_ab = r_a - r_b is formed in FP64 exactly as in
-// the scan. A skin mask (v.skin) also holds pairs out to R s: those that fail
-// the exact predicate |r_ab|^2 < (2h)^2 are skipped.
+// the scan. The skin mask also holds pairs out to R s: those that fail the
+// exact predicate |r_ab|^2 < (2h)^2 are skipped (in FP32 contexts decided
+// through the FP32 band of pair_within, with the same verdict).
 template <typename T, int NB = 4, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
                                                 const RowMask& M, LoadFn&& load, ComputeFn&& compute) {
@@ -449,6 +450,8 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
     }
     uint32_t m = qm[0], base = qb[0];
     uint32_t m1 = qm[1], b1 = qb[1], m2 = qm[2], b2 = qb[2], m3 = qm[3], b3 = qb[3], m4 = qm[4], b4 = qb[4];
+    const float r2_in = S.r2_in, r2_out = S.r2_out;
+    const double R2 = S.R2;
     // next recorded neighbour; false once every word is spent
     auto next = [&](uint32_t& b) -> bool {
         const bool ok = m != 0u;
@@ -474,7 +477,7 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
         if (!ok[0]) break;
         double2 q[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) q[j] = v.pos[bb[j]];
+        for (int j = 0; j < NB; ++j) q[j] = at(v.pos, bb[j]);
         // payloads unconditionally: a spent lane's index is its own slot, so
         // every load is in bounds and none needs a branch around it
         P pl[NB];
@@ -483,9 +486,17 @@ __device__ __forceinline__ void mask_neighbours(const EvalView<T>& v, const SysD
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (ok[j]) {
-                double ex, ey;
-                const double r2 = pair_r2(pa, q[j], ex, ey);
-                if (!v.skin || r2 < S.R2) compute(bb[j], (T)ex, (T)ey, pl[j]);
+                const double ex = pa.x - q[j].x, ey = pa.y - q[j].y;
+                const T dx = (T)ex, dy = (T)ey;
+                const T r2w = dx * dx + dy * dy;   // the sweeps form the same square
+                bool in;
+                if constexpr (sizeof(T) == 4) {
+                    in = pair_within(ex, ey, r2w, r2_in, r2_out, R2);
+                } else {
+                    double fx, fy;
+                    in = pair_r2(pa, q[j], fx, fy) < R2;
+                }
+                if (in) compute(bb[j], dx, dy, pl[j]);
             }
         }
     }
@@ -557,7 +568,7 @@ __device__ __forceinline__ void for_outran_chunks(const EvalView<T>& v, Fn&& bod
     }
 }
 
-template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; uint32_t tag; };
+template <typename T> struct Pay2 { V2<T> vel; V4<T> eos; };
 template <typename T> struct Pay3 { V2<T> nrm; T vol; };
 
 // Repulsive-force walls (eq. 29): the force per unit mass on every fluid
@@ -665,9 +676,10 @@ __global__ void __launch_bounds__(256) k_density(EvalView<T> v) {
 
 // Sweep 1: colour function C_a = sum_b (m_b / rho_b) W_ab, self included
 // (eq. 14). The Tait equation (eq. 26) is evaluated here once per particle:
-// the record (P / rho^2, C, rho, m / rho) is everything the main sweep
+// the record (P / rho^2, C, rho, +-m / rho) is everything the main sweep
 // gathers of a neighbour besides its position and velocity (the sound speed
-// follows from rho).
+// follows from rho; m / rho carries a minus sign for a boundary particle, so
+// the sweep needs no type tag of its neighbours).
 //
 // The first evaluation of a step scans the cells. Its candidates within R s
 // (the cell block's radius) are recorded as the skin mask, and those within 2h
@@ -709,7 +721,7 @@ struct MaskBuilder {
 // The colour, then the record of slot a.
 template <typename T>
 __device__ __forceinline__ void colour_finish(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, T vol_a,
-                                              T dens_a, T wsum) {
+                                              T dens_a, T wsum, bool fluid_a) {
     const T sum = vol_a * S.W0 + S.wnorm * wsum;
     v.colour[a] = sum;
     T rho_a, pr_a;
@@ -718,7 +730,7 @@ __device__ __forceinline__ void colour_finish(const EvalView<T>& v, const SysDev
     e.x = pr_a;
     e.y = sum;
     e.z = rho_a;
-    e.w = vol_a;
+    e.w = fluid_a ? vol_a : -vol_a;   // the sign tells the main sweep a boundary particle
     v.eos[a] = e;
 }
 
@@ -757,7 +769,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                            },
                            row_end, S.Rs2, S.reach);
     }
-    colour_finish(v, S, a, vol_a, dens_a, wsum);
+    colour_finish(v, S, a, vol_a, dens_a, wsum, tag_type(v.tag[a]) == T_FLUID);
     Sk.store(v.smask, v.smask4, a);
 }
 
@@ -772,10 +784,10 @@ __device__ __forceinline__ void colour_skin_slot(const EvalView<T>& v, int sys, 
     const T vol_a = v.vol[a];
     const T dens_a = v.dens[a];
     T wsum = 0;
-    neighbours<T, 4, RESCAN>(v, S, a, pa, [&](uint32_t b) { return v.vol[b]; },
+    neighbours<T, 4, RESCAN>(v, S, a, pa, [&](uint32_t b) { return at(v.vol, b); },
                              [&](uint32_t, T dx, T dy, T vol_b) { wsum += vol_b * kernel_shape(K, sqrt_(dx * dx + dy * dy)); },
                              rescan);
-    colour_finish(v, S, a, vol_a, dens_a, wsum);
+    colour_finish(v, S, a, vol_a, dens_a, wsum, tag_type(v.tag[a]) == T_FLUID);
 }
 
 template <typename T>
@@ -811,6 +823,8 @@ __global__ void __launch_bounds__(256) k_colour_rescan(EvalView<T> v) {
 // to its own slot of dt_wave (plain stores); k_dt_finalize reduces them.
 // FP32: six waves per SIMD (at most 80 VGPRs) fit without spilling.
 // One wave's chunk of the main sweep (every lane of the wave calls it).
+// RESCAN: the half step of a system that outran its skin mask scans the
+// step-start cells with the wider reach `rescan`.
 template <typename T, bool RESCAN>
 __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32_t a, uint32_t chunk, int rescan) {
     const SysDev<T>& S = v.sys[sys];
@@ -829,23 +843,16 @@ __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32
         const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
         const KernelConsts<T> K = kconsts(S);
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, sig_vr = 0, sig_r2 = 1;
-        neighbours<T, 4, RESCAN>(v, S, a, pa,
-            [&](uint32_t b) {
-                Pay2<T> p;
-                p.vel = v.vel[b];
-                p.eos = v.eos[b];
-                p.tag = fluid ? 0u : v.tag[b];
-                return p;
-            },
-            [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
-                if (!fluid && tag_type(p.tag) != T_FLUID) return;
-                const T pr_b = p.eos.x, C_b = p.eos.y, rho_b = p.eos.z, vol_b = p.eos.w;
-                const T m_b = vol_b * rho_b;
+        auto pair = [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
+                // the record's m/rho is negative for a boundary particle
+                if (!fluid && !(p.eos.w > T(0))) return;
+                const T pr_b = p.eos.x, C_b = p.eos.y, rho_b = p.eos.z, vol_b = fabs(p.eos.w);
                 T r2 = dx * dx + dy * dy;
                 T F = kernel_f(K, sqrt_(r2));
                 T ux = va.x - p.vel.x, uy = va.y - p.vel.y;
                 T vr = ux * dx + uy * dy;
-                const T mF = m_b * F;
+                const T vF = vol_b * F;
+                const T mF = vF * rho_b;   // m_b F
                 drho += mF * vr;
                 // signal term max_b |v_ab . r_ab| / r_ab^2, kept as a fraction
                 const T avr = fabs(vr);
@@ -855,19 +862,24 @@ __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32
                 if (fluid) {
                     T pi = 0;
                     if (vr < T(0)) {
-                        T cbar = T(0.5) * (c_a + sound_speed(S, rho_b));
-                        T rbar = T(0.5) * (rho_a + rho_b);
-                        pi = -alpha_h * cbar * vr * rcp(rbar * (r2 + eta2));
+                        // the mean sound speed over the mean density: the halves cancel
+                        pi = -alpha_h * (c_a + sound_speed(S, rho_b)) * vr * rcp((rho_a + rho_b) * (r2 + eta2));
                     }
                     T coef = mF * (pr_a + pr_b + pi);
                     ax -= coef * dx;
                     ay -= coef * dy;
-                    T cn = vol_b * (C_b - Ca) * F;
+                    T cn = (C_b - Ca) * vF;
                     nx += cn * dx;
                     ny += cn * dy;
                 }
-            },
-            rescan);
+            };
+        auto global_load = [&](uint32_t b) {
+            Pay2<T> p;
+            p.vel = at(v.vel, b);
+            p.eos = at(v.eos, b);
+            return p;
+        };
+        neighbours<T, 4, RESCAN>(v, S, a, pa, global_load, pair, rescan);
         const T vsig = h * sig_vr / sig_r2;
         v.drho[a] = drho;
         V2<T> acc, nrm;
@@ -1003,7 +1015,7 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
             T den = v.vol[a] * S.W0;
             const double2 pa = v.pos[a];
             neighbours<T, 4, RESCAN>(v, S, a, pa,
-                [&](uint32_t b) { return Pay3<T>{v.nrm[b], v.vol[b]}; },
+                [&](uint32_t b) { return Pay3<T>{at(v.nrm, b), at(v.vol, b)}; },
                 [&](uint32_t, T dx, T dy, const Pay3<T>& p) {
                     T mb = sqrt_(p.nrm.x * p.nrm.x + p.nrm.y * p.nrm.y);
                     if (mb > eps) {
