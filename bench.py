@@ -52,7 +52,7 @@ METHOD_BYTES_PER_STEP = 400
 # m/rho), neighbour mask 20 (one word per cell row).
 IMPL_BYTES = {
     "colour": 16 + 4 + 4 + 4 + 4 + 16 + 20,               # pos vol cell tag dens -> colour eos skin-mask
-    "colour_skin": 16 + 4 + 4 + 4 + 20 + 4 + 16,          # pos vol cell dens skin-mask -> colour eos
+    "colour_skin": 16 + 4 + 4 + 4 + 4 + 20 + 4 + 16,      # pos vol cell tag dens skin-mask -> colour eos
     "main": 4 + 16 + 8 + 16 + 20 + 4 + 4 + 8 + 8,         # tag pos vel eos mask cell -> drho acc nrm
     # per filtered particle: list entry tag nrm acc rho vol pos mask cell -> acc kappa kappa_plain
     # (88 B), over active particles at the 2.9% filtered on the 64-jet batch
@@ -113,8 +113,8 @@ def _pmc(path: str, counter: str):
     out = collections.defaultdict(list)
     with open(path) as f:
         for r in csv.DictReader(f):
-            if r["Counter_Name"] != counter:
-                continue
+            if r["Counter_Name"] != counter or ", true>" in r["Kernel_Name"]:
+                continue   # (the RESCAN instantiations run only when a system outran its skin)
             name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").split("::")[-1]
             out[name].append(float(r["Counter_Value"]))
     return out

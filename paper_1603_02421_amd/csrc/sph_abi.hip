@@ -1108,6 +1108,7 @@ SysDev<T> make_sysdev(const sph_params& p, uint32_t base) {
     s.gamma = (T)p.gamma;
     s.half_gm1 = (T)(0.5 * (p.gamma - 1.0));
     s.alpha_h = (T)(p.alpha * h);
+    s.visc_c0 = (T)(-p.alpha * h * p.c0);
     s.eta2 = (T)(p.eta2_h2 * h * h);
     s.sigma = (T)p.sigma;
     s.eps = (T)(p.eps_h / h);

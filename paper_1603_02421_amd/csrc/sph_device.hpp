@@ -67,6 +67,7 @@ struct SysDev {
     T rho0, inv_rho0, B, c0;       // Tait: P = B((1 + delta)^gamma - 1), delta = dens / rho0
     T gamma, half_gm1;             // gamma, (gamma - 1)/2
     T alpha_h, eta2;               // alpha * h, eta^2
+    T visc_c0;                     // -alpha h c0: c_b scaled for the viscosity term (gamma = 7)
     T sigma, eps;                  // surface tension, eps = eps_h / h
     T gx, gy;
     int32_t gamma7, closure;
@@ -236,6 +237,14 @@ __device__ __forceinline__ T sound_speed(const SysDev<T>& S, T rho) {
     const T s = rho * S.inv_rho0;
     if (S.gamma7) return S.c0 * s * s * s;
     return S.c0 * exp(S.half_gm1 * log(s));
+}
+
+// -alpha h c(rho): the sound speed as the viscosity term (eq. 10) uses it.
+template <typename T>
+__device__ __forceinline__ T visc_speed(const SysDev<T>& S, T rho) {
+    const T s = rho * S.inv_rho0;
+    if (S.gamma7) return S.visc_c0 * s * s * s;
+    return -S.alpha_h * S.c0 * exp(S.half_gm1 * log(s));
 }
 
 // m / rho, which the colour sum needs of every neighbour.

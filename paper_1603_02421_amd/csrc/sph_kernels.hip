@@ -840,7 +840,8 @@ __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32
         const V4<T> ea = v.eos[a];
         const T pr_a = ea.x, Ca = ea.y, rho_a = ea.z;
         const T c_a = sound_speed(S, rho_a);
-        const T h = S.h, alpha_h = S.alpha_h, eta2 = S.eta2;
+        const T vc_a = -S.alpha_h * c_a;
+        const T h = S.h, eta2 = S.eta2;
         const KernelConsts<T> K = kconsts(S);
         T drho = 0, ax = 0, ay = 0, nx = 0, ny = 0, sig_vr = 0, sig_r2 = 1;
         auto pair = [&](uint32_t, T dx, T dy, const Pay2<T>& p) {
@@ -863,7 +864,7 @@ __device__ __forceinline__ void main_chunk(const EvalView<T>& v, int sys, uint32
                     T pi = 0;
                     if (vr < T(0)) {
                         // the mean sound speed over the mean density: the halves cancel
-                        pi = -alpha_h * (c_a + sound_speed(S, rho_b)) * vr * rcp((rho_a + rho_b) * (r2 + eta2));
+                        pi = (vc_a + visc_speed(S, rho_b)) * vr * rcp((rho_a + rho_b) * (r2 + eta2));
                     }
                     T coef = mF * (pr_a + pr_b + pi);
                     ax -= coef * dx;
