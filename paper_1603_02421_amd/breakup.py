@@ -38,18 +38,21 @@ def groups_row(u0: float):
                 L_corr=groups.breakup_length_correlation(We, Oh))
 
 
-def run(nD: int = 20, t_max: float = 1.0, check: int = 400, kernels=(0, 1), u0s=U0, seed: int = 0, log=print):
+def run(nD: int = 20, t_max: float = 1.0, check: int = 400, kernels=(0, 1), u0s=U0, seed: int = 0,
+        free_length: float = 70.0, log=print):
     """Steps the batch to t_max (every system's own time), taking the breakup
     criterion every `check` steps. Per system: the first breakup (time and
     length), and the intact length L of the established jet -- the median, over
     the checks in the second half of the run, of the length to the first gap
-    (checks without a gap count with the jet's full length)."""
+    (checks without a gap count with the jet's full length). The domain reaches
+    free_length D0 beyond the orifice: a jet intact to its end is cut there."""
     import workloads as wl
     from . import sim as simmod
     # the tank holds the same volume at every resolution (the piston travels
     # about 3.6 D0 in 1 s at the fastest inflow, of a 14 D0 tank)
     n_target = int(40_000 * (nD / 20.0) ** 2)
-    systems = [wl.paper_jet(u0, kernel=k, nD=nD, seed=seed + i, n_target=n_target) for i, (k, u0) in
+    systems = [wl.paper_jet(u0, kernel=k, nD=nD, seed=seed + i, n_target=n_target, free_length=free_length)
+               for i, (k, u0) in
                enumerate((k, u0) for k in kernels for u0 in u0s)]
     batch = wl.Batch(systems)
     starts = np.array([s.meta["exit"] for s in systems])
@@ -90,6 +93,7 @@ def run(nD: int = 20, t_max: float = 1.0, check: int = 400, kernels=(0, 1), u0s=
     for i, s in enumerate(systems):
         u0 = s.meta["u0"]
         row = dict(u0=u0, kernel="wendland" if s.params["kernel"] == 0 else "cubic", nD=nD, n=s.n,
+                   free_length_over_D0=free_length,
                    **groups_row(u0))
         row.update(t_first=first[i][0] if i in first else None,
                    L_first_over_D0=first[i][1] / D0 if i in first else None)
@@ -109,9 +113,10 @@ def main():
     ap.add_argument("--nD", type=int, default=20)
     ap.add_argument("--t-max", type=float, default=1.0)
     ap.add_argument("--check", type=int, default=400)
+    ap.add_argument("--free-length", type=float, default=70.0, help="domain beyond the orifice, in D0")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    res = run(nD=a.nD, t_max=a.t_max, check=a.check, log=lambda m: print(m, flush=True))
+    res = run(nD=a.nD, t_max=a.t_max, check=a.check, free_length=a.free_length, log=lambda m: print(m, flush=True))
     for r in res["rows"]:
         first = "none" if r["L_first_over_D0"] is None else f"{r['L_first_over_D0']:.2f} at {r['t_first']:.3f} s"
         print(f"u0 = {r['u0']:.2f} m/s {r['kernel']:8s} nD {r['nD']} We {r['We']:.2f} Re {r['Re']:.0f} Fr {r['Fr']:.2f}: "

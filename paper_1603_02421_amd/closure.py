@@ -287,10 +287,16 @@ def _wendland(q):
 
 def fine_jet_snapshots(nD_coarse: int, Re: float, We: float, seed: int, steps: Sequence[int],
                        n_fine: int = 300_000, free_length: float = 30.0, piston_amp: float = 0.01,
-                       device="cuda:0"):
+                       avg_steps: int = 1, device="cuda:0"):
     """Run a jet at 4 nD_coarse particles per D (piston velocity amplitude
     `piston_amp`) and return snapshots (fluid positions, unit normals, plain
-    curvature and filter flags) after each step count in `steps` (ascending)."""
+    curvature and filter flags) after each step count in `steps` (ascending).
+
+    With avg_steps = K > 1 the curvature of each snapshot is the mean over the
+    K fine steps that start at it (K = 4 spans about one step of the coarse
+    run, whose dt is four times the fine one), taken over the steps at which
+    the particle is an interface particle; positions, normals and the
+    interface flag are the first step's."""
     import workloads as wl
     from .sim import Simulation
     fine = wl.round_for_dtype(wl.jet(n_target=n_fine, nD=4 * nD_coarse, Re=Re, We=We, seed=seed,
@@ -299,6 +305,13 @@ def fine_jet_snapshots(nD_coarse: int, Re: float, We: float, seed: int, steps: S
     t_plate = 3 * fine.meta["dx"]
     snaps = []
     done = 0
+    h = fine.params["h"]
+
+    def interface(sim):
+        nrm = sim.read("normal")
+        mag = np.linalg.norm(nrm, axis=1)
+        return nrm, mag, (sim.read("nflag") == 1) & (mag * h >= INTERFACE_NH)
+
     with Simulation(fine, dtype_bits=32, device=device, graph_steps=50) as sim:
         for st in steps:
             if st > done:
@@ -308,19 +321,35 @@ def fine_jet_snapshots(nD_coarse: int, Re: float, We: float, seed: int, steps: S
             typ = sim.read("type")
             pos = sim.read("pos")
             sel = (typ == wl.FLUID) & (pos[:, 0] > t_plate + 0.5)
-            nrm = sim.read("normal")
-            mag = np.linalg.norm(nrm, axis=1)
+            nrm, mag, iface = interface(sim)
             nh = np.where(mag[:, None] > 0, nrm / np.maximum(mag, 1e-300)[:, None], 0.0)
-            iface = (sim.read("nflag") == 1) & (mag * fine.params["h"] >= INTERFACE_NH)
-            snaps.append(dict(pos=pos[sel], nhat=nh[sel], kappa=sim.read("curv")[sel],
-                              iface=iface[sel], step=st, h_fine=fine.params["h"]))
+            k1 = sim.read("curv")
+            ksum = np.where(iface, k1, 0.0)
+            kcnt = iface.astype(np.int64)
+            for _ in range(avg_steps - 1):
+                sim.step(1)
+                done += 1
+                sim.evaluate()
+                _, _, fi = interface(sim)
+                ksum += np.where(fi, sim.read("curv"), 0.0)
+                kcnt += fi
+            kappa = ksum / np.maximum(kcnt, 1)
+            snaps.append(dict(pos=pos[sel], nhat=nh[sel], kappa=kappa[sel], kappa_first=k1[sel],
+                              iface=iface[sel], step=st, h_fine=h, avg_steps=avg_steps))
     return snaps
 
 
-def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int):
+def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int, window: float = 1.0,
+                         label_h: float = 0.0, rmin: float = 0.78):
     """Poisson-disk subsample of a fine snapshot at the coarse spacing (number
     density 1/dx^2) with reference labels; returns a closure System whose
     meta holds (nhat_ref, kappa_ref, has_ref).
+
+    A label is the Wendland-weighted mean, W(r / h_l), of the fine interface
+    particles' normals and curvatures within window * h_l of the kept
+    particle, h_l the coarse smoothing length (or label_h, so that a finer
+    subsample can be labelled at the same physical scale); window = 2 is the
+    whole support of the coarse kernel.
 
     The meta also holds kappa_halves (n x 2) and has_halves: the same label
     computed from each half of a seeded random split of the fine interface
@@ -329,16 +358,17 @@ def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int):
     from scipy.spatial import cKDTree
     dxc = 1.0 / nD_coarse
     # one greedy pass over the fine points (16 per coarse cell) with
-    # rmin = 0.78 dx keeps one point per dx^2 (measured on a jittered lattice)
-    keep = poisson_subsample(snap["pos"], 0.78 * dxc, seed)
+    # rmin = 0.78 dx keeps one point per dx^2 (measured on a jittered lattice;
+    # a subsample at half the fine run's spacing needs its own rmin)
+    keep = poisson_subsample(snap["pos"], rmin * dxc, seed)
     pc = snap["pos"][keep]
-    hc = 1.3 * dxc
+    hc = label_h if label_h > 0 else 1.3 * dxc
     surf = snap["iface"]
     sp = snap["pos"][surf]
     sn = snap["nhat"][surf]
     sk = snap["kappa"][surf]
     tree = cKDTree(sp)
-    nbrs = tree.query_ball_point(pc, r=hc)
+    nbrs = tree.query_ball_point(pc, r=window * hc)
     nref = np.zeros((len(pc), 2))
     kref = np.zeros(len(pc))
     has = np.zeros(len(pc), dtype=bool)

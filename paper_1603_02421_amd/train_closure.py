@@ -46,22 +46,35 @@ SWEEP_JETS = [
 SWEEP_HELD_OUT = [(10, 700.0, 12.0, 101, 0.1), (12, 250.0, 35.0, 102, 0.2), (16, 1200.0, 20.0, 103, 0.01)]
 
 
-def jet_sets(spec, snap_steps, n_coarse, free_length):
-    """Coarse labelled sets from jets run at 4x resolution: the fine run has
-    16 n_coarse particles, so that its tank matches a coarse jet of n_coarse."""
+def fine_runs(spec, snap_steps, n_coarse, free_length, avg_steps):
+    """(spec entry, snapshots) of the jets of `spec` run at 4x resolution (the
+    fine run has 16 n_coarse particles, so that its tank matches a coarse jet
+    of n_coarse); jets whose run fails are skipped."""
     from . import closure as cl
-    out = []
     from .native import SphError
+    runs = []
     for (nD, Re, We, seed, amp) in spec:
         t0 = time.time()
         try:
             snaps = cl.fine_jet_snapshots(nD, Re, We, seed, snap_steps, n_fine=16 * n_coarse,
-                                          free_length=free_length, piston_amp=amp)
+                                          free_length=free_length, piston_amp=amp, avg_steps=avg_steps)
         except SphError as e:
             log(f"[jets] nD={nD} Re={Re} We={We} amp={amp}: skipped ({e})")
             continue
+        runs.append(((nD, Re, We, seed, amp), snaps))
+        log(f"[jets] nD={nD} Re={Re} We={We} amp={amp}: {len(snaps)} snapshots, {time.time() - t0:.1f} s")
+    return runs
+
+
+def jet_sets(spec, snap_steps, n_coarse, free_length, avg_steps=1, window=1.0):
+    """Coarse labelled sets from jets run at 4x resolution (labels: see
+    closure.coarse_from_snapshot and fine_jet_snapshots)."""
+    from . import closure as cl
+    out = []
+    for (nD, Re, We, seed, amp), snaps in fine_runs(spec, snap_steps, n_coarse, free_length, avg_steps):
+        t0 = time.time()
         for k, sn in enumerate(snaps):
-            out.append(cl.coarse_from_snapshot(sn, nD, Re, We, seed * 100 + k))
+            out.append(cl.coarse_from_snapshot(sn, nD, Re, We, seed * 100 + k, window=window))
         log(f"[jets] nD={nD} Re={Re} We={We} amp={amp}: {len(snaps)} snapshots, "
             f"{sum(s.n for s in out[-len(snaps):])} coarse particles, {time.time() - t0:.1f} s")
     return out
@@ -127,11 +140,21 @@ def main(argv=None):
     ap.add_argument("--no-mirror", action="store_true", help="no mirror images of the training stencils")
     ap.add_argument("--skip-eval", action="store_true", help="stop after training")
     ap.add_argument("--eval-only", action="store_true", help="skip data and training; evaluate the weights")
+    ap.add_argument("--label-steps", type=int, default=4,
+                    help="fine steps each jet label's curvature is averaged over (4: one coarse step)")
+    ap.add_argument("--label-window", type=float, default=2.0,
+                    help="radius of a jet label's average, in coarse smoothing lengths (2: the kernel's support)")
+    ap.add_argument("--label-study", action="store_true",
+                    help="only measure the held-out jet labels' split-half noise and the plain estimate's "
+                         "error (at the coarse and at twice the coarse resolution) for label variants")
     ap.add_argument("--weights", default="", help="weights file for --eval-only (default: the shipped ones)")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     rep = dict(args=vars(a))
 
+    if a.label_study:
+        label_study(cl, a, rep)
+        return
     if a.eval_only:
         w = cl.load(a.weights) if a.weights else cl.load()
         evaluate_and_cost(cl, w, a, rep)
@@ -141,8 +164,10 @@ def main(argv=None):
     Xs, Ts, Ps, _ = cl.harvest_shapes(shapes)
     del shapes
     log(f"[data] shapes: {len(Xs)} neighbourhoods ({time.time() - t0:.1f} s)")
-    jets = jet_sets(TRAIN_JETS[:a.jets], _snaps(a.jet_snap_steps), a.jet_n, a.jet_free_length)
-    jets += jet_sets(SWEEP_JETS[:a.sweep_jets], _snaps(a.sweep_snap_steps), a.sweep_n, a.sweep_free_length)
+    jets = jet_sets(TRAIN_JETS[:a.jets], _snaps(a.jet_snap_steps), a.jet_n, a.jet_free_length,
+                    a.label_steps, a.label_window)
+    jets += jet_sets(SWEEP_JETS[:a.sweep_jets], _snaps(a.sweep_snap_steps), a.sweep_n, a.sweep_free_length,
+                     a.label_steps, a.label_window)
     Xj, Tj, Pj, _, _ = cl.harvest_coarse(jets)
     del jets
     log(f"[data] jets: {len(Xj)} neighbourhoods ({time.time() - t0:.1f} s)")
@@ -168,8 +193,56 @@ def main(argv=None):
     evaluate_and_cost(cl, w, a, rep)
 
 
-def held_out_jets(cl, w, spec, snaps, n, free_length):
-    hj = jet_sets(spec, snaps, n, free_length)
+def label_study(cl, a, rep):
+    """Split-half noise of the held-out jets' labels, and the plain estimate's
+    error against them at the coarse and at twice the coarse resolution, for
+    labels from one fine step or averaged over `label_steps`, over one or two
+    coarse smoothing lengths. The twice-as-fine subsample is labelled at the
+    coarse scale, so both resolutions are measured against the same labels."""
+    out = {}
+    for name, spec, snaps, n, fl in (("jets_D20", HELD_OUT_JETS, a.jet_snap_steps, a.jet_n, a.jet_free_length),
+                                     ("sweep_jets", SWEEP_HELD_OUT, a.sweep_snap_steps, a.sweep_n,
+                                      a.sweep_free_length)):
+        runs = fine_runs(spec, _snaps(snaps), n, fl, a.label_steps)
+        # the Poisson radius that keeps one point per dx^2 at twice the coarse
+        # resolution (four fine points per cell), from the first snapshot
+        (nD0, *_), sn0 = runs[0][0], runs[0][1][-1]
+        target = len(sn0["pos"]) / 4.0
+        rmin2 = min((0.60, 0.64, 0.68, 0.72, 0.76),
+                    key=lambda f: abs(len(cl.poisson_subsample(sn0["pos"], f / (2 * nD0), 1)) - target))
+        log(f"[labels] {name}: Poisson radius {rmin2} dx at twice the coarse resolution")
+        for steps in (1, a.label_steps):
+            for window in (1.0, 2.0):
+                for fine in (1, 2):
+                    systems, kept, expect = [], 0, 0.0
+                    for (nD, Re, We, seed, amp), sn_list in runs:
+                        for k, sn in enumerate(sn_list):
+                            snap = sn if steps > 1 else dict(sn, kappa=sn["kappa_first"])
+                            systems.append(cl.coarse_from_snapshot(snap, fine * nD, Re, We, seed * 100 + k,
+                                                                   window=window, label_h=1.3 / nD,
+                                                                   rmin=0.78 if fine == 1 else rmin2))
+                            kept += systems[-1].n
+                            expect += len(sn["pos"]) * (fine / 4.0) ** 2
+                    X, T, P, K, F, H, HM = cl.harvest_coarse(systems, halves=True)
+                    ref = T[:, 2]
+                    # kept points per dx^2 of the subsample's spacing (1 is the target)
+                    r = dict(n=int(len(ref)), plain=cl.rel_l2(P, ref), density=kept / expect)
+                    if HM.any():
+                        d = H[HM, 0] - H[HM, 1]
+                        r.update(n_split=int(HM.sum()),
+                                 noise=float(0.5 * np.linalg.norm(d) / np.linalg.norm(ref[HM])))
+                    key = f"{name} steps={steps} window={window} resolution={fine}x"
+                    out[key] = r
+                    log(f"[labels] {key}: {r}")
+                    del X, T, P, K, F, H, HM, systems
+    rep["label_study"] = out
+    with open(os.path.join(a.out, "label_study.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    log("[done]")
+
+
+def held_out_jets(cl, w, spec, snaps, n, free_length, avg_steps=1, window=1.0):
+    hj = jet_sets(spec, snaps, n, free_length, avg_steps, window)
     X2, T2, P2, K2, F2, H2, HM2 = cl.harvest_coarse(hj, params=w, halves=True)
     Y2 = cl.predict(w, X2)
     nh = Y2[:, :2] / np.linalg.norm(Y2[:, :2], axis=1, keepdims=True)
@@ -204,10 +277,10 @@ def evaluate_and_cost(cl, w, a, rep):
     # held-out jets (the D = 20 dx workload at seeds 100-103, and varied smaller
     # jets), with the closure's curvature taken from the particle update
     rep["held_out_jets"] = held_out_jets(cl, w, HELD_OUT_JETS, _snaps(a.jet_snap_steps), a.jet_n,
-                                         a.jet_free_length)
+                                         a.jet_free_length, a.label_steps, a.label_window)
     log(f"[eval] held-out jets (D = 20 dx): {rep['held_out_jets']}")
     rep["held_out_sweep_jets"] = held_out_jets(cl, w, SWEEP_HELD_OUT, _snaps(a.sweep_snap_steps), a.sweep_n,
-                                               a.sweep_free_length)
+                                               a.sweep_free_length, a.label_steps, a.label_window)
     log(f"[eval] held-out jets (D = 10-16 dx): {rep['held_out_sweep_jets']}")
 
     # cost: plain vs closure on a jet at D = 20 dx, and the same jet at 4x

@@ -103,3 +103,30 @@ def test_split_half_labels_measure_the_reference_noise():
     actual = np.linalg.norm(ref + 1.0 / R) / np.linalg.norm(ref)
     assert 0.02 < actual < 0.5
     assert 0.6 * actual < floor < 1.6 * actual
+
+
+def test_wider_label_window_averages_out_more_noise():
+    """A label averaged over the whole support of the coarse kernel (window
+    2 h) holds more fine interface particles than one over h, so independent
+    noise in the fine curvature leaves less in it (compared on the particles
+    that carry both labels: the wider window also labels particles farther
+    from the interface); label_h sets the scale."""
+    R, dxc = 1.0, 0.1
+    snap = _disc_snapshot(R, dxc / 4, 0.5, 2)
+    s1 = cl.coarse_from_snapshot(snap, 10, 500.0, 20.0, seed=3, window=1.0)
+    s2 = cl.coarse_from_snapshot(snap, 10, 500.0, 20.0, seed=3, window=2.0)
+    assert np.array_equal(s1.pos, s2.pos)
+    m = s1.meta["has_ref"] & s2.meta["has_ref"]
+    assert m.sum() > 20 and np.all(s2.meta["has_ref"][s1.meta["has_ref"]])
+
+    def err(s):
+        ref = s.meta["kappa_ref"][m]
+        return np.linalg.norm(ref + 1.0 / R) / np.linalg.norm(ref)
+    assert err(s2) < 0.9 * err(s1)
+    # twice the coarse resolution labelled on the coarse scale: the same fine
+    # particles enter the labels, so the noise is that of the coarse labels
+    s3 = cl.coarse_from_snapshot(snap, 20, 500.0, 20.0, seed=3, window=2.0, label_h=1.3 * dxc, rmin=0.7)
+    near = np.hypot(s3.pos[:, 0], s3.pos[:, 1]) > R - 1.3 * dxc
+    m3 = s3.meta["has_ref"] & near
+    ref = s3.meta["kappa_ref"][m3]
+    assert m3.sum() > 20 and np.linalg.norm(ref + 1.0 / R) / np.linalg.norm(ref) < err(s1)
