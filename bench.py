@@ -245,7 +245,7 @@ def closure_leg(sph, batch, bits, block_sweep, cell_factor, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--profile-steps", type=int, default=5)

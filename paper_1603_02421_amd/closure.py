@@ -340,7 +340,7 @@ def fine_jet_snapshots(nD_coarse: int, Re: float, We: float, seed: int, steps: S
 
 
 def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int, window: float = 1.0,
-                         label_h: float = 0.0, rmin: float = 0.78):
+                         label_h: float = 0.0, rmin: float = 0.78, keep=None):
     """Poisson-disk subsample of a fine snapshot at the coarse spacing (number
     density 1/dx^2) with reference labels; returns a closure System whose
     meta holds (nhat_ref, kappa_ref, has_ref).
@@ -353,14 +353,16 @@ def coarse_from_snapshot(snap, nD_coarse: int, Re: float, We: float, seed: int, 
 
     The meta also holds kappa_halves (n x 2) and has_halves: the same label
     computed from each half of a seeded random split of the fine interface
-    particles. Their spread measures the label's own noise (split-half)."""
+    particles. Their spread measures the label's own noise (split-half).
+    `keep` (indices into the snapshot) replaces the subsample when given."""
     import workloads as wl
     from scipy.spatial import cKDTree
     dxc = 1.0 / nD_coarse
     # one greedy pass over the fine points (16 per coarse cell) with
     # rmin = 0.78 dx keeps one point per dx^2 (measured on a jittered lattice;
     # a subsample at half the fine run's spacing needs its own rmin)
-    keep = poisson_subsample(snap["pos"], rmin * dxc, seed)
+    if keep is None:
+        keep = poisson_subsample(snap["pos"], rmin * dxc, seed)
     pc = snap["pos"][keep]
     hc = label_h if label_h > 0 else 1.3 * dxc
     surf = snap["iface"]

@@ -491,10 +491,30 @@ struct Impl : sph_ctx_base {
         return v;
     }
 
+    // Whether the current buffer's sort keys, slots and cell counts are
+    // already written: every step's corrector writes them for the state it
+    // produces, so the next sort starts at the count scan.
+    bool keys_fresh = false;
+
     // Sort the current buffer into the other one; the other becomes current.
     void sort(hipStream_t st, KernelTimer* kt) {
-        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], vol, st, kt);
+        launch_sort<T>(L, sb, sys, buf[cur], buf[cur ^ 1], vol, keys_fresh, st, kt);
+        keys_fresh = false;
         cur ^= 1;
+    }
+
+    // The current buffer's keys, where no corrector wrote them (after set-up,
+    // a restore or a sort outside a step).
+    void prepare_keys(hipStream_t st, KernelTimer* kt) {
+        if (!keys_fresh) launch_key<T>(L, sb, sys, buf[cur], st, kt);
+        keys_fresh = true;
+    }
+
+    // Before the state is overwritten: counts of keys that will not be
+    // sorted are cleared, so the next key pass starts from zero.
+    void discard_keys(hipStream_t st) {
+        if (keys_fresh) launch_fill_u32(sb.count, (size_t)sb.trash + 1, 0u, st);
+        keys_fresh = false;
     }
 
     // One predictor-corrector step, enqueued on st.
@@ -504,7 +524,14 @@ struct Impl : sph_ctx_base {
         launch_dt<T>(n_sys, sys, sb.chunk_base, dt_wave, dtmin, dt, skin_max, st, kt);
         launch_predict<T>(L, integ_view(), st, kt);
         evaluate(true, false, st, kt);
-        launch_correct<T>(L, integ_view(), n_sys, dt, time, st, kt);
+        IntegView<T> cv = integ_view();
+        cv.key = sb.key;
+        cv.kslot = sb.slot;
+        cv.kcount = sb.count;
+        cv.kblk = sb.blk;
+        cv.trash = sb.trash;
+        launch_correct<T>(L, cv, n_sys, dt, time, st, kt);
+        keys_fresh = true;
     }
 };
 
@@ -516,6 +543,8 @@ int step_impl(sph_ctx* c, int n_steps) {
     Impl<T>* m = impl_of<T>(c);
     int left = n_steps;
     if (m->graphs) {
+        // the graphs' first sort takes the keys a corrector wrote
+        if (left > 0) m->prepare_keys(c->stream, &c->timer);
         while (left >= m->graph_steps) {
             HIP_OK(hipGraphLaunch(m->mexec[m->cur], c->stream));
             left -= m->graph_steps;
@@ -897,6 +926,7 @@ int restore_impl(sph_ctx* c, const void* blob, size_t bytes) {
     }
     hipStream_t st = c->stream;
     HIP_OK(hipStreamSynchronize(st));
+    m->discard_keys(st);   // the keys of the state being replaced
     // the blob's arrays are in id order: slot a holds particle a until the sort
     StateBuf<T>& X = m->buf[m->cur];
     HIP_OK(hipMemcpyAsync(X.pos, pos, (size_t)n * 16, hipMemcpyHostToDevice, st));
@@ -1277,6 +1307,8 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
     if (c->opt.use_graph) {
         HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         int saved = m->cur;
+        const bool saved_keys = m->keys_fresh;
+        m->keys_fresh = true;   // replays start from keys written by a corrector (step_impl ensures it)
         KernelTimer off;
         for (int k = 0; k < 2; ++k) {
             m->cur = k;
@@ -1291,6 +1323,7 @@ int init_impl(sph_ctx* c, const double* pos, const double* vel, const double* rh
             HIP_OK(hipGraphInstantiate(&m->mexec[k], m->mgraph[k], nullptr, nullptr, 0));
         }
         m->cur = saved;
+        m->keys_fresh = saved_keys;
         m->graph_steps = c->opt.graph_steps;
         m->graphs = true;
     }

@@ -200,6 +200,13 @@ struct IntegView {
     uint32_t* surf_count;  // surface-list counters, cleared for the half-step evaluation
     unsigned long long* skin_max;  // per system, then over all: largest squared half-step displacement
                                    // beyond half the skin (0: none)
+    // corrector only: the next sort's keys, slots, cell counts and workgroup
+    // inactive counts of the new state (key == nullptr: not written)
+    uint32_t* key;
+    uint32_t* kslot;
+    uint32_t* kcount;
+    uint32_t* kblk;
+    uint32_t trash;
 };
 
 struct LaunchCfg {
@@ -241,8 +248,12 @@ void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipS
 void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st);
 
 template <typename T>
+void launch_key(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, hipStream_t st,
+                KernelTimer* kt);
+// keyed: X's keys, slots and cell counts are already written (by the corrector)
+template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
-                 T* vol, hipStream_t st, KernelTimer* kt);
+                 T* vol, bool keyed, hipStream_t st, KernelTimer* kt);
 template <typename T>
 void launch_eval(const LaunchCfg& L, const EvalView<T>& v, const WallView* W, hipStream_t st, KernelTimer* kt);
 template <typename T>

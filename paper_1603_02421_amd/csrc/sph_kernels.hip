@@ -166,20 +166,21 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(uint32_t* in, uint3
 // walls of repulsive-force systems -- whose order comes from a stable
 // compaction.
 
+// Every thread of the workgroup calls it (valid = slot i < n), with the
+// particle's tag and position: the key goes to key[i], the slot within the
+// cell to slot[i], and the workgroup's count of particles outside the cells
+// to blk_inactive[blockIdx.x].
 template <typename T>
-__global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uint32_t* tag,
-                      uint32_t* key, uint32_t* slot, uint32_t* counts, uint32_t trash,
-                      uint32_t* blk_inactive) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void key_and_count(const SysDev<T>* sys, int i, bool valid, uint32_t t, double2 p,
+                                              uint32_t* key, uint32_t* slot, uint32_t* counts, uint32_t trash,
+                                              uint32_t* blk_inactive) {
     bool inactive = false, act = false;
     uint32_t k = trash;
-    if (i < n) {
-        uint32_t t = tag[i];
+    if (valid) {
         // repulsive-force walls stay out of the cells, like inactive particles:
         // they act on the fluid only through the wall force (eq. 29)
         if (tag_type(t) != T_INACTIVE && !(sys[tag_sys(t)].boundary && tag_type(t) != T_FLUID)) {
             const SysDev<T>& S = sys[tag_sys(t)];
-            double2 p = pos[i];
             int cx = cell_coord(p.x, S.x0, S.inv_s, S.nx);
             int cy = cell_coord(p.y, S.y0, S.inv_s, S.ny);
             k = S.cell_base + (uint32_t)cx * (uint32_t)S.ny + (uint32_t)cy;
@@ -206,12 +207,23 @@ __global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uin
         base = atomicAdd(&counts[k], (uint32_t)(next - lane));
     }
     base = __shfl(base, hlane, 64);
-    if (i < n) {
+    if (valid) {
         key[i] = k;
         slot[i] = act ? base + (uint32_t)(lane - hlane) : 0u;
     }
     int c = __syncthreads_count(inactive);
     if (threadIdx.x == 0) blk_inactive[blockIdx.x] = (uint32_t)c;
+}
+
+template <typename T>
+__global__ void k_key(int n, const SysDev<T>* sys, const double2* pos, const uint32_t* tag,
+                      uint32_t* key, uint32_t* slot, uint32_t* counts, uint32_t trash,
+                      uint32_t* blk_inactive) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t t = valid ? tag[i] : 0u;
+    const double2 p = valid ? pos[i] : make_double2(0.0, 0.0);
+    key_and_count<T>(sys, i, valid, t, p, key, slot, counts, trash, blk_inactive);
 }
 
 // The ids of every cell's particles, in the cell's slot range (in the
@@ -1186,54 +1198,60 @@ __global__ void k_predict(IntegView<T> v) {
 }
 
 // Corrector: state n+1 from state n and the half-step derivatives, in place;
-// fluid leaving the box becomes inactive; instability checks.
+// fluid leaving the box becomes inactive; instability checks. With v.key set
+// it also does the next sort's first pass on the new state (cell keys, slots
+// within the cells, counts), in the key kernel's launch shape.
 template <typename T>
 __global__ void k_correct(IntegView<T> v) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= v.n) return;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = a < v.n;
     // the slot's state with its tag: the loads do not wait for the type test
-    const uint32_t t = v.tag[a];
-    double2 p = v.pos[a];
-    V2<T> u = v.vel[a];
-    const V2<T> acc = v.acc[a];
-    const T dens0 = v.dens[a], drho = v.drho[a];
+    uint32_t t = valid ? v.tag[a] : 0u;
+    double2 p = valid ? v.pos[a] : make_double2(0.0, 0.0);
     const uint32_t ty = tag_type(t);
-    if (ty == T_INACTIVE) return;
-    const SysDev<T>& S = v.sys[tag_sys(t)];
-    double dt = v.dt[tag_sys(t)];
-    T tdt = (T)dt;
-    // eq. 6: the density of the half-step evaluation; eq. 7 otherwise
-    const bool summed = ty == T_FLUID && S.density_sum;
-    const bool wall_f = ty != T_FLUID && S.boundary;   // repulsive-force wall: density fixed
-    T dens = summed ? v.dens_h[a] : (wall_f ? dens0 : dens0 + tdt * drho);
-    if (ty != T_FLUID && dens < T(0)) dens = T(0);   // boundaries never below rho0
-    v.dens[a] = dens;
-    uint32_t flags = 0;
-    if (!isfinite(dens)) flags |= FLAG_NONFINITE;
-    else if (!wall_f && ((!summed && dens < T(-0.5) * S.rho0) || dens > S.rho0)) flags |= FLAG_DENSITY;
-    if (ty == T_FLUID) {
-        p.x = p.x + dt * ((double)u.x + 0.5 * dt * (double)acc.x);
-        p.y = p.y + dt * ((double)u.y + 0.5 * dt * (double)acc.y);
-        u.x += tdt * acc.x;
-        u.y += tdt * acc.y;
-        v.pos[a] = p;
-        v.vel[a] = u;
-        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(u.x) || !isfinite(u.y)) flags |= FLAG_NONFINITE;
-        if (p.x < S.box_lo_x || p.x > S.box_hi_x || p.y < S.box_lo_y || p.y > S.box_hi_y)
-            v.tag[a] = (t & ~15u) | T_INACTIVE;
-    } else if (ty == T_PISTON) {
-        double tn = v.time[tag_sys(t)];
-        double dX = piston_travel(S.pu, S.pamp, S.pomega, tn + dt) - piston_travel(S.pu, S.pamp, S.pomega, tn);
-        double U = piston_speed(S.pu, S.pamp, S.pomega, tn + dt);
-        p.x += S.pdx * dX;
-        p.y += S.pdy * dX;
-        v.pos[a] = p;
-        V2<T> w;
-        w.x = (T)(S.pdx * U);
-        w.y = (T)(S.pdy * U);
-        v.vel[a] = w;
+    if (valid && ty != T_INACTIVE) {
+        V2<T> u = v.vel[a];
+        const V2<T> acc = v.acc[a];
+        const T dens0 = v.dens[a], drho = v.drho[a];
+        const SysDev<T>& S = v.sys[tag_sys(t)];
+        double dt = v.dt[tag_sys(t)];
+        T tdt = (T)dt;
+        // eq. 6: the density of the half-step evaluation; eq. 7 otherwise
+        const bool summed = ty == T_FLUID && S.density_sum;
+        const bool wall_f = ty != T_FLUID && S.boundary;   // repulsive-force wall: density fixed
+        T dens = summed ? v.dens_h[a] : (wall_f ? dens0 : dens0 + tdt * drho);
+        if (ty != T_FLUID && dens < T(0)) dens = T(0);   // boundaries never below rho0
+        v.dens[a] = dens;
+        uint32_t flags = 0;
+        if (!isfinite(dens)) flags |= FLAG_NONFINITE;
+        else if (!wall_f && ((!summed && dens < T(-0.5) * S.rho0) || dens > S.rho0)) flags |= FLAG_DENSITY;
+        if (ty == T_FLUID) {
+            p.x = p.x + dt * ((double)u.x + 0.5 * dt * (double)acc.x);
+            p.y = p.y + dt * ((double)u.y + 0.5 * dt * (double)acc.y);
+            u.x += tdt * acc.x;
+            u.y += tdt * acc.y;
+            v.pos[a] = p;
+            v.vel[a] = u;
+            if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(u.x) || !isfinite(u.y)) flags |= FLAG_NONFINITE;
+            if (p.x < S.box_lo_x || p.x > S.box_hi_x || p.y < S.box_lo_y || p.y > S.box_hi_y) {
+                t = (t & ~15u) | T_INACTIVE;
+                v.tag[a] = t;
+            }
+        } else if (ty == T_PISTON) {
+            double tn = v.time[tag_sys(t)];
+            double dX = piston_travel(S.pu, S.pamp, S.pomega, tn + dt) - piston_travel(S.pu, S.pamp, S.pomega, tn);
+            double U = piston_speed(S.pu, S.pamp, S.pomega, tn + dt);
+            p.x += S.pdx * dX;
+            p.y += S.pdy * dX;
+            v.pos[a] = p;
+            V2<T> w;
+            w.x = (T)(S.pdx * U);
+            w.y = (T)(S.pdy * U);
+            v.vel[a] = w;
+        }
+        if (flags) atomicOr(v.flags, flags);
     }
-    if (flags) atomicOr(v.flags, flags);
+    if (v.key) key_and_count<T>(v.sys, a, valid, t, p, v.key, v.kslot, v.kcount, v.trash, v.kblk);
 }
 
 __global__ void k_advance_time(int n_sys, const double* dt, double* time) {
@@ -1451,17 +1469,25 @@ void copy_kernel(const void* src, void* dst, size_t bytes, hipStream_t st) {
 }
 
 template <typename T>
+void launch_key(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, hipStream_t st,
+                KernelTimer* kt) {
+    kt->begin("sort_key", st);
+    k_key<T><<<nblk(L.n, L.block_stream), L.block_stream, 0, st>>>(L.n, sys, X.pos, X.tag, B.key, B.slot, B.count,
+                                                                    B.trash, B.blk);
+    kt->end(st);
+}
+
+template <typename T>
 void launch_sort(const LaunchCfg& L, const SortBufs& B, const SysDev<T>* sys, StateBuf<T> X, StateBuf<T> Y,
-                 T* vol, hipStream_t st, KernelTimer* kt) {
+                 T* vol, bool keyed, hipStream_t st, KernelTimer* kt) {
     const int n = L.n;
     const int bs = L.block_stream;
     const uint32_t trash = B.trash;
     const unsigned nb = nblk(n, bs);
-    // the per-cell counts are zero here: the cell scan of the previous sort
-    // cleared them (and the first sort finds them cleared at set-up)
-    kt->begin("sort_key", st);
-    k_key<T><<<nb, bs, 0, st>>>(n, sys, X.pos, X.tag, B.key, B.slot, B.count, trash, B.blk);
-    kt->end(st);
+    // keyed: the corrector that produced X already wrote its keys, slots and
+    // counts. Otherwise the per-cell counts are zero here: the cell scan of
+    // the previous sort cleared them (and the first sort finds them cleared)
+    if (!keyed) launch_key<T>(L, B, sys, X, st, kt);
     launch_scan(B.count, B.cstart, (int64_t)trash + 1, true, B.part, st, kt);
     launch_scan(B.blk, B.blk, (int64_t)nb, false, B.part2, st, kt);
     kt->begin("sort_scatter", st);
@@ -1591,8 +1617,10 @@ void launch_pressure(int n, const SysDev<T>* sys, const uint32_t* tag, const T* 
 }
 
 #define SPHJET_INSTANTIATE(T)                                                                               \
+    template void launch_key<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,         \
+                                hipStream_t, KernelTimer*);                                                \
     template void launch_sort<T>(const LaunchCfg&, const SortBufs&, const SysDev<T>*, StateBuf<T>,        \
-                                 StateBuf<T>, T*, hipStream_t, KernelTimer*);                              \
+                                 StateBuf<T>, T*, bool, hipStream_t, KernelTimer*);                        \
     template void launch_eval<T>(const LaunchCfg&, const EvalView<T>&, const WallView*, hipStream_t,      \
                                  KernelTimer*);                                                            \
     template void launch_dt<T>(int, const SysDev<T>*, const uint32_t*, const double*, unsigned long long*, \

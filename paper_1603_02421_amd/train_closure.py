@@ -140,8 +140,9 @@ def main(argv=None):
     ap.add_argument("--no-mirror", action="store_true", help="no mirror images of the training stencils")
     ap.add_argument("--skip-eval", action="store_true", help="stop after training")
     ap.add_argument("--eval-only", action="store_true", help="skip data and training; evaluate the weights")
-    ap.add_argument("--label-steps", type=int, default=4,
-                    help="fine steps each jet label's curvature is averaged over (4: one coarse step)")
+    ap.add_argument("--label-steps", type=int, default=1,
+                    help="fine steps each jet label's curvature is averaged over (4: one coarse step; "
+                         "measured to leave the labels' noise unchanged)")
     ap.add_argument("--label-window", type=float, default=2.0,
                     help="radius of a jet label's average, in coarse smoothing lengths (2: the kernel's support)")
     ap.add_argument("--label-study", action="store_true",
@@ -203,7 +204,7 @@ def label_study(cl, a, rep):
     for name, spec, snaps, n, fl in (("jets_D20", HELD_OUT_JETS, a.jet_snap_steps, a.jet_n, a.jet_free_length),
                                      ("sweep_jets", SWEEP_HELD_OUT, a.sweep_snap_steps, a.sweep_n,
                                       a.sweep_free_length)):
-        runs = fine_runs(spec, _snaps(snaps), n, fl, a.label_steps)
+        runs = fine_runs(spec, _snaps(snaps), n, fl, max(a.label_steps, 4))
         # the Poisson radius that keeps one point per dx^2 at twice the coarse
         # resolution (four fine points per cell), from the first snapshot
         (nD0, *_), sn0 = runs[0][0], runs[0][1][-1]
@@ -211,16 +212,20 @@ def label_study(cl, a, rep):
         rmin2 = min((0.60, 0.64, 0.68, 0.72, 0.76),
                     key=lambda f: abs(len(cl.poisson_subsample(sn0["pos"], f / (2 * nD0), 1)) - target))
         log(f"[labels] {name}: Poisson radius {rmin2} dx at twice the coarse resolution")
-        for steps in (1, a.label_steps):
+        keeps = {(i, k, fine): cl.poisson_subsample(sn["pos"], (0.78 if fine == 1 else rmin2) / (fine * nD),
+                                                    seed * 100 + k)
+                 for i, ((nD, Re, We, seed, amp), sn_list) in enumerate(runs)
+                 for k, sn in enumerate(sn_list) for fine in (1, 2)}
+        for steps in (1, max(a.label_steps, 4)):
             for window in (1.0, 2.0):
                 for fine in (1, 2):
                     systems, kept, expect = [], 0, 0.0
-                    for (nD, Re, We, seed, amp), sn_list in runs:
+                    for i, ((nD, Re, We, seed, amp), sn_list) in enumerate(runs):
                         for k, sn in enumerate(sn_list):
                             snap = sn if steps > 1 else dict(sn, kappa=sn["kappa_first"])
                             systems.append(cl.coarse_from_snapshot(snap, fine * nD, Re, We, seed * 100 + k,
                                                                    window=window, label_h=1.3 / nD,
-                                                                   rmin=0.78 if fine == 1 else rmin2))
+                                                                   keep=keeps[(i, k, fine)]))
                             kept += systems[-1].n
                             expect += len(sn["pos"]) * (fine / 4.0) ** 2
                     X, T, P, K, F, H, HM = cl.harvest_coarse(systems, halves=True)

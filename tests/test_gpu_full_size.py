@@ -74,6 +74,39 @@ def test_full_batch_trajectory(gpu, orc, c3):
     assert ep <= 1e-4 and er <= 1e-4 and ev <= 1e-4
 
 
+def test_large_single_jet_evaluation_and_steps(gpu, orc):
+    """The largest single-jet workload (D = 80 dx, 100 D domain, 4.0M particles,
+    FP32, cell size 1.05 h): one evaluation to 1e-5 of scale and two
+    graph-replayed steps to 1e-4, every particle compared."""
+    import bench
+    batch, _, bits = bench.make_workload("c5")
+    s = batch.systems[0]
+    s.params["cell_size"] = CELL_FACTOR * s.params["h"]
+    say(f"[full size] one jet D = 80 dx: n={s.n}, cell {CELL_FACTOR} h")
+    with gpu.Simulation(s, dtype_bits=bits, block_sweep=BLOCK_SWEEP) as sim:
+        g = gpu_eval(sim)
+    o = orc.evaluate(s)
+    start, nbr = orc.neighbors(s)
+    rep = compare_eval(g, o, np.full(s.n, s.params["eps_h"] / s.params["h"]), start, nbr, 1e-5,
+                       s.type == wl.FLUID)
+    say("  ", rep)
+    assert np.allclose(g["dt"], o["dt"], rtol=1e-5, atol=0)
+    del g, o, start, nbr
+    st = orc.State(s)
+    with gpu.Simulation(s, dtype_bits=bits, block_sweep=BLOCK_SWEEP, use_graph=1, graph_steps=2) as sim:
+        sim.step(2)
+        pos, vel, rho = sim.read("pos"), sim.read("vel"), sim.read("rho")
+        flags = sim.read("flags")[0]
+    st.step(2)
+    assert flags == 0
+    act = st.type != wl.INACTIVE
+    ep = np.abs(pos - st.pos)[act].max() / s.meta["dx"]
+    er = np.abs(rho - st.rho)[act].max() / s.params["rho0"]
+    ev = np.abs(vel - st.vel)[act].max() / np.abs(st.vel)[act].max()
+    say(f"   after 2 steps: pos {ep:.2e} dx, rho {er:.2e}, vel {ev:.2e}")
+    assert ep <= 1e-4 and er <= 1e-4 and ev <= 1e-4
+
+
 def test_full_batch_closure_evaluation(gpu, orc, c3):
     """The closure leg of the benchmark: the same batch with the learned closure
     in every jet (random network weights). The listed particles, network
