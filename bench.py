@@ -58,7 +58,7 @@ IMPL_BYTES = {
     # (88 B), over active particles at the 2.9% filtered on the 64-jet batch
     "surface": 0.029 * (4 + 4 + 8 + 8 + 4 + 4 + 16 + 20 + 4 + 8 + 4 + 4),
     "predict": 4 + 16 + 8 + 4 + 4 + 8 + 4 + 16 + 8 + 4 + 4,  # tag pos vel dens drho acc mass -> half state, vol
-    "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4,       # tag pos vel dens drho acc -> pos vel dens
+    "correct": 4 + 16 + 8 + 4 + 4 + 8 + 16 + 8 + 4 + 8,   # tag pos vel dens drho acc -> pos vel dens, key slot
     "sort_key": 16 + 4 + 4 + 4,                           # pos tag -> key slot
     "sort_scatter": 4 + 4 + 4 + 4 + 4,                    # key slot id cstart -> cell_ids
     "sort_permute": 4 + 4 + 4 + 40 + 40 + 4 + 4,          # key cstart cell_ids X -> Y cell vol
