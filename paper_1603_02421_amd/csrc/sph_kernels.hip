@@ -355,10 +355,28 @@ __device__ __forceinline__ void scan_cells_rows(const SysDev<T>& S, const uint32
     const int xlo = cx - R < 0 ? 0 : cx - R;
     const int xhi = cx + R > S.nx - 1 ? S.nx - 1 : cx + R;
     const double R2 = rp2;
+    // the rows' slot ranges, loaded together before the scan (reach <= 2
+    // here, so at most five rows; wider rescans load each row's in turn)
+    uint32_t rb0[5], rb1[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int X = xlo + i;
+        const bool in = X <= xhi && R <= 2;
+        const uint32_t row = S.cell_base + (uint32_t)(in ? X : xlo) * ny;
+        rb0[i] = in ? cstart[row + ylo] : 0u;
+        rb1[i] = in ? cstart[row + yhi + 1] : 0u;
+    }
     int r = 0;   // row of the block, 0 at x = xlo
     for (int X = xlo; X <= xhi; ++X, ++r) {
         const uint32_t row = S.cell_base + (uint32_t)X * ny;
-        const uint32_t b0 = cstart[row + ylo], b1 = cstart[row + yhi + 1];
+        uint32_t b0, b1;
+        if (R <= 2) {
+            b0 = r == 0 ? rb0[0] : r == 1 ? rb0[1] : r == 2 ? rb0[2] : r == 3 ? rb0[3] : rb0[4];
+            b1 = r == 0 ? rb1[0] : r == 1 ? rb1[1] : r == 2 ? rb1[2] : r == 3 ? rb1[3] : rb1[4];
+        } else {
+            b0 = cstart[row + ylo];
+            b1 = cstart[row + yhi + 1];
+        }
         for (uint32_t b = b0; b < b1; b += NB) {
             // NB positions from one address: the position arrays hold
             // POS_PAD slots past the last particle, so a batch may run over
