@@ -19,6 +19,10 @@ constexpr int POS_PAD = 4;
 // with its own counter, so its appends do not all contend for one address.
 constexpr int SURF_REGIONS = 64;
 constexpr int SURF_BLOCK = 32;   // consecutive sweep chunks that share a region
+// Surface lists of at most this many entries (fewer than one 64-lane wave per
+// SIMD of the chip at one lane per entry) give each entry four lanes in the
+// surface sweep.
+constexpr uint32_t SURF_SPLIT_MAX = 65536;
 
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;

@@ -548,15 +548,24 @@ __device__ __forceinline__ RowMask load_mask(const uint4* nmask, const uint32_t*
 // RESCAN: the half step of slot a's system outran the skin mask; the
 // step-start cells are scanned with reach `rescan` instead (the kernels built
 // with RESCAN run only for such systems, so the others keep their registers).
+// keep: the mask bits this lane visits (several lanes can share slot a, each
+// visiting its own bits of every cell row); scans: whether this lane scans the
+// cells when there is no mask to split (an overflowed mask, a rescan).
 template <typename T, int NB = 4, bool RESCAN = false, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void neighbours(const EvalView<T>& v, const SysDev<T>& S, uint32_t a, double2 pa,
-                                           LoadFn&& load, ComputeFn&& compute, int rescan = 0) {
+                                           LoadFn&& load, ComputeFn&& compute, int rescan = 0, uint32_t keep = ~0u,
+                                           bool scans = true) {
     if constexpr (RESCAN) {
-        scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute, rescan);
+        if (scans) scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute, rescan);
     } else {
-        const RowMask M = load_mask(v.nmask, v.nmask4, a);
-        if (!(M.w[4] & MASK_OVERFLOW)) mask_neighbours<T, NB>(v, S, a, pa, M, load, compute);
-        else scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute, S.reach);  // rare: keep it lean
+        RowMask M = load_mask(v.nmask, v.nmask4, a);
+        if (!(M.w[4] & MASK_OVERFLOW)) {
+#pragma unroll
+            for (int r = 0; r < 5; ++r) M.w[r] &= keep;
+            mask_neighbours<T, NB>(v, S, a, pa, M, load, compute);
+        } else if (scans) {
+            scan_cells<T, 1>(S, v.cstart, v.cell[a], a, pa, v.pos, load, compute, S.reach);  // rare: keep it lean
+        }
     }
 }
 
@@ -1012,40 +1021,39 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
     const uint32_t total = __shfl(incl, 63, 64);
     __shared__ uint32_t cl_n[4], cl_base;
     __syncthreads();
-    // the workgroup takes 256 consecutive entries per pass (64 per wave), so
-    // all its waves run the same passes and can share the closure-list atomic
-    for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < total; e0 += gridDim.x * blockDim.x) {
-        const uint32_t e = e0 + (uint32_t)w * 64u;
-        const uint32_t idx = e + (uint32_t)lane;
+    // A short list (at most SURF_SPLIT_MAX entries) gives each entry four
+    // adjacent lanes, which split its neighbours by mask bit (sub = the lane's
+    // place among them): its chain of dependent loads is shorter and the chip
+    // gets more waves. A long list already fills the chip: one lane per entry.
+    // The workgroup takes 256 / G consecutive entries per pass, so all its
+    // waves run the same passes and can share the closure-list atomic.
+    const int G = total <= SURF_SPLIT_MAX ? 4 : 1;   // the same in every wave
+    const int sub = lane & (G - 1);
+    const uint32_t keep = G == 4 ? 0x11111111u << sub : ~0u;
+    const uint32_t per_block = blockDim.x / (uint32_t)G, per_wave = 64u / (uint32_t)G;
+    for (uint32_t e0 = blockIdx.x * per_block; e0 < total; e0 += gridDim.x * per_block) {
+        const uint32_t e = e0 + (uint32_t)w * per_wave;
+        const uint32_t idx = e + (uint32_t)(lane >> (G == 4 ? 2 : 0));
         // region holding entry idx: the last r with pre[r] <= idx
         int r = 0;
 #pragma unroll
         for (int step = 32; step > 0; step >>= 1)
             if (pre[w][r + step] <= idx) r += step;
         const uint32_t off = idx - pre[w][r];
+        // the same for the G lanes of an entry
         bool in = idx < total && off < v.surf_region;
         const uint32_t a = in ? v.surf_list[(size_t)r * v.surf_region + off] : 0u;
         const uint32_t sys = in ? tag_sys(v.tag[a]) : 0u;
         in = in && (RESCAN ? outran(v, (int)sys) : !outran(v, (int)sys));
         const SysDev<T>& S = v.sys[sys];
-        double dtf = __builtin_inf();
-        bool listed = false;
+        T num = 0, den = 0;   // this lane's share of the two sums
         if (in) {
             const T eps = S.eps;
             const KernelConsts<T> K = kconsts(S);
             const V2<T> n_a = v.nrm[a];
-            const T mag = sqrt_(n_a.x * n_a.x + n_a.y * n_a.y);
-            V2<T> acc = v.acc[a];
-            const T rho_a = v.eos[a].z;
-            // with the learned closure the surface force of a filtered particle is
-            // added later, from the network's curvature or the plain fallback
-            listed = v.cl_count != nullptr && S.closure != 0;
-            const T im = rcp(mag);
+            const T im = rcp(sqrt_(n_a.x * n_a.x + n_a.y * n_a.y));
             const T hx = n_a.x * im, hy = n_a.y * im;
-            T num = 0;
-            T den = v.vol[a] * S.W0;
-            const double2 pa = v.pos[a];
-            neighbours<T, 4, RESCAN>(v, S, a, pa,
+            neighbours<T, 4, RESCAN>(v, S, a, v.pos[a],
                 [&](uint32_t b) { return Pay3<T>{at(v.nrm, b), at(v.vol, b)}; },
                 [&](uint32_t, T dx, T dy, const Pay3<T>& p) {
                     T mb = sqrt_(p.nrm.x * p.nrm.x + p.nrm.y * p.nrm.y);
@@ -1058,7 +1066,29 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
                         den += p.vol * W;
                     }
                 },
-                RESCAN ? rescan_reach(v, S, (int)sys) : 0);
+                RESCAN ? rescan_reach(v, S, (int)sys) : 0, keep, sub == 0);
+        }
+        if (G == 4) {
+            // the entry's sums over its four lanes (every lane of the wave is
+            // active here, and an entry's lanes are adjacent)
+#pragma unroll
+            for (int o = 1; o < 4; o <<= 1) {
+                num += __shfl_xor(num, o, 64);
+                den += __shfl_xor(den, o, 64);
+            }
+        }
+        const bool lead = in && sub == 0;
+        double dtf = __builtin_inf();
+        bool listed = false;
+        if (lead) {
+            const V2<T> n_a = v.nrm[a];
+            V2<T> acc = v.acc[a];
+            const T rho_a = v.eos[a].z;
+            const double2 pa = v.pos[a];
+            // with the learned closure the surface force of a filtered particle is
+            // added later, from the network's curvature or the plain fallback
+            listed = v.cl_count != nullptr && S.closure != 0;
+            den += v.vol[a] * S.W0;   // self term of the denominator
             const T kappa = num / den;
             v.kappa_plain[a] = kappa;
             T f = listed ? T(0) : -S.sigma * rcp(rho_a) * kappa;
@@ -1070,7 +1100,7 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
             T am = sqrt_(acc.x * acc.x + acc.y * acc.y);
             if (am > T(0) && !listed) dtf = sqrt((double)S.h / (double)am);
         }
-        if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, (int)sys, dtf, in);
+        if (v.do_dt) atomic_min_per_system(v.dtmin + 1, 2, (int)sys, dtf, lead);
         if (v.cl_count) {
             // append the listed slots, one atomic per workgroup and pass
             const unsigned long long bal = __ballot(listed);
