@@ -590,7 +590,8 @@ __device__ __forceinline__ int chunk_system(const EvalView<T>& v, uint32_t c) {
 
 // Grid of the RESCAN kernels: its waves stride over the chunks of the systems
 // that outran the skin mask; with none (skin_max[n_sys], the largest over all
-// systems, is 0) every wave returns at once.
+// systems, is 0) every wave returns at once. The half step's surface sweep
+// carries as many workgroups past its own grid for the same systems' entries.
 constexpr int RESCAN_BLOCKS = 256;
 
 template <typename T, typename Fn>
@@ -839,6 +840,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     colour_skin_slot<T, false>(v, sys, a, 0);
 }
 
+// Its own kernel (not workgroups past the colour sweep's grid, as in the
+// surface sweep): the colour sweep's code comes out slower with it.
 template <typename T>
 __global__ void __launch_bounds__(256) k_colour_rescan(EvalView<T> v) {
     for_outran_chunks(v, [&](int sys, uint32_t a, uint32_t, int rescan) {
@@ -984,6 +987,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     main_chunk<T, false>(v, sys, a, chunk, 0);
 }
 
+// Its own kernel (not workgroups past the main sweep's grid, as in the surface
+// sweep): inside the main sweep the rescan's registers would spill.
 template <typename T>
 __global__ void __launch_bounds__(256) k_main_rescan(EvalView<T> v) {
     for_outran_chunks(v, [&](int sys, uint32_t a, uint32_t chunk, int rescan) {
@@ -1003,8 +1008,8 @@ __global__ void __launch_bounds__(256) k_main_rescan(EvalView<T> v) {
 // RESCAN: the entries of systems whose half step outran the skin mask (and
 // only those; the plain kernel skips them).
 template <typename T, bool RESCAN>
-__global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
-    if (RESCAN && v.skin_max[v.n_sys] == 0ull) return;
+__device__ __forceinline__ void surface_pass(const EvalView<T>& v, uint32_t blk, uint32_t nblk) {
+    if (RESCAN && (v.skin_max == nullptr || v.skin_max[v.n_sys] == 0ull)) return;
     __shared__ uint32_t pre[4][SURF_REGIONS];
     static_assert(SURF_REGIONS == 64, "one region per lane");
     const int lane = __lane_id(), w = (int)(threadIdx.x >> 6);
@@ -1031,7 +1036,7 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
     const int sub = lane & (G - 1);
     const uint32_t keep = G == 4 ? 0x11111111u << sub : ~0u;
     const uint32_t per_block = blockDim.x / (uint32_t)G, per_wave = 64u / (uint32_t)G;
-    for (uint32_t e0 = blockIdx.x * per_block; e0 < total; e0 += gridDim.x * per_block) {
+    for (uint32_t e0 = blk * per_block; e0 < total; e0 += nblk * per_block) {
         const uint32_t e = e0 + (uint32_t)w * per_wave;
         const uint32_t idx = e + (uint32_t)(lane >> (G == 4 ? 2 : 0));
         // region holding entry idx: the last r with pre[r] <= idx
@@ -1119,6 +1124,14 @@ __global__ void __launch_bounds__(256) k_surface(EvalView<T> v) {
             __syncthreads();
         }
     }
+}
+
+// The first sweep_blocks workgroups take the entries of the systems that kept
+// to their skin masks; any past them, those of the systems that outran theirs.
+template <typename T>
+__global__ void __launch_bounds__(256) k_surface(EvalView<T> v, unsigned sweep_blocks) {
+    if (blockIdx.x < sweep_blocks) surface_pass<T, false>(v, blockIdx.x, sweep_blocks);
+    else surface_pass<T, true>(v, blockIdx.x - sweep_blocks, gridDim.x - sweep_blocks);
 }
 
 // ------------------------------------------------------------------ time step
@@ -1605,13 +1618,9 @@ void launch_eval(const LaunchCfg& L, const EvalView<T>& v, const WallView* W, hi
         kt->end(st);
     }
     kt->begin("surface", st);
-    k_surface<T, false><<<surface_blocks(L.n), 256, 0, st>>>(v);
+    const unsigned sb = surface_blocks(L.n);
+    k_surface<T><<<sb + (half ? (unsigned)RESCAN_BLOCKS : 0u), 256, 0, st>>>(v, sb);
     kt->end(st);
-    if (half) {
-        kt->begin("rescan", st);
-        k_surface<T, true><<<RESCAN_BLOCKS, 256, 0, st>>>(v);
-        kt->end(st);
-    }
 }
 
 template <typename T>
