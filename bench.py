@@ -113,8 +113,8 @@ def _pmc(path: str, counter: str):
     out = collections.defaultdict(list)
     with open(path) as f:
         for r in csv.DictReader(f):
-            if r["Counter_Name"] != counter or ", true>" in r["Kernel_Name"]:
-                continue   # (the RESCAN instantiations run only when a system outran its skin)
+            if r["Counter_Name"] != counter:
+                continue
             name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").split("::")[-1]
             out[name].append(float(r["Counter_Value"]))
     return out
