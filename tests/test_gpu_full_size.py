@@ -119,3 +119,33 @@ def test_full_batch_closure_evaluation(gpu, orc, c3):
         s.params["closure"] = 1
     say(f"[full size] closure evaluation: 64 jets, n={batch.n}")
     check_closure_evaluation(gpu, orc, batch, 32, 0.2, sim_kw=dict(block_sweep=BLOCK_SWEEP), sample=4000)
+
+
+def test_surface_lane_split_matches_one_lane(gpu, c3):
+    """The surface sweep gives each entry of a short list (at most 65,536
+    entries) four lanes that split its neighbours by mask bit, and each entry of
+    a long list one lane. One jet evaluated alone (a list of a few thousand
+    entries: four lanes) and inside the 64-jet batch (about 230k entries: one
+    lane) has the same cells, order and masks, so the colour, continuity and
+    normal sweeps agree bit for bit, and the curvature and the accelerations
+    it sets agree to the rounding of the sum's order."""
+    j = 0
+    one = c3.systems[j]
+    say(f"[surface lanes] jet {j} alone (n={one.n}) and in the batch (n={c3.n})")
+    with gpu.Simulation(one, dtype_bits=32, block_sweep=BLOCK_SWEEP) as sim:
+        a = gpu_eval(sim)
+    with gpu.Simulation(c3, dtype_bits=32, block_sweep=BLOCK_SWEEP) as sim:
+        b = gpu_eval(sim)
+    n = one.n
+    b = {k: (v[:n] if k != "dt" else v[j:j + 1]) for k, v in b.items()}
+    for k in ("colour", "drho", "nrm", "nflag", "type"):
+        assert np.array_equal(a[k], b[k]), k
+    listed = a["nflag"] == 1
+    say(f"   {int(listed.sum())} filtered particles")
+    assert listed.sum() > 100
+    ek = np.abs(a["kappa"] - b["kappa"])[listed].max() / np.abs(b["kappa"][listed]).max()
+    ea = np.linalg.norm(a["acc"] - b["acc"], axis=1).max() / np.linalg.norm(b["acc"], axis=1).max()
+    say(f"   curvature {ek:.2e}, acceleration {ea:.2e} of their largest magnitudes")
+    assert ek < 1e-5 and ea < 1e-5
+    assert np.array_equal(a["acc"][~listed], b["acc"][~listed])
+    assert np.allclose(a["dt"], b["dt"], rtol=1e-6, atol=0)
